@@ -1,0 +1,186 @@
+"""Benchmark: ML-CG ptychography on one MI355X.
+
+Workload: the single large projection -- 2048^2 complex64 object, 128^2
+apodised-disk probe, 64x64 = 4096 positions on a 24 px raster with +-2 px
+jitter, 128^2 float32 Poisson intensities at 1e5 photons per pattern,
+object-only CG with FP64 reductions.  A step is one CG iteration (GRAD ->
+DIR -> LS -> Update over all 4096 patterns).  W warm-up iterations run in a
+separate solve; the timed region is one ptyg_cg_solve of K iterations from
+the usual start (psi_0 = 1), inputs resident in HBM.
+
+value = diffraction patterns per second through grad + line search
+(4096 * K / t).  The roofline object is for the line-search kernel or the
+fused GRAD kernel, whichever takes more time, with its duration measured by
+HIP events on the launch stream inside the timed region.  The CPU baseline
+is the FP64 oracle on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# per-pattern-pixel algorithmic bytes: patch read 8 B (+ direction patch 8 B
+# for a line-search trial), intensity read 4 B, gradient accumulate 8 B
+BYTES_PER_PX = {"grad": 20, "minfunc": 20}
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3
+
+
+def fft_flops(n: int) -> float:
+    m = n * n
+    return 5.0 * m * math.log2(m)
+
+
+def make_inputs(cfg_name: str, device):
+    import numpy as np
+    import torch
+
+    from paper_2106_07575_amd import ptyg, synth
+
+    cfg = synth.CONFIGS[cfg_name]
+    inp = synth.make_inputs(cfg)
+    obj_true = torch.from_numpy(inp.obj_true.astype(np.complex64)).to(device)
+    probe = torch.from_numpy(inp.probe.astype(np.complex64)).to(device)
+    pos = torch.from_numpy(inp.pos).to(device)
+    # synthetic measurements: expected intensities from the forward model on
+    # the ground truth, then seeded Poisson counts
+    far = ptyg.forward(obj_true, probe, pos)
+    gen = torch.Generator(device=device)
+    gen.manual_seed(cfg.seed("poisson"))
+    data = torch.poisson((far.real ** 2 + far.imag ** 2).float(), generator=gen).contiguous()
+    del far
+    return cfg, inp, probe, pos, data
+
+
+def cpu_baseline(cfg_name: str, halvings_per_iter: float, budget_s: float = 12.0):
+    """FP64 oracle on a bounded sample: one GRAD pass plus the mean number of
+    line-search passes over the first 512 patterns of the workload (full
+    object), repeated until ~budget_s; reported in patterns/s of CG."""
+    import numpy as np
+
+    from oracle import ptycho as O
+    from paper_2106_07575_amd import synth
+
+    cfg = synth.CONFIGS[cfg_name]
+    inp = synth.make_inputs(cfg)
+    ks = 512
+    pos = inp.pos[:ks]
+    probe = inp.probe.astype(np.complex64).astype(np.complex128)
+    truth = inp.obj_true.astype(np.complex64).astype(np.complex128)
+    data = synth.poisson_counts(np.abs(O.forward(truth, probe, pos)) ** 2, cfg.seed("poisson")).astype(np.float64)
+    psi = np.ones(truth.shape, np.complex128)
+    eta = np.full(truth.shape, 1e-3 + 0j)
+    ntrials = max(1, int(round(halvings_per_iter)))
+    t0 = time.perf_counter()
+    reps = 0
+    while True:
+        O.grad(psi, probe, pos, data)
+        for j in range(ntrials):
+            O.minfunc(psi + 0.5 ** (j + 1) * eta, probe, pos, data)
+        reps += 1
+        if time.perf_counter() - t0 >= budget_s:
+            break
+    dt = time.perf_counter() - t0
+    per_iter = dt / reps
+    return {"value": ks / per_iter, "unit": "patterns/s", "cores": os.cpu_count(), "kind": "oracle",
+            "sample": f"{ks} of {cfg.k} patterns of the same workload (full 2048^2 object), 1 GRAD + "
+                      f"{ntrials} line-search passes per iteration, {reps} repetitions in {dt:.1f} s, "
+                      f"float64, scipy.fft with {os.cpu_count()} workers"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100, help="timed CG iterations")
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--config", default="c2")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU: the ML-CG hot path here is single-GPU "
+              "(multi-GPU sharding is design-only); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2106_07575_amd import ptyg
+
+    device = torch.device("cuda:0")
+    torch.cuda.set_device(device)
+    cfg, inp, probe, pos, data = make_inputs(args.config, device)
+    K = cfg.k
+    obj0 = torch.ones((cfg.obj_h, cfg.obj_w), dtype=torch.complex64, device=device)
+    ws = ptyg.workspace(ptyg.dims_of(obj0.shape, cfg.n, K), device)
+
+    if args.warmup > 0:
+        ptyg.cg_solve(obj0, probe, pos, data, args.warmup, ws=ws)
+    torch.cuda.synchronize()
+    ptyg.timing_reset()
+    ptyg.timing_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    res = ptyg.cg_solve(obj0, probe, pos, data, args.steps, ws=ws)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ptyg.timing_enable(False)
+    kt = ptyg.timing_read()
+
+    iters = res.iters_done
+    halvings = sum(r["halvings"] for r in res.trace)
+    value = K * iters / dt
+    px = K * cfg.n * cfg.n
+    kinds = {}
+    for kind, (ms, cnt) in kt.items():
+        if cnt:
+            avg_s = ms / cnt / 1e3
+            kinds[kind] = {"launches": cnt, "avg_us": avg_s * 1e6, "total_ms": ms,
+                           "alg_GBs": BYTES_PER_PX[kind] * px / avg_s / 1e9,
+                           "fft_TFLOPs": (1 if kind == "minfunc" else 2) * K * fft_flops(cfg.n) / avg_s / 1e12}
+    dom = max(kinds, key=lambda k: kinds[k]["total_ms"])
+    d = kinds[dom]
+    roofline = {"bound": "hbm", "achieved": round(d["alg_GBs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(d["alg_GBs"] / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": "k_minfunc (line-search trial)" if dom == "minfunc" else "k_grad (fused GRAD)",
+                "bytes_per_launch": BYTES_PER_PX[dom] * px, "avg_launch_us": round(d["avg_us"], 2),
+                "fft_tflops": round(d["fft_TFLOPs"], 2), "fft_frac_of_fp32_peak":
+                    round(d["fft_TFLOPs"] / FP32_PEAK_TFLOPS, 4)}
+    out = {
+        "metric": "diffraction patterns/s through grad+line search",
+        "value": round(value, 1),
+        "unit": "patterns/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(dt / max(iters, 1) * 1e3, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "fp32 transforms, fp64 reductions",
+        "data": "synthetic",
+        "config": {"workload": f"{args.config}: {cfg.obj_h}x{cfg.obj_w} complex64 object, {cfg.n}x{cfg.n} probe, "
+                               f"{K} positions ({cfg.grid[0]}x{cfg.grid[1]} raster, step {cfg.step}, "
+                               f"+-{cfg.jitter} px), Poisson at {cfg.photons:g} photons, object-only ML-CG",
+                   "iterations": iters, "patterns": K},
+        "cg_iters_per_s": round(iters / dt, 3),
+        "pattern_passes_per_s": round(K * (iters + halvings) / dt, 1),
+        "mean_halvings": round(halvings / max(iters, 1), 3),
+        "final_phi": res.trace[-1]["phi"] if res.trace else None,
+        "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
+                    for k, v in kinds.items()},
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(args.config, halvings / max(iters, 1))
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

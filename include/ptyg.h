@@ -1,0 +1,178 @@
+/* ptyg: maximum-likelihood conjugate-gradient ptychography on one MI355X.
+ *
+ * C ABI of libptyg.so.  The operations follow arXiv 2106.07575 ("Scalable and
+ * accurate multi-GPU based image reconstruction of large-scale ptychography
+ * data"), section "Background":
+ *   forward model   Eq. fwd_model   |G psi|^2 = |F Q psi|^2 = d
+ *   objective       Eq. ML          F(psi) = sum_j |G psi|_j^2 - 2 d_j log |G psi|_j
+ *   gradient        Eq. gradient    grad F = G^H (G psi - d / conj(G psi)),
+ *                                   G^H = Q^H F^H, Q^H multiplies by conj(p)
+ *   CG update       Eq. update      psi_{m+1} = psi_m + gamma_m eta_m
+ *   direction       Eq. DaiYuan     eta_m = -grad_m + ||grad_m||^2 /
+ *                                   <eta_{m-1}, grad_m - grad_{m-1}> eta_{m-1}
+ *   line search     Eq. linesearch  F(psi + gamma eta) <= F(psi) + gamma t
+ *   workflow        Algorithm 1     GRAD -> DIR -> LS -> Update
+ *
+ * Conventions for every entry point:
+ *   - Complex values are interleaved float32 (re, im), i.e. torch.complex64.
+ *     Arrays are row-major and contiguous.
+ *   - All array pointers are DEVICE pointers owned by the caller unless a
+ *     parameter says "host".  The library never frees or retains them.
+ *   - F is the unitary 2-D DFT (1/n per n x n transform); the zero frequency
+ *     is at [0][0] (no shift).
+ *   - Scan positions are int32 [k][2] = (row, col) of the patch's top-left
+ *     corner; every patch must lie inside the object
+ *     (0 <= row <= obj_h - n, 0 <= col <= obj_w - n).  The enqueue calls do
+ *     not check this (ptyg_check_positions does; ptyg_cg_solve calls it).
+ *   - Enqueue calls are asynchronous on `stream` (a hipStream_t; NULL is the
+ *     default stream) and return after the launches.  Host-detectable
+ *     argument errors return before anything is launched.
+ *   - Scratch comes from a caller-provided device workspace of at least
+ *     ptyg_workspace_size() bytes (256-byte aligned).  The calls allocate no
+ *     device memory.  Concurrent calls must not share a workspace.
+ *   - Supported probe sizes n: 16, 32, 64, 128.  obj_h * obj_w * 8 bytes and
+ *     n * n * k * 8 bytes must each stay below 2^31 elements' worth of
+ *     indices (objects up to 32768 x 32768).
+ *   - No C++ exception crosses the ABI; the last error text of the calling
+ *     thread is available from ptyg_last_error().
+ */
+#ifndef PTYG_H
+#define PTYG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct {
+  float re, im;
+} ptyg_c64;
+
+typedef int32_t ptyg_status;
+enum {
+  PTYG_OK = 0,
+  PTYG_E_INVAL = -1,      /* null pointer, bad dims, unsupported n, misaligned workspace */
+  PTYG_E_BOUNDS = -2,     /* a scan position puts its patch outside the object */
+  PTYG_E_HIP = -3,        /* HIP launch or runtime error (see ptyg_last_error) */
+  PTYG_E_NONFINITE = -4,  /* NaN or Inf in the objective at the current iterate */
+  PTYG_E_WORKSPACE = -5   /* workspace smaller than ptyg_workspace_size() */
+};
+
+/* hipStream_t, passed as an opaque pointer so this header needs no HIP headers. */
+typedef void* ptyg_stream_t;
+
+typedef struct {
+  int32_t obj_h, obj_w; /* object rows, columns */
+  int32_t n;            /* probe side = detector side, in {16, 32, 64, 128} */
+  int32_t k;            /* number of scan positions = diffraction patterns, >= 1 */
+} ptyg_dims;
+
+/* Options of ptyg_cg_solve (Algorithm 1 and Eq. linesearch). */
+typedef struct {
+  int32_t iters;        /* iteration limit (Algorithm 1's iter_limit) */
+  int32_t update_probe; /* 0: object only (the paper); 1: joint object+probe CG */
+  double gamma0;        /* initial step of each line search (Algorithm 1: 1.0) */
+  double tau;           /* step shrink factor (Algorithm 1: 0.5) */
+  double t;             /* termination parameter of Eq. linesearch (0 in practice) */
+  int32_t max_halvings; /* line-search trials before giving up (gamma = 0, restart); e.g. 40 */
+  double eps;           /* guard on |G psi|^2 for log and division (e.g. 1e-32) */
+  double target_phi;    /* stop before an iteration whose deviance is <= target; < 0 disables */
+} ptyg_cg_opts;
+
+/* One row per completed iteration m of ptyg_cg_solve. */
+typedef struct {
+  double phi;       /* deviance form of Eq. ML at psi_m: sum d h((x-d)/d), h(u) = u - log(1+u) */
+  double f_eq2;     /* Eq. ML at psi_m (2 d log|g| written as d log|g|^2) */
+  double gamma;     /* accepted step gamma_m (0 if the line search failed) */
+  double beta;      /* Dai-Yuan coefficient used for eta_m (0 on a restart) */
+  double step_norm; /* ||psi_{m+1} - psi_m||_2 = gamma ||eta_m|| (the paper's convergence 2-norm) */
+  int32_t halvings; /* line-search trials (objective evaluations) */
+  int32_t restarted;/* 1 if eta_m = -grad_m (first iteration, bad denominator or failed search) */
+} ptyg_cg_iter_stats;
+
+/* Version of this ABI (increments on incompatible changes). */
+int32_t ptyg_abi_version(void);
+const char* ptyg_status_string(ptyg_status s);
+/* Text of the last error raised on the calling thread ("" if none). */
+const char* ptyg_last_error(void);
+
+/* Bytes of workspace needed by every call below for these dims; `opts` may be
+ * NULL (then the object-only solver is assumed).  Includes a transposed copy
+ * of the intensities (k*n*n floats) used by ptyg_cg_solve. */
+size_t ptyg_workspace_size(const ptyg_dims* dims, const ptyg_cg_opts* opts);
+
+/* Checks that every scan position keeps its patch inside the object.
+ * Synchronises `stream`.  Returns PTYG_OK or PTYG_E_BOUNDS. */
+ptyg_status ptyg_check_positions(const ptyg_dims* dims, const int32_t* pos, void* ws, size_t ws_bytes,
+                                 ptyg_stream_t stream);
+
+/* Eq. fwd_model: far[k] = F(probe * obj[pos_k]) for every position.
+ * obj [obj_h][obj_w], probe [n][n], pos [k][2], far [k][n][n] (written). */
+ptyg_status ptyg_forward(const ptyg_dims* dims, const ptyg_c64* obj, const ptyg_c64* probe,
+                         const int32_t* pos, ptyg_c64* far, ptyg_stream_t stream);
+
+/* G^H (text after Eq. gradient): obj_out = sum_k place_k(conj(probe) * F^H far[k]),
+ * overwritten.  If probe_out != NULL (then obj must be given):
+ * probe_out = sum_k conj(obj[pos_k]) * F^H far[k] (the adjoint of the map
+ * probe -> G(obj, probe)).  Summation order over k is unspecified (FP32 atomics). */
+ptyg_status ptyg_adjoint(const ptyg_dims* dims, const ptyg_c64* far, const ptyg_c64* probe,
+                         const int32_t* pos, ptyg_c64* obj_out, const ptyg_c64* obj, ptyg_c64* probe_out,
+                         void* ws, size_t ws_bytes, ptyg_stream_t stream);
+
+/* GRAD stage (Eq. gradient, Wirtinger derivative dF/d conj(psi), no factor 2):
+ * grad_obj = G^H (g - d g / |g|^2) with g = G(obj) and the residual replaced
+ * by g where |g|^2 < eps.  data: float32 intensities [k][n][n].
+ * grad_probe (nullable): sum_k conj(obj[pos_k]) * F^H r_k.
+ * objective (nullable, device double[2]): {deviance Phi, Eq. ML value F},
+ * accumulated in FP64 with a fixed reduction order. */
+ptyg_status ptyg_grad(const ptyg_dims* dims, const ptyg_c64* obj, const ptyg_c64* probe,
+                      const int32_t* pos, const float* data, float eps, ptyg_c64* grad_obj,
+                      ptyg_c64* grad_probe, double* objective, void* ws, size_t ws_bytes,
+                      ptyg_stream_t stream);
+
+/* MINFUNC of Algorithm 1 (one line-search trial): objective (device
+ * double[2], {Phi, F}) at obj + gamma*dir_obj and probe + gamma*dir_probe.
+ * dir_obj / dir_probe may be NULL (no step in that block). */
+ptyg_status ptyg_minfunc(const ptyg_dims* dims, const ptyg_c64* obj, const ptyg_c64* dir_obj,
+                         const ptyg_c64* probe, const ptyg_c64* dir_probe, double gamma, const int32_t* pos,
+                         const float* data, float eps, double* objective, void* ws, size_t ws_bytes,
+                         ptyg_stream_t stream);
+
+/* ML-CG reconstruction (Algorithm 1 on one GPU; Eqs. update, DaiYuan,
+ * linesearch).  obj: in psi_0, out psi_iters.  probe: read, and updated when
+ * opts->update_probe.  trace: HOST array of opts->iters rows (nullable).
+ * iters_done: HOST (nullable).  Synchronous: it waits on `stream` once per
+ * iteration and once per line-search trial (a few bytes read back each time).
+ * Returns PTYG_E_BOUNDS for a bad scan position and PTYG_E_NONFINITE if the
+ * objective at an iterate is not finite. */
+ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj, ptyg_c64* probe, const int32_t* pos,
+                          const float* data, const ptyg_cg_opts* opts, void* ws, size_t ws_bytes,
+                          ptyg_cg_iter_stats* trace, int32_t* iters_done, ptyg_stream_t stream);
+
+/* Opt-in kernel timing for benchmarks: when enabled, the fused GRAD kernel
+ * (kind 0) and the line-search MINFUNC kernel (kind 1) launched by any call
+ * above are bracketed by HIP events on their stream.  ptyg_timing_read
+ * waits for the recorded events and returns, per kind, the total elapsed
+ * milliseconds and the number of launches since the last reset (arrays of
+ * `kinds` entries, kinds <= 2).  Timing is per process and not thread-safe. */
+void ptyg_timing_enable(int32_t on);
+void ptyg_timing_reset(void);
+ptyg_status ptyg_timing_read(double* ms, int32_t* count, int32_t kinds);
+
+/* Test hooks (no FFT): patches[k] = obj[pos_k] bit for bit; obj_out (zeroed
+ * by the call) = sum_k place_k(patches[k]) with FP32 atomics. */
+ptyg_status ptyg_debug_gather(const ptyg_dims* dims, const ptyg_c64* obj, const int32_t* pos,
+                              ptyg_c64* patches, ptyg_stream_t stream);
+ptyg_status ptyg_debug_scatter(const ptyg_dims* dims, const ptyg_c64* patches, const int32_t* pos,
+                               ptyg_c64* obj_out, ptyg_stream_t stream);
+/* Test hook: applies the lane exchange used by the split-line transforms to
+ * two device float[64] arrays (lanes 32..63 of a <-> lanes 0..31 of b). */
+ptyg_status ptyg_debug_lane_swap(float* a, float* b, ptyg_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PTYG_H */

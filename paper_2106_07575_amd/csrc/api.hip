@@ -1,0 +1,550 @@
+// C-ABI entry points of libptyg.so: argument validation, workspace layout,
+// kernel sequencing and the ML-CG driver loop (Algorithm 1 on one GPU).
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <string>
+#include <vector>
+
+#include "../../include/ptyg.h"
+#include "kernels.hpp"
+
+using namespace ptyg;
+
+namespace {
+
+thread_local std::string g_last_error;
+
+ptyg_status fail(ptyg_status st, const char* fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_last_error = buf;
+  return st;
+}
+
+#define PTYG_HIP(expr)                                                                      \
+  do {                                                                                      \
+    hipError_t e_ = (expr);                                                                 \
+    if (e_ != hipSuccess) return fail(PTYG_E_HIP, "%s: %s", #expr, hipGetErrorString(e_)); \
+  } while (0)
+
+constexpr size_t kAlign = 256;
+constexpr int kProbeCopies = 32;  // probe-gradient accumulators (spreads atomics)
+constexpr size_t kScalars = 32;
+
+size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+
+bool n_supported(int n) { return n == 16 || n == 32 || n == 64 || n == 128; }
+
+ptyg_status check_dims(const ptyg_dims* d) {
+  if (!d) return fail(PTYG_E_INVAL, "dims is NULL");
+  if (!n_supported(d->n)) return fail(PTYG_E_INVAL, "probe size n=%d not in {16,32,64,128}", d->n);
+  if (d->k < 1) return fail(PTYG_E_INVAL, "k=%d must be >= 1", d->k);
+  if (d->obj_h < d->n || d->obj_w < d->n)
+    return fail(PTYG_E_INVAL, "object %dx%d smaller than the probe %d", d->obj_h, d->obj_w, d->n);
+  if ((int64_t)d->obj_h * d->obj_w >= (int64_t(1) << 31))
+    return fail(PTYG_E_INVAL, "object %dx%d too large", d->obj_h, d->obj_w);
+  return PTYG_OK;
+}
+
+// Workspace regions (byte offsets, each 256-byte aligned).
+struct Layout {
+  size_t partials, scalars, flag, pcopies, eta_obj, grad_obj, eta_probe, grad_probe, data_t, total;
+  size_t n_partials;
+};
+
+Layout layout(const ptyg_dims* d, bool joint) {
+  Layout L{};
+  const size_t obj_n = (size_t)d->obj_h * d->obj_w;
+  const size_t probe_n = (size_t)d->n * d->n;
+  // partial (phi, f) pairs: pattern kernels use <= 8*ceil(k/8)+8 blocks,
+  // vector kernels <= 2048
+  L.n_partials = (size_t)d->k + 16 + 4096;
+  size_t o = 0;
+  L.partials = o;
+  o = align_up(o + L.n_partials * 2 * sizeof(double));
+  L.scalars = o;
+  o = align_up(o + kScalars * sizeof(double));
+  L.flag = o;
+  o = align_up(o + sizeof(int));
+  L.pcopies = o;
+  o = align_up(o + (size_t)kProbeCopies * probe_n * sizeof(float2));
+  L.eta_obj = o;
+  o = align_up(o + obj_n * sizeof(float2));
+  L.grad_obj = o;
+  o = align_up(o + obj_n * sizeof(float2));
+  L.eta_probe = o;
+  o = align_up(o + (joint ? probe_n : 1) * sizeof(float2));
+  L.grad_probe = o;
+  o = align_up(o + (joint ? probe_n : 1) * sizeof(float2));
+  L.data_t = o;
+  o = align_up(o + (size_t)d->k * probe_n * sizeof(float));
+  L.total = o;
+  return L;
+}
+
+ptyg_status check_ws(const ptyg_dims* d, void* ws, size_t ws_bytes, bool joint, Layout* out) {
+  *out = layout(d, joint);
+  if (!ws) return fail(PTYG_E_INVAL, "workspace is NULL");
+  if (((uintptr_t)ws) % kAlign) return fail(PTYG_E_INVAL, "workspace not 256-byte aligned");
+  if (ws_bytes < out->total)
+    return fail(PTYG_E_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, out->total);
+  return PTYG_OK;
+}
+
+template <typename T>
+T* at(void* ws, size_t off) {
+  return reinterpret_cast<T*>(static_cast<char*>(ws) + off);
+}
+
+PatArgs base_args(const ptyg_dims* d) {
+  PatArgs a{};
+  a.H = d->obj_h;
+  a.W = d->obj_w;
+  a.K = d->k;
+  a.N = d->n;
+  a.eps = 1e-32f;
+  return a;
+}
+
+hipStream_t S(ptyg_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
+
+// ---- opt-in kernel timing (HIP events around the pattern kernels)
+struct Timing {
+  bool on = false;
+  struct Rec {
+    int kind;
+    hipEvent_t a, b;
+  };
+  std::vector<Rec> pending;
+  std::vector<hipEvent_t> pool;
+  double ms[2] = {0.0, 0.0};
+  int count[2] = {0, 0};
+  hipEvent_t get() {
+    if (!pool.empty()) {
+      hipEvent_t e = pool.back();
+      pool.pop_back();
+      return e;
+    }
+    hipEvent_t e = nullptr;
+    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    return e;
+  }
+  // waits for every recorded pair and accumulates it
+  void drain() {
+    for (Rec& r : pending) {
+      float t = 0.0f;
+      if (hipEventSynchronize(r.b) == hipSuccess && hipEventElapsedTime(&t, r.a, r.b) == hipSuccess) {
+        ms[r.kind] += t;
+        count[r.kind] += 1;
+      }
+      pool.push_back(r.a);
+      pool.push_back(r.b);
+    }
+    pending.clear();
+  }
+};
+Timing g_timing;
+
+struct TimedLaunch {
+  int kind;
+  hipStream_t s;
+  hipEvent_t a = nullptr, b = nullptr;
+  TimedLaunch(int k, hipStream_t st) : kind(k), s(st) {
+    if (!g_timing.on) return;
+    a = g_timing.get();
+    b = g_timing.get();
+    if (a && b) hipEventRecord(a, s);
+  }
+  ~TimedLaunch() {
+    if (!a || !b) return;
+    hipEventRecord(b, s);
+    g_timing.pending.push_back({kind, a, b});
+  }
+};
+
+}  // namespace
+
+extern "C" {
+
+int32_t ptyg_abi_version(void) { return 1; }
+
+const char* ptyg_status_string(ptyg_status s) {
+  switch (s) {
+    case PTYG_OK: return "ok";
+    case PTYG_E_INVAL: return "invalid argument";
+    case PTYG_E_BOUNDS: return "scan position outside the object";
+    case PTYG_E_HIP: return "HIP error";
+    case PTYG_E_NONFINITE: return "non-finite objective";
+    case PTYG_E_WORKSPACE: return "workspace too small";
+    default: return "unknown status";
+  }
+}
+
+const char* ptyg_last_error(void) { return g_last_error.c_str(); }
+
+size_t ptyg_workspace_size(const ptyg_dims* dims, const ptyg_cg_opts* opts) {
+  if (check_dims(dims) != PTYG_OK) return 0;
+  return layout(dims, opts && opts->update_probe).total;
+}
+
+ptyg_status ptyg_check_positions(const ptyg_dims* dims, const int32_t* pos, void* ws, size_t ws_bytes,
+                                 ptyg_stream_t stream) {
+  if (ptyg_status st = check_dims(dims)) return st;
+  if (!pos) return fail(PTYG_E_INVAL, "pos is NULL");
+  Layout L;
+  if (ptyg_status st = check_ws(dims, ws, ws_bytes, false, &L)) return st;
+  int* flag = at<int>(ws, L.flag);
+  PTYG_HIP(launch_fill_i32(flag, 1, 0, S(stream)));
+  PTYG_HIP(launch_check_positions(reinterpret_cast<const int2*>(pos), dims->k, dims->obj_h, dims->obj_w,
+                                  dims->n, flag, S(stream)));
+  int h = 0;
+  PTYG_HIP(hipMemcpyAsync(&h, flag, sizeof(int), hipMemcpyDeviceToHost, S(stream)));
+  PTYG_HIP(hipStreamSynchronize(S(stream)));
+  if (h) return fail(PTYG_E_BOUNDS, "a scan position puts its patch outside the %dx%d object", dims->obj_h,
+                     dims->obj_w);
+  return PTYG_OK;
+}
+
+ptyg_status ptyg_forward(const ptyg_dims* dims, const ptyg_c64* obj, const ptyg_c64* probe,
+                         const int32_t* pos, ptyg_c64* far, ptyg_stream_t stream) {
+  if (ptyg_status st = check_dims(dims)) return st;
+  if (!obj || !probe || !pos || !far) return fail(PTYG_E_INVAL, "NULL array argument");
+  PatArgs a = base_args(dims);
+  a.obj = reinterpret_cast<const float2*>(obj);
+  a.probe = reinterpret_cast<const float2*>(probe);
+  a.pos = reinterpret_cast<const int2*>(pos);
+  a.far = reinterpret_cast<float2*>(far);
+  PTYG_HIP(launch_forward(a, S(stream)));
+  return PTYG_OK;
+}
+
+ptyg_status ptyg_adjoint(const ptyg_dims* dims, const ptyg_c64* far, const ptyg_c64* probe,
+                         const int32_t* pos, ptyg_c64* obj_out, const ptyg_c64* obj, ptyg_c64* probe_out,
+                         void* ws, size_t ws_bytes, ptyg_stream_t stream) {
+  if (ptyg_status st = check_dims(dims)) return st;
+  if (!far || !probe || !pos || !obj_out) return fail(PTYG_E_INVAL, "NULL array argument");
+  if (probe_out && !obj) return fail(PTYG_E_INVAL, "probe_out requires obj");
+  Layout L;
+  if (probe_out) {
+    if (ptyg_status st = check_ws(dims, ws, ws_bytes, false, &L)) return st;
+  }
+  const hipStream_t s = S(stream);
+  PatArgs a = base_args(dims);
+  a.far = const_cast<float2*>(reinterpret_cast<const float2*>(far));
+  a.probe = reinterpret_cast<const float2*>(probe);
+  a.pos = reinterpret_cast<const int2*>(pos);
+  a.obj = reinterpret_cast<const float2*>(obj);
+  a.gobj = reinterpret_cast<float2*>(obj_out);
+  const int64_t pn = (int64_t)dims->n * dims->n;
+  PTYG_HIP(launch_zero(a.gobj, (int64_t)dims->obj_h * dims->obj_w, s));
+  if (probe_out) {
+    a.gprobe = at<float2>(ws, L.pcopies);
+    a.gprobe_copies = kProbeCopies;
+    PTYG_HIP(launch_zero(a.gprobe, kProbeCopies * pn, s));
+  }
+  PTYG_HIP(launch_adjoint(a, probe_out != nullptr, nullptr, s));
+  if (probe_out)
+    PTYG_HIP(launch_sum_copies(a.gprobe, kProbeCopies, pn, reinterpret_cast<float2*>(probe_out), s));
+  return PTYG_OK;
+}
+
+namespace {
+// One fused GRAD pass; writes {phi, f} to `objective` (device) when given.
+ptyg_status run_grad(const ptyg_dims* dims, const float2* obj, const float2* probe, const int2* pos,
+                     const float* data, DataLayout lay, float eps, float2* grad_obj, float2* grad_probe,
+                     double* objective, void* ws, const Layout& L, hipStream_t s) {
+  PatArgs a = base_args(dims);
+  a.obj = obj;
+  a.probe = probe;
+  a.pos = pos;
+  a.data = data;
+  a.eps = eps;
+  a.gobj = grad_obj;
+  a.partials = at<double>(ws, L.partials);
+  const int64_t pn = (int64_t)dims->n * dims->n;
+  PTYG_HIP(launch_zero(grad_obj, (int64_t)dims->obj_h * dims->obj_w, s));
+  if (grad_probe) {
+    a.gprobe = at<float2>(ws, L.pcopies);
+    a.gprobe_copies = kProbeCopies;
+    PTYG_HIP(launch_zero(a.gprobe, kProbeCopies * pn, s));
+  }
+  int nb = 0;
+  {
+    TimedLaunch tl(0, s);
+    PTYG_HIP(launch_grad(a, lay, grad_probe != nullptr, &nb, s));
+  }
+  if (objective) PTYG_HIP(launch_finalize(a.partials, nb, 2, objective, s));
+  if (grad_probe) PTYG_HIP(launch_sum_copies(a.gprobe, kProbeCopies, pn, grad_probe, s));
+  return PTYG_OK;
+}
+
+ptyg_status run_minfunc(const ptyg_dims* dims, const float2* obj, const float2* dobj, const float2* probe,
+                        const float2* dprobe, double gamma, const int2* pos, const float* data, DataLayout lay,
+                        float eps, double* objective, void* ws, const Layout& L, hipStream_t s) {
+  PatArgs a = base_args(dims);
+  a.obj = obj;
+  a.dobj = dobj;
+  a.probe = probe;
+  a.dprobe = dprobe;
+  a.gamma = (float)gamma;
+  a.pos = pos;
+  a.data = data;
+  a.eps = eps;
+  a.partials = at<double>(ws, L.partials);
+  int nb = 0;
+  {
+    TimedLaunch tl(1, s);
+    PTYG_HIP(launch_minfunc(a, lay, &nb, s));
+  }
+  PTYG_HIP(launch_finalize(a.partials, nb, 2, objective, s));
+  return PTYG_OK;
+}
+}  // namespace
+
+ptyg_status ptyg_grad(const ptyg_dims* dims, const ptyg_c64* obj, const ptyg_c64* probe, const int32_t* pos,
+                      const float* data, float eps, ptyg_c64* grad_obj, ptyg_c64* grad_probe, double* objective,
+                      void* ws, size_t ws_bytes, ptyg_stream_t stream) {
+  if (ptyg_status st = check_dims(dims)) return st;
+  if (!obj || !probe || !pos || !data || !grad_obj) return fail(PTYG_E_INVAL, "NULL array argument");
+  if (!(eps >= 0.0f)) return fail(PTYG_E_INVAL, "eps must be >= 0");
+  Layout L;
+  if (ptyg_status st = check_ws(dims, ws, ws_bytes, false, &L)) return st;
+  return run_grad(dims, reinterpret_cast<const float2*>(obj), reinterpret_cast<const float2*>(probe),
+                  reinterpret_cast<const int2*>(pos), data, DataLayout::Rows, eps,
+                  reinterpret_cast<float2*>(grad_obj), reinterpret_cast<float2*>(grad_probe), objective, ws, L,
+                  S(stream));
+}
+
+ptyg_status ptyg_minfunc(const ptyg_dims* dims, const ptyg_c64* obj, const ptyg_c64* dir_obj,
+                         const ptyg_c64* probe, const ptyg_c64* dir_probe, double gamma, const int32_t* pos,
+                         const float* data, float eps, double* objective, void* ws, size_t ws_bytes,
+                         ptyg_stream_t stream) {
+  if (ptyg_status st = check_dims(dims)) return st;
+  if (!obj || !probe || !pos || !data || !objective) return fail(PTYG_E_INVAL, "NULL array argument");
+  if (!std::isfinite(gamma)) return fail(PTYG_E_INVAL, "gamma not finite");
+  Layout L;
+  if (ptyg_status st = check_ws(dims, ws, ws_bytes, false, &L)) return st;
+  return run_minfunc(dims, reinterpret_cast<const float2*>(obj), reinterpret_cast<const float2*>(dir_obj),
+                     reinterpret_cast<const float2*>(probe), reinterpret_cast<const float2*>(dir_probe), gamma,
+                     reinterpret_cast<const int2*>(pos), data, DataLayout::Rows, eps, objective, ws, L,
+                     S(stream));
+}
+
+ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* probe_c, const int32_t* pos_i,
+                          const float* data, const ptyg_cg_opts* opts, void* ws, size_t ws_bytes,
+                          ptyg_cg_iter_stats* trace, int32_t* iters_done, ptyg_stream_t stream) {
+  if (ptyg_status st = check_dims(dims)) return st;
+  if (!obj_c || !probe_c || !pos_i || !data || !opts) return fail(PTYG_E_INVAL, "NULL argument");
+  if (opts->iters < 0) return fail(PTYG_E_INVAL, "iters < 0");
+  if (!(opts->tau > 0.0 && opts->tau < 1.0)) return fail(PTYG_E_INVAL, "tau must be in (0, 1)");
+  if (!(opts->gamma0 > 0.0) || !std::isfinite(opts->gamma0)) return fail(PTYG_E_INVAL, "gamma0 must be > 0");
+  if (opts->max_halvings < 1) return fail(PTYG_E_INVAL, "max_halvings must be >= 1");
+  if (!(opts->eps >= 0.0)) return fail(PTYG_E_INVAL, "eps must be >= 0");
+  const bool joint = opts->update_probe != 0;
+  Layout L;
+  if (ptyg_status st = check_ws(dims, ws, ws_bytes, joint, &L)) return st;
+  if (iters_done) *iters_done = 0;
+  if (ptyg_status st = ptyg_check_positions(dims, pos_i, ws, ws_bytes, stream)) return st;
+
+  const hipStream_t s = S(stream);
+  float2* obj = reinterpret_cast<float2*>(obj_c);
+  float2* probe = reinterpret_cast<float2*>(probe_c);
+  const int2* pos = reinterpret_cast<const int2*>(pos_i);
+  const int64_t on = (int64_t)dims->obj_h * dims->obj_w;
+  const int64_t pn = (int64_t)dims->n * dims->n;
+  float2* eta_o = at<float2>(ws, L.eta_obj);
+  float2* grad_o = at<float2>(ws, L.grad_obj);
+  float2* eta_p = joint ? at<float2>(ws, L.eta_probe) : nullptr;
+  float2* grad_p = joint ? at<float2>(ws, L.grad_probe) : nullptr;
+  float* dt = at<float>(ws, L.data_t);
+  double* partials = at<double>(ws, L.partials);
+  double* sc = at<double>(ws, L.scalars);
+  const float eps = (float)opts->eps;
+
+  // the intensities are read by every pass: store them per pattern transposed
+  // so that the row-layout reads are coalesced
+  PTYG_HIP(launch_transpose_data(data, dt, dims->k, dims->n, s));
+
+  // scalar slots
+  enum { PHI = 0, FEQ = 1, N1O = 2, N2O = 3, N1P = 4, N2P = 5, N3O = 6, EEO = 7, N3P = 8, EEP = 9, PHIT = 10 };
+  double h[16];
+  double n3_prev = 0.0;  // Re<eta_{m-1}, grad_{m-1}>
+  bool restart = true;
+  const int nvb_o = vec_blocks(on), nvb_p = vec_blocks(pn);
+
+  for (int m = 0; m < opts->iters; ++m) {
+    // GRAD stage
+    if (ptyg_status st = run_grad(dims, obj, probe, pos, dt, DataLayout::Transposed, eps, grad_o, grad_p,
+                                  sc + PHI, ws, L, s))
+      return st;
+    VecArgs v{};
+    v.n = on;
+    v.a = grad_o;
+    v.b = restart ? nullptr : eta_o;
+    v.partials = partials;
+    PTYG_HIP(launch_dot2(v, s));
+    PTYG_HIP(launch_finalize(partials, nvb_o, 2, sc + N1O, s));
+    if (joint) {
+      VecArgs vp{};
+      vp.n = pn;
+      vp.a = grad_p;
+      vp.b = restart ? nullptr : eta_p;
+      vp.partials = partials;
+      PTYG_HIP(launch_dot2(vp, s));
+      PTYG_HIP(launch_finalize(partials, nvb_p, 2, sc + N1P, s));
+    }
+    PTYG_HIP(hipMemcpyAsync(h, sc, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
+    PTYG_HIP(hipStreamSynchronize(s));
+    const double phi_m = h[PHI], f_m = h[FEQ];
+    if (!std::isfinite(phi_m))
+      return fail(PTYG_E_NONFINITE, "objective is %g at iteration %d", phi_m, m);
+    if (opts->target_phi >= 0.0 && phi_m <= opts->target_phi) break;
+
+    // DIR stage (Eq. DaiYuan): beta = ||g_m||^2 / Re<eta_{m-1}, g_m - g_{m-1}>
+    double beta = 0.0;
+    bool restarted = restart;
+    if (!restart) {
+      const double n1 = h[N1O] + (joint ? h[N1P] : 0.0);
+      const double n2 = h[N2O] + (joint ? h[N2P] : 0.0);
+      const double den = n2 - n3_prev;
+      if (std::isfinite(den) && den > 0.0 && std::isfinite(n1)) beta = n1 / den;
+      else restarted = true;
+    }
+    v = VecArgs{};
+    v.n = on;
+    v.a = grad_o;
+    v.b = eta_o;
+    v.alpha = beta;
+    v.partials = partials;
+    if (restarted) {
+      // eta = -grad: run the same kernel on a zeroed direction
+      PTYG_HIP(launch_zero(eta_o, on, s));
+      if (joint) PTYG_HIP(launch_zero(eta_p, pn, s));
+      v.alpha = 0.0;
+    }
+    PTYG_HIP(launch_dir(v, s));
+    PTYG_HIP(launch_finalize(partials, nvb_o, 2, sc + N3O, s));
+    if (joint) {
+      VecArgs vp{};
+      vp.n = pn;
+      vp.a = grad_p;
+      vp.b = eta_p;
+      vp.alpha = restarted ? 0.0 : beta;
+      vp.partials = partials;
+      PTYG_HIP(launch_dir(vp, s));
+      PTYG_HIP(launch_finalize(partials, nvb_p, 2, sc + N3P, s));
+    }
+
+    // LS stage (Eq. linesearch, Algorithm 1 order: shrink, then evaluate)
+    double gamma = opts->gamma0;
+    bool accepted = false;
+    int trials = 0;
+    double eta2 = 0.0, n3 = 0.0;
+    for (int j = 1; j <= opts->max_halvings; ++j) {
+      gamma *= opts->tau;
+      trials = j;
+      if (ptyg_status st = run_minfunc(dims, obj, eta_o, probe, eta_p, gamma, pos, dt, DataLayout::Transposed,
+                                       eps, sc + PHIT, ws, L, s))
+        return st;
+      PTYG_HIP(hipMemcpyAsync(h + N3O, sc + N3O, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
+      PTYG_HIP(hipStreamSynchronize(s));
+      n3 = h[N3O] + (joint ? h[N3P] : 0.0);
+      eta2 = h[EEO] + (joint ? h[EEP] : 0.0);
+      const double phi_t = h[PHIT];
+      if (phi_t <= phi_m + gamma * opts->t) {
+        accepted = true;
+        break;
+      }
+    }
+    if (!accepted) gamma = 0.0;
+
+    // Update stage (Eq. update)
+    if (gamma != 0.0) {
+      VecArgs u{};
+      u.n = on;
+      u.a = obj;
+      u.c = eta_o;
+      u.alpha = gamma;
+      PTYG_HIP(launch_axpy(u, s));
+      if (joint) {
+        VecArgs up{};
+        up.n = pn;
+        up.a = probe;
+        up.c = eta_p;
+        up.alpha = gamma;
+        PTYG_HIP(launch_axpy(up, s));
+      }
+    }
+    if (trace) {
+      ptyg_cg_iter_stats& t = trace[m];
+      t.phi = phi_m;
+      t.f_eq2 = f_m;
+      t.gamma = gamma;
+      t.beta = restarted ? 0.0 : beta;
+      t.step_norm = gamma * std::sqrt(eta2 > 0.0 ? eta2 : 0.0);
+      t.halvings = trials;
+      t.restarted = restarted ? 1 : 0;
+    }
+    n3_prev = n3;
+    restart = !accepted;
+    if (iters_done) *iters_done = m + 1;
+  }
+  PTYG_HIP(hipStreamSynchronize(s));
+  return PTYG_OK;
+}
+
+void ptyg_timing_enable(int32_t on) { g_timing.on = on != 0; }
+
+void ptyg_timing_reset(void) {
+  g_timing.drain();
+  g_timing.ms[0] = g_timing.ms[1] = 0.0;
+  g_timing.count[0] = g_timing.count[1] = 0;
+}
+
+ptyg_status ptyg_timing_read(double* ms, int32_t* count, int32_t kinds) {
+  if (!ms || !count || kinds < 0 || kinds > 2) return fail(PTYG_E_INVAL, "bad timing arguments");
+  g_timing.drain();
+  for (int i = 0; i < kinds; ++i) {
+    ms[i] = g_timing.ms[i];
+    count[i] = g_timing.count[i];
+  }
+  return PTYG_OK;
+}
+
+ptyg_status ptyg_debug_gather(const ptyg_dims* dims, const ptyg_c64* obj, const int32_t* pos,
+                              ptyg_c64* patches, ptyg_stream_t stream) {
+  if (ptyg_status st = check_dims(dims)) return st;
+  if (!obj || !pos || !patches) return fail(PTYG_E_INVAL, "NULL array argument");
+  PatArgs a = base_args(dims);
+  a.obj = reinterpret_cast<const float2*>(obj);
+  a.pos = reinterpret_cast<const int2*>(pos);
+  PTYG_HIP(launch_debug_gather(a, reinterpret_cast<float2*>(patches), S(stream)));
+  return PTYG_OK;
+}
+
+ptyg_status ptyg_debug_scatter(const ptyg_dims* dims, const ptyg_c64* patches, const int32_t* pos,
+                               ptyg_c64* obj_out, ptyg_stream_t stream) {
+  if (ptyg_status st = check_dims(dims)) return st;
+  if (!patches || !pos || !obj_out) return fail(PTYG_E_INVAL, "NULL array argument");
+  PatArgs a = base_args(dims);
+  a.pos = reinterpret_cast<const int2*>(pos);
+  a.gobj = reinterpret_cast<float2*>(obj_out);
+  PTYG_HIP(launch_zero(a.gobj, (int64_t)dims->obj_h * dims->obj_w, S(stream)));
+  PTYG_HIP(launch_debug_scatter(a, reinterpret_cast<const float2*>(patches), S(stream)));
+  return PTYG_OK;
+}
+
+ptyg_status ptyg_debug_lane_swap(float* a, float* b, ptyg_stream_t stream) {
+  if (!a || !b) return fail(PTYG_E_INVAL, "NULL array argument");
+  PTYG_HIP(launch_debug_lane_swap(a, b, S(stream)));
+  return PTYG_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,697 @@
+// HIP kernels for gfx950: the ML-CG ptychography hot path.
+//
+//   forward  (Eq. fwd_model)    g_k = F (p * psi[s_k])
+//   adjoint  (text after Eq. gradient) G^H = Q^H F^H with scatter-add
+//   grad     (Eq. gradient, GRAD stage of Algorithm 1) fused:
+//            gather -> *p -> F -> residual + objective terms -> F^H -> *conj p
+//            -> scatter-add (+ probe gradient terms in joint mode)
+//   minfunc  (MINFUNC of Algorithm 1, a line-search trial of Eq. linesearch)
+//            gather (psi + gamma eta) -> *(p + gamma eta_p) -> F -> objective
+//   vector kernels for the DIR and Update stages (Eqs. DaiYuan, update).
+//
+// F is the unitary 2-D DFT (1/N per transform), DC at [0][0].  Transform
+// arithmetic is FP32; objective terms are accumulated per thread in FP64 and
+// reduced deterministically (fixed workgroup -> pattern mapping, fixed
+// reduction trees).  The object-gradient scatter uses FP32 atomics.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+#include "pattern.hpp"
+
+namespace ptyg {
+
+namespace {
+
+// Pattern kernels: the LDS transpose buffer allows Geo<N>::WAVES_PER_EU waves
+// per SIMD; asking the register allocator for exactly that occupancy keeps
+// the scheduler from hoisting every gather load at once.
+#define PTYG_PATTERN_KERNEL(N) \
+  __launch_bounds__(Geo<N>::WG) __attribute__((amdgpu_waves_per_eu(Geo<N>::WAVES_PER_EU, Geo<N>::WAVES_PER_EU)))
+
+constexpr float kLn2 = 0.69314718055994530942f;
+
+// Block-wide sum of two doubles; the result is valid in thread 0.
+template <int WG>
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* red) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    a += __shfl_xor(a, off);
+    b += __shfl_xor(b, off);
+  }
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) {
+    red[2 * w] = a;
+    red[2 * w + 1] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a = 0.0;
+    b = 0.0;
+#pragma unroll
+    for (int i = 0; i < WG / 64; ++i) {
+      a += red[2 * i];
+      b += red[2 * i + 1];
+    }
+  }
+}
+
+// Per-pixel objective terms and residual factor (Eqs. ML, gradient).
+//   phi   : deviance x - d - d log(max(x,eps)/d)  (x for d = 0)
+//   fterm : x - d log max(x, eps)                  (x for d = 0)
+//   fac   : 1 - d/x for x >= eps, 1 otherwise      (r = g * fac)
+// The deviance is d * h with h = delta - log(1 + delta), delta = (x-d)/d:
+// a series for |delta| < 0.1 (no cancellation near a fit), otherwise the
+// log of the ratio x/d itself (1 + delta would round to 0 for x << d).
+// A NaN intensity propagates into every term.
+template <bool WANT_F>
+__device__ __forceinline__ void pixel_terms(float x, float d, float eps, float& phi, float& fterm,
+                                            float& fac) {
+  const bool dpos = !(d <= 0.0f);  // NaN counts as positive so that it propagates
+  const bool big = x >= eps;
+  const float rd = __builtin_amdgcn_rcpf(dpos ? d : 1.0f);
+  const float xg = big ? x : eps;
+  const float delta = (xg - d) * rd;
+  // series of delta - log1p(delta)
+  float s = fmaf(-delta, 1.0f / 9.0f, 1.0f / 8.0f);
+  s = fmaf(-delta, s, 1.0f / 7.0f);
+  s = fmaf(-delta, s, 1.0f / 6.0f);
+  s = fmaf(-delta, s, 1.0f / 5.0f);
+  s = fmaf(-delta, s, 1.0f / 4.0f);
+  s = fmaf(-delta, s, 1.0f / 3.0f);
+  s = fmaf(-delta, s, 0.5f);
+  const float hser = delta * delta * s;
+  // x/d, scaled by 2^64 under the guard so that eps/d stays a normal number
+  const float lr = big ? __log2f(xg * rd) : __log2f(xg * rd * 0x1p64f) - 64.0f;
+  const float hlog = delta - lr * kLn2;
+  const float h = fabsf(delta) < 0.1f ? hser : hlog;
+  const float ph = d * h + (x - xg);
+  phi = dpos ? ph : x;
+  if constexpr (WANT_F) fterm = dpos ? x - d * __log2f(xg) * kLn2 : x;
+  const float rx = __builtin_amdgcn_rcpf(big ? x : 1.0f);
+  fac = (big && dpos) ? 1.0f - d * rx : 1.0f;
+}
+
+// Addressing: every global access is written as a pointer that is uniform
+// across the wave (computed from the pattern index and a compile-time slot
+// offset) plus a 32-bit lane offset, so the loads use the scalar-base form
+// and the 64 slots share one offset register.
+template <int N>
+__device__ __forceinline__ uint32_t lane_off(const Lane& L, uint32_t stride) {
+  return (L.h ? stride : 0u) + (uint32_t)L.line;
+}
+
+// Intensity at (row arow = lane line, frequency column slot s).
+template <int N, DataLayout LAY>
+__device__ __forceinline__ float load_data(const float* data, int k, const Lane& L, int s) {
+  constexpr int f = 0;
+  (void)f;
+  const float* dk = data + (size_t)k * N * N;
+  if constexpr (LAY == DataLayout::Transposed) {
+    // element (a, b) at b*N + a; b = kFreq[s] + (E/2) h, a = line
+    return (dk + (size_t)kFreq<N>.f[s] * N)[lane_off<N>(L, (Geo<N>::E / 2) * N)];
+  } else {
+    return (dk + kFreq<N>.f[s])[(uint32_t)L.line * N + (L.h ? Geo<N>::E / 2 : 0)];
+  }
+}
+
+// Gather p * psi patch (optionally (p + g eta_p) * (psi + g eta_psi)) into
+// column-layout spatial slots.  The object loads go straight into the data
+// registers (all in flight at once); the probe and direction loads follow in
+// chunks fenced from the scheduler so that their results never occupy more
+// than a few registers.
+constexpr int kChunk = 8;
+constexpr int kResChunk = 4;  // residual: many temporaries per pixel
+
+template <int N, bool LINC_O, bool LINC_P>
+__device__ __forceinline__ void gather_exit_wave(float2* v, const PatArgs& a, const Lane& L, int2 rc,
+                                                 bool valid) {
+  using G = Geo<N>;
+  constexpr int T = G::TPC;
+  const uint32_t lo = lane_off<N>(L, (uint32_t)a.W);
+  const size_t corner = (size_t)rc.x * a.W + rc.y;
+  if constexpr (!LINC_O) {
+#pragma unroll
+    for (int m = 0; m < G::E; ++m) v[m] = (a.obj + corner + (size_t)(m * T) * a.W)[lo];
+  } else {
+#pragma unroll
+    for (int c = 0; c < G::E; c += 2 * kChunk) {
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int m = c; m < c + 2 * kChunk; ++m) {
+        const size_t row = corner + (size_t)(m * T) * a.W;
+        const float2 o = (a.obj + row)[lo], e = (a.dobj + row)[lo];
+        v[m] = make_float2(fmaf(a.gamma, e.x, o.x), fmaf(a.gamma, e.y, o.y));
+      }
+    }
+  }
+  const uint32_t plo = lane_off<N>(L, N);
+#pragma unroll
+  for (int c = 0; c < G::E; c += kChunk) {
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int m = c; m < c + kChunk; ++m) {
+      float2 p = (a.probe + m * T * N)[plo];
+      if constexpr (LINC_P) {
+        const float2 dp = (a.dprobe + m * T * N)[plo];
+        p = make_float2(fmaf(a.gamma, dp.x, p.x), fmaf(a.gamma, dp.y, p.y));
+      }
+      if (!valid) p = make_float2(0.f, 0.f);
+      v[m] = cmul(p, v[m]);
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// Scatter conj(p) * v onto the object accumulator; joint mode also adds
+// conj(psi patch) * v onto a probe-gradient copy.
+template <int N, bool PROBE>
+__device__ __forceinline__ void scatter_adjoint(const float2* v, const PatArgs& a, const Lane& L, int2 rc,
+                                                bool valid, int copy) {
+  using G = Geo<N>;
+  constexpr int T = G::TPC;
+  if (!valid) return;
+  const uint32_t lo = lane_off<N>(L, (uint32_t)a.W);
+  const uint32_t plo = lane_off<N>(L, N);
+  const size_t corner = (size_t)rc.x * a.W + rc.y;
+#pragma unroll
+  for (int c = 0; c < G::E; c += kChunk) {
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int m = c; m < c + kChunk; ++m) {
+      const size_t row = corner + (size_t)(m * T) * a.W;
+      const float2 p = (a.probe + m * T * N)[plo];
+      const float2 val = cmulc(p, v[m]);
+      float2* g = (a.gobj + row) + lo;
+      unsafeAtomicAdd(&g->x, val.x);
+      unsafeAtomicAdd(&g->y, val.y);
+      if constexpr (PROBE) {
+        const float2 o = (a.obj + row)[lo];
+        const float2 pv = cmulc(o, v[m]);
+        float2* gp = (a.gprobe + (size_t)copy * N * N + m * T * N) + plo;
+        unsafeAtomicAdd(&gp->x, pv.x);
+        unsafeAtomicAdd(&gp->y, pv.y);
+      }
+    }
+  }
+}
+
+// Pattern handled by this lane.  Lanes past the last pattern (only possible
+// when several patterns share a workgroup) read pattern 0 so that every load
+// stays in bounds, and their contributions are masked.  Returns false when
+// the whole workgroup has no pattern (it then writes zero partials and exits
+// before any barrier).
+template <int N>
+__device__ __forceinline__ bool pattern_of(const PatArgs& a, const Lane& L, int& k, bool& valid, int2& rc) {
+  const int groups = (a.K + Geo<N>::PPW - 1) / Geo<N>::PPW;
+  const int g = group_of_block(blockIdx.x, groups);
+  if (g < 0) return false;
+  k = g * Geo<N>::PPW + L.pslot;
+  valid = k < a.K;
+  if (!valid) k = 0;
+  rc = a.pos[k];
+  return true;
+}
+
+__device__ __forceinline__ void write_zero_partials(const PatArgs& a) {
+  if (threadIdx.x == 0 && a.partials) {
+    a.partials[2 * blockIdx.x] = 0.0;
+    a.partials[2 * blockIdx.x + 1] = 0.0;
+  }
+}
+
+// ----------------------------------------------------------------- kernels
+template <int N>
+__global__ PTYG_PATTERN_KERNEL(N) void k_forward(PatArgs a) {
+  using G = Geo<N>;
+  __shared__ float2 lds[G::LDS_ELEMS];
+  const Lane L = lane_info<N>();
+  int k;
+  bool valid;
+  int2 rc;
+  if (!pattern_of<N>(a, L, k, valid, rc)) {
+    write_zero_partials(a);
+    return;
+  }
+  float2 v[G::E];
+  gather_exit_wave<N, false, false>(v, a, L, rc, valid);
+  fwd_line<N>(v, L.h);
+  transpose_c2r<N>(v, lds, L);
+  fwd_line<N>(v, L.h);
+  if (!valid) return;
+  const float invN = 1.0f / N;
+#pragma unroll
+  for (int s = 0; s < G::E; ++s) {
+    const int b = fidx<N>(s, L.h);
+    (a.far + (size_t)k * N * N + kFreq<N>.f[s])[(uint32_t)L.line * N + (L.h ? G::E / 2 : 0)] = cscale(v[s], invN);
+  }
+}
+
+template <int N, bool PROBE>
+__global__ PTYG_PATTERN_KERNEL(N) void k_adjoint(PatArgs a) {
+  using G = Geo<N>;
+  __shared__ float2 lds[G::LDS_ELEMS];
+  const Lane L = lane_info<N>();
+  int k;
+  bool valid;
+  int2 rc;
+  if (!pattern_of<N>(a, L, k, valid, rc)) {
+    write_zero_partials(a);
+    return;
+  }
+  float2 v[G::E];
+  const float invN = 1.0f / N;
+#pragma unroll
+  for (int s = 0; s < G::E; ++s) {
+    const int b = fidx<N>(s, L.h);
+    v[s] = cscale((a.far + (size_t)k * N * N + kFreq<N>.f[s])[(uint32_t)L.line * N + (L.h ? G::E / 2 : 0)],
+                  valid ? invN : 0.0f);
+  }
+  inv_line<N>(v, L.h);
+  transpose_r2c<N>(v, lds, L);
+  inv_line<N>(v, L.h);
+  scatter_adjoint<N, PROBE>(v, a, L, rc, valid, blockIdx.x % (a.gprobe_copies > 0 ? a.gprobe_copies : 1));
+}
+
+template <int N, DataLayout LAY, bool PROBE>
+__global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
+  using G = Geo<N>;
+  __shared__ float2 lds[G::LDS_ELEMS];
+  __shared__ double red[2 * (G::WG / 64)];
+  const Lane L = lane_info<N>();
+  int k;
+  bool valid;
+  int2 rc;
+  if (!pattern_of<N>(a, L, k, valid, rc)) {
+    write_zero_partials(a);
+    return;
+  }
+  float2 v[G::E];
+  gather_exit_wave<N, false, false>(v, a, L, rc, valid);
+  fwd_line<N>(v, L.h);
+  transpose_c2r<N>(v, lds, L);
+  fwd_line<N>(v, L.h);
+  const float invN = 1.0f / N;
+  double acc_phi = 0.0, acc_f = 0.0;
+#pragma unroll
+  for (int s = 0; s < G::E; ++s) {
+    if (s % kResChunk == 0) __builtin_amdgcn_sched_barrier(0);
+    const int b = fidx<N>(s, L.h);
+    const float d = load_data<N, LAY>(a.data, k, L, s);
+    const float2 g = cscale(v[s], invN);
+    const float x = fmaf(g.x, g.x, g.y * g.y);
+    float phi, ft, fac;
+    pixel_terms<true>(x, d, a.eps, phi, ft, fac);
+    acc_phi += (double)phi;
+    acc_f += (double)ft;
+    v[s] = cscale(g, fac * invN);
+  }
+  inv_line<N>(v, L.h);
+  transpose_r2c<N>(v, lds, L);
+  inv_line<N>(v, L.h);
+  scatter_adjoint<N, PROBE>(v, a, L, rc, valid, blockIdx.x % (a.gprobe_copies > 0 ? a.gprobe_copies : 1));
+  if (!valid) {
+    acc_phi = 0.0;
+    acc_f = 0.0;
+  }
+  block_sum2<G::WG>(acc_phi, acc_f, red);
+  if (threadIdx.x == 0) {
+    a.partials[2 * blockIdx.x] = acc_phi;
+    a.partials[2 * blockIdx.x + 1] = acc_f;
+  }
+}
+
+template <int N, DataLayout LAY, bool LINC_O, bool LINC_P>
+__global__ PTYG_PATTERN_KERNEL(N) void k_minfunc(PatArgs a) {
+  using G = Geo<N>;
+  __shared__ float2 lds[G::LDS_ELEMS];
+  __shared__ double red[2 * (G::WG / 64)];
+  const Lane L = lane_info<N>();
+  int k;
+  bool valid;
+  int2 rc;
+  if (!pattern_of<N>(a, L, k, valid, rc)) {
+    write_zero_partials(a);
+    return;
+  }
+  float2 v[G::E];
+  gather_exit_wave<N, LINC_O, LINC_P>(v, a, L, rc, valid);
+  fwd_line<N>(v, L.h);
+  transpose_c2r<N>(v, lds, L);
+  fwd_line<N>(v, L.h);
+  const float invN = 1.0f / N;
+  double acc_phi = 0.0, acc_f = 0.0;
+#pragma unroll
+  for (int s = 0; s < G::E; ++s) {
+    if (s % kResChunk == 0) __builtin_amdgcn_sched_barrier(0);
+    const int b = fidx<N>(s, L.h);
+    const float d = load_data<N, LAY>(a.data, k, L, s);
+    const float2 g = cscale(v[s], invN);
+    const float x = fmaf(g.x, g.x, g.y * g.y);
+    float phi, ft, fac;
+    pixel_terms<true>(x, d, a.eps, phi, ft, fac);
+    acc_phi += (double)phi;
+    acc_f += (double)ft;
+  }
+  if (!valid) {
+    acc_phi = 0.0;
+    acc_f = 0.0;
+  }
+  block_sum2<G::WG>(acc_phi, acc_f, red);
+  if (threadIdx.x == 0) {
+    a.partials[2 * blockIdx.x] = acc_phi;
+    a.partials[2 * blockIdx.x + 1] = acc_f;
+  }
+}
+
+// d [K][N][N] -> per-pattern transpose [K][N][N] (element (a,b) at b*N+a),
+// tiled 32 x 32 through LDS.
+__global__ __launch_bounds__(256) void k_transpose_data(const float* __restrict__ d, float* __restrict__ dt,
+                                                         int N) {
+  __shared__ float tile[32][33];
+  const int tiles = N / 32;
+  const int k = blockIdx.z;
+  const int ta = blockIdx.y, tb = blockIdx.x;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;  // 32 x 8
+  const float* src = d + (size_t)k * N * N;
+  float* dst = dt + (size_t)k * N * N;
+  (void)tiles;
+#pragma unroll
+  for (int j = 0; j < 32; j += 8) tile[ty + j][tx] = src[(size_t)(ta * 32 + ty + j) * N + tb * 32 + tx];
+  __syncthreads();
+#pragma unroll
+  for (int j = 0; j < 32; j += 8) dst[(size_t)(tb * 32 + ty + j) * N + ta * 32 + tx] = tile[tx][ty + j];
+}
+
+// Small-N transpose (N < 32): one thread per element.
+__global__ void k_transpose_data_small(const float* __restrict__ d, float* __restrict__ dt, int K, int N) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t tot = (int64_t)K * N * N;
+  if (i >= tot) return;
+  const int64_t k = i / ((int64_t)N * N);
+  const int r = (int)(i % ((int64_t)N * N));
+  const int aa = r / N, bb = r % N;
+  dt[k * N * N + (int64_t)bb * N + aa] = d[i];
+}
+
+template <int N>
+__global__ PTYG_PATTERN_KERNEL(N) void k_debug_gather(PatArgs a, float2* patches) {
+  using G = Geo<N>;
+  const Lane L = lane_info<N>();
+  int k;
+  bool valid;
+  int2 rc;
+  if (!pattern_of<N>(a, L, k, valid, rc)) {
+    write_zero_partials(a);
+    return;
+  }
+  if (!valid) return;
+#pragma unroll
+  for (int m = 0; m < G::E; ++m) {
+    const int u = sidx<N>(m, L.h);
+    patches[(size_t)k * N * N + u * N + L.line] = a.obj[(size_t)(rc.x + u) * a.W + rc.y + L.line];
+  }
+}
+
+template <int N>
+__global__ PTYG_PATTERN_KERNEL(N) void k_debug_scatter(PatArgs a, const float2* patches) {
+  using G = Geo<N>;
+  const Lane L = lane_info<N>();
+  int k;
+  bool valid;
+  int2 rc;
+  if (!pattern_of<N>(a, L, k, valid, rc)) {
+    write_zero_partials(a);
+    return;
+  }
+  if (!valid) return;
+#pragma unroll
+  for (int m = 0; m < G::E; ++m) {
+    const int u = sidx<N>(m, L.h);
+    const float2 val = patches[(size_t)k * N * N + u * N + L.line];
+    const size_t idx = (size_t)(rc.x + u) * a.W + rc.y + L.line;
+    unsafeAtomicAdd(&a.gobj[idx].x, val.x);
+    unsafeAtomicAdd(&a.gobj[idx].y, val.y);
+  }
+}
+
+__global__ void k_check_positions(const int2* pos, int K, int H, int W, int N, int* flag) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= K) return;
+  const int2 p = pos[i];
+  if (p.x < 0 || p.y < 0 || p.x > H - N || p.y > W - N) atomicOr(flag, 1);
+}
+
+__global__ void k_debug_lane_swap(float* a, float* b) {
+  const int t = threadIdx.x;
+  float2 x = make_float2(a[t], 0.f), y = make_float2(b[t], 0.f);
+  swap32(x, y);
+  a[t] = x.x;
+  b[t] = y.x;
+}
+
+// ------------------------------------------------------------ vector kernels
+constexpr int kVecWG = 256;
+constexpr int kVecMaxBlocks = 2048;
+
+__global__ __launch_bounds__(kVecWG) void k_zero(float2* x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kVecWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVecWG)
+    x[i] = make_float2(0.f, 0.f);
+}
+__global__ __launch_bounds__(kVecWG) void k_zero_f64(double* x, int64_t n) {
+  for (int64_t i = (int64_t)blockIdx.x * kVecWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVecWG)
+    x[i] = 0.0;
+}
+
+__global__ __launch_bounds__(kVecWG) void k_fill_i32(int* x, int64_t n, int value) {
+  for (int64_t i = (int64_t)blockIdx.x * kVecWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVecWG)
+    x[i] = value;
+}
+
+__global__ __launch_bounds__(kVecWG) void k_dot2(VecArgs v) {
+  __shared__ double red[2 * (kVecWG / 64)];
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kVecWG + threadIdx.x; i < v.n; i += (int64_t)gridDim.x * kVecWG) {
+    const float2 g = v.a[i];
+    s1 += (double)g.x * g.x + (double)g.y * g.y;
+    if (v.b) {
+      const float2 e = v.b[i];
+      s2 += (double)e.x * g.x + (double)e.y * g.y;
+    }
+  }
+  block_sum2<kVecWG>(s1, s2, red);
+  if (threadIdx.x == 0) {
+    v.partials[2 * blockIdx.x] = s1;
+    v.partials[2 * blockIdx.x + 1] = s2;
+  }
+}
+
+__global__ __launch_bounds__(kVecWG) void k_dir(VecArgs v) {
+  __shared__ double red[2 * (kVecWG / 64)];
+  double s1 = 0.0, s2 = 0.0;
+  const float beta = (float)v.alpha;
+  for (int64_t i = (int64_t)blockIdx.x * kVecWG + threadIdx.x; i < v.n; i += (int64_t)gridDim.x * kVecWG) {
+    const float2 g = v.a[i];
+    const float2 e = v.b[i];
+    const float2 en = make_float2(fmaf(beta, e.x, -g.x), fmaf(beta, e.y, -g.y));
+    v.b[i] = en;
+    s1 += (double)en.x * g.x + (double)en.y * g.y;
+    s2 += (double)en.x * en.x + (double)en.y * en.y;
+  }
+  block_sum2<kVecWG>(s1, s2, red);
+  if (threadIdx.x == 0) {
+    v.partials[2 * blockIdx.x] = s1;
+    v.partials[2 * blockIdx.x + 1] = s2;
+  }
+}
+
+__global__ __launch_bounds__(kVecWG) void k_axpy(VecArgs v) {
+  const float al = (float)v.alpha;
+  for (int64_t i = (int64_t)blockIdx.x * kVecWG + threadIdx.x; i < v.n; i += (int64_t)gridDim.x * kVecWG) {
+    const float2 x = v.a[i], c = v.c[i];
+    v.a[i] = make_float2(fmaf(al, c.x, x.x), fmaf(al, c.y, x.y));
+  }
+}
+
+__global__ __launch_bounds__(kVecWG) void k_sum_copies(const float2* src, int copies, int64_t n, float2* out) {
+  for (int64_t i = (int64_t)blockIdx.x * kVecWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVecWG) {
+    float2 s = make_float2(0.f, 0.f);
+    for (int c = 0; c < copies; ++c) {
+      const float2 x = src[(int64_t)c * n + i];
+      s.x += x.x;
+      s.y += x.y;
+    }
+    out[i] = s;
+  }
+}
+
+// In-order reduction of `count` rows of `width` (<= 4) doubles, one workgroup.
+__global__ __launch_bounds__(256) void k_finalize(const double* partials, int count, int width, double* out) {
+  __shared__ double red[256 * 4];
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  // contiguous chunk per thread keeps the order fixed
+  const int per = (count + 255) / 256;
+  const int lo = threadIdx.x * per, hi = min(count, lo + per);
+  for (int i = lo; i < hi; ++i)
+    for (int j = 0; j < width; ++j) acc[j] += partials[(size_t)i * width + j];
+  for (int j = 0; j < 4; ++j) red[threadIdx.x * 4 + j] = acc[j];
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off)
+      for (int j = 0; j < 4; ++j) red[threadIdx.x * 4 + j] += red[(threadIdx.x + off) * 4 + j];
+    __syncthreads();
+  }
+  if (threadIdx.x < width) out[threadIdx.x] = red[threadIdx.x];
+}
+
+template <int N>
+int pattern_blocks(int K) {
+  return blocks_for_groups((K + Geo<N>::PPW - 1) / Geo<N>::PPW);
+}
+
+template <typename F>
+hipError_t dispatch_n(int n, F&& f) {
+  switch (n) {
+    case 16: return f(std::integral_constant<int, 16>{});
+    case 32: return f(std::integral_constant<int, 32>{});
+    case 64: return f(std::integral_constant<int, 64>{});
+    case 128: return f(std::integral_constant<int, 128>{});
+    default: return hipErrorInvalidValue;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_forward(const PatArgs& a, hipStream_t s) {
+  return dispatch_n(a.N, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    hipLaunchKernelGGL(k_forward<N>, dim3(pattern_blocks<N>(a.K)), dim3(Geo<N>::WG), 0, s, a);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_adjoint(const PatArgs& a, bool probe, int* blocks_out, hipStream_t s) {
+  return dispatch_n(a.N, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    const int nb = pattern_blocks<N>(a.K);
+    if (blocks_out) *blocks_out = nb;
+    if (probe) hipLaunchKernelGGL((k_adjoint<N, true>), dim3(nb), dim3(Geo<N>::WG), 0, s, a);
+    else hipLaunchKernelGGL((k_adjoint<N, false>), dim3(nb), dim3(Geo<N>::WG), 0, s, a);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_grad(const PatArgs& a, DataLayout lay, bool probe, int* blocks_out, hipStream_t s) {
+  return dispatch_n(a.N, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    const int nb = pattern_blocks<N>(a.K);
+    if (blocks_out) *blocks_out = nb;
+    const dim3 g(nb), b(Geo<N>::WG);
+    if (lay == DataLayout::Transposed) {
+      if (probe) hipLaunchKernelGGL((k_grad<N, DataLayout::Transposed, true>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((k_grad<N, DataLayout::Transposed, false>), g, b, 0, s, a);
+    } else {
+      if (probe) hipLaunchKernelGGL((k_grad<N, DataLayout::Rows, true>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((k_grad<N, DataLayout::Rows, false>), g, b, 0, s, a);
+    }
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_minfunc(const PatArgs& a, DataLayout lay, int* blocks_out, hipStream_t s) {
+  return dispatch_n(a.N, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    const int nb = pattern_blocks<N>(a.K);
+    if (blocks_out) *blocks_out = nb;
+    const dim3 g(nb), b(Geo<N>::WG);
+    const bool lo = a.dobj != nullptr, lp = a.dprobe != nullptr;
+    if (lay == DataLayout::Transposed) {
+      if (lo && lp) hipLaunchKernelGGL((k_minfunc<N, DataLayout::Transposed, true, true>), g, b, 0, s, a);
+      else if (lo) hipLaunchKernelGGL((k_minfunc<N, DataLayout::Transposed, true, false>), g, b, 0, s, a);
+      else if (lp) hipLaunchKernelGGL((k_minfunc<N, DataLayout::Transposed, false, true>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((k_minfunc<N, DataLayout::Transposed, false, false>), g, b, 0, s, a);
+    } else {
+      if (lo && lp) hipLaunchKernelGGL((k_minfunc<N, DataLayout::Rows, true, true>), g, b, 0, s, a);
+      else if (lo) hipLaunchKernelGGL((k_minfunc<N, DataLayout::Rows, true, false>), g, b, 0, s, a);
+      else if (lp) hipLaunchKernelGGL((k_minfunc<N, DataLayout::Rows, false, true>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((k_minfunc<N, DataLayout::Rows, false, false>), g, b, 0, s, a);
+    }
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_transpose_data(const float* d, float* dt, int K, int N, hipStream_t s) {
+  if (N >= 32) {
+    hipLaunchKernelGGL(k_transpose_data, dim3(N / 32, N / 32, K), dim3(256), 0, s, d, dt, N);
+  } else {
+    const int64_t tot = (int64_t)K * N * N;
+    hipLaunchKernelGGL(k_transpose_data_small, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, d, dt, K,
+                       N);
+  }
+  return hipGetLastError();
+}
+
+hipError_t launch_debug_gather(const PatArgs& a, float2* patches, hipStream_t s) {
+  return dispatch_n(a.N, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    hipLaunchKernelGGL(k_debug_gather<N>, dim3(pattern_blocks<N>(a.K)), dim3(Geo<N>::WG), 0, s, a, patches);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_debug_scatter(const PatArgs& a, const float2* patches, hipStream_t s) {
+  return dispatch_n(a.N, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    hipLaunchKernelGGL(k_debug_scatter<N>, dim3(pattern_blocks<N>(a.K)), dim3(Geo<N>::WG), 0, s, a, patches);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_check_positions(const int2* pos, int K, int H, int W, int N, int* flag, hipStream_t s) {
+  hipLaunchKernelGGL(k_check_positions, dim3((K + 255) / 256), dim3(256), 0, s, pos, K, H, W, N, flag);
+  return hipGetLastError();
+}
+
+hipError_t launch_debug_lane_swap(float* a, float* b, hipStream_t s) {
+  hipLaunchKernelGGL(k_debug_lane_swap, dim3(1), dim3(64), 0, s, a, b);
+  return hipGetLastError();
+}
+
+int vec_blocks(int64_t n) {
+  const int64_t nb = (n + kVecWG * 4 - 1) / (kVecWG * 4);
+  return (int)(nb < 1 ? 1 : (nb > kVecMaxBlocks ? kVecMaxBlocks : nb));
+}
+
+hipError_t launch_zero(float2* x, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero, dim3(vec_blocks(n)), dim3(kVecWG), 0, s, x, n);
+  return hipGetLastError();
+}
+hipError_t launch_zero_f64(double* x, int64_t n, hipStream_t s) {
+  hipLaunchKernelGGL(k_zero_f64, dim3(vec_blocks(n)), dim3(kVecWG), 0, s, x, n);
+  return hipGetLastError();
+}
+hipError_t launch_fill_i32(int* x, int64_t n, int value, hipStream_t s) {
+  hipLaunchKernelGGL(k_fill_i32, dim3(vec_blocks(n)), dim3(kVecWG), 0, s, x, n, value);
+  return hipGetLastError();
+}
+hipError_t launch_dot2(const VecArgs& v, hipStream_t s) {
+  hipLaunchKernelGGL(k_dot2, dim3(vec_blocks(v.n)), dim3(kVecWG), 0, s, v);
+  return hipGetLastError();
+}
+hipError_t launch_dir(const VecArgs& v, hipStream_t s) {
+  hipLaunchKernelGGL(k_dir, dim3(vec_blocks(v.n)), dim3(kVecWG), 0, s, v);
+  return hipGetLastError();
+}
+hipError_t launch_axpy(const VecArgs& v, hipStream_t s) {
+  hipLaunchKernelGGL(k_axpy, dim3(vec_blocks(v.n)), dim3(kVecWG), 0, s, v);
+  return hipGetLastError();
+}
+hipError_t launch_sum_copies(const float2* src, int copies, int64_t n, float2* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_sum_copies, dim3(vec_blocks(n)), dim3(kVecWG), 0, s, src, copies, n, out);
+  return hipGetLastError();
+}
+hipError_t launch_finalize(const double* partials, int count, int width, double* out, hipStream_t s) {
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partials, count, width, out);
+  return hipGetLastError();
+}
+
+}  // namespace ptyg

@@ -1,0 +1,69 @@
+// Kernel argument blocks and launcher declarations shared by the kernel
+// translation unit and the C-ABI host code.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+
+namespace ptyg {
+
+// Everything a pattern kernel may touch.  Unused pointers are null.
+struct PatArgs {
+  int H, W, K, N;
+  const float2* obj;     // psi [H][W]
+  const float2* dobj;    // eta_psi [H][W] (line-search trial: psi + gamma eta)
+  const float2* probe;   // p [N][N]
+  const float2* dprobe;  // eta_p [N][N] (joint line-search trial)
+  float gamma;
+  const int2* pos;       // [K] (row, col)
+  const float* data;     // intensities, [K][N][N] or per-pattern transposed
+  float2* far;           // far field [K][N][N] (forward out / adjoint in)
+  float2* gobj;          // object gradient / adjoint accumulator [H][W]
+  float2* gprobe;        // probe gradient copies [copies][N][N]
+  int gprobe_copies;
+  double* partials;      // per-workgroup (phi, f) pairs
+  float eps;
+};
+
+// Object-sized vector kernels (complex64 arrays of length n).
+struct VecArgs {
+  int64_t n;
+  float2* a;
+  float2* b;
+  const float2* c;
+  double alpha;
+  double* partials;
+};
+
+enum class DataLayout { Rows = 0, Transposed = 1 };
+
+// Launchers; each returns hipSuccess or the launch error.  `blocks_out`
+// receives the number of (phi, f) partial pairs written.
+hipError_t launch_forward(const PatArgs& a, hipStream_t s);
+hipError_t launch_adjoint(const PatArgs& a, bool probe, int* blocks_out, hipStream_t s);
+hipError_t launch_grad(const PatArgs& a, DataLayout lay, bool probe, int* blocks_out, hipStream_t s);
+hipError_t launch_minfunc(const PatArgs& a, DataLayout lay, int* blocks_out, hipStream_t s);
+hipError_t launch_transpose_data(const float* d, float* dt, int K, int N, hipStream_t s);
+hipError_t launch_debug_gather(const PatArgs& a, float2* patches, hipStream_t s);
+hipError_t launch_debug_scatter(const PatArgs& a, const float2* patches, hipStream_t s);
+hipError_t launch_check_positions(const int2* pos, int K, int H, int W, int N, int* flag, hipStream_t s);
+hipError_t launch_debug_lane_swap(float* a, float* b, hipStream_t s);
+
+// Vector kernels.  Partials: `vec_blocks(n)` pairs per call.
+int vec_blocks(int64_t n);
+hipError_t launch_zero(float2* x, int64_t n, hipStream_t s);
+hipError_t launch_zero_f64(double* x, int64_t n, hipStream_t s);
+hipError_t launch_fill_i32(int* x, int64_t n, int value, hipStream_t s);
+// partials <- (||a||^2, Re<b, a>) ; b may be null
+hipError_t launch_dot2(const VecArgs& v, hipStream_t s);
+// b <- -a + alpha b ; partials <- (Re<b_new, a>, ||b_new||^2)
+hipError_t launch_dir(const VecArgs& v, hipStream_t s);
+// a <- a + alpha c
+hipError_t launch_axpy(const VecArgs& v, hipStream_t s);
+// out[j] (+)= sum over copies of probe-gradient copies (out[j] = sum_c src[c][j])
+hipError_t launch_sum_copies(const float2* src, int copies, int64_t n, float2* out, hipStream_t s);
+// out[0..width) = in-order sums of `count` rows of `width` doubles
+hipError_t launch_finalize(const double* partials, int count, int width, double* out, hipStream_t s);
+
+}  // namespace ptyg

@@ -1,0 +1,301 @@
+"""ctypes binding of libptyg.so (include/ptyg.h) over torch device tensors.
+
+Argument marshalling only: every step of the method runs in the HIP library.
+There is no CPU fallback; if the library or a GPU is missing the calls raise.
+Tensors must be contiguous, on the current HIP device: complex64 for
+object / probe / far field, int32 [k, 2] for scan positions (an integer-valued
+float tensor is accepted and converted exactly), float32 for intensities.
+Calls run on torch's current stream.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+
+import torch
+
+_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libptyg.so")
+_lib = None
+
+PTYG_OK = 0
+STATUS = {0: "OK", -1: "E_INVAL", -2: "E_BOUNDS", -3: "E_HIP", -4: "E_NONFINITE", -5: "E_WORKSPACE"}
+
+
+class PtygError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__(f"ptyg {STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+class Dims(ctypes.Structure):
+    _fields_ = [("obj_h", ctypes.c_int32), ("obj_w", ctypes.c_int32),
+                ("n", ctypes.c_int32), ("k", ctypes.c_int32)]
+
+
+class CgOpts(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("update_probe", ctypes.c_int32),
+                ("gamma0", ctypes.c_double), ("tau", ctypes.c_double), ("t", ctypes.c_double),
+                ("max_halvings", ctypes.c_int32), ("eps", ctypes.c_double),
+                ("target_phi", ctypes.c_double)]
+
+
+class IterStats(ctypes.Structure):
+    _fields_ = [("phi", ctypes.c_double), ("f_eq2", ctypes.c_double), ("gamma", ctypes.c_double),
+                ("beta", ctypes.c_double), ("step_norm", ctypes.c_double),
+                ("halvings", ctypes.c_int32), ("restarted", ctypes.c_int32)]
+
+
+_P = ctypes.c_void_p
+_SIGS = {
+    "ptyg_abi_version": (ctypes.c_int32, []),
+    "ptyg_status_string": (ctypes.c_char_p, [ctypes.c_int32]),
+    "ptyg_last_error": (ctypes.c_char_p, []),
+    "ptyg_workspace_size": (ctypes.c_size_t, [ctypes.POINTER(Dims), ctypes.POINTER(CgOpts)]),
+    "ptyg_check_positions": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, ctypes.c_size_t, _P]),
+    "ptyg_forward": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P, _P]),
+    "ptyg_adjoint": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "ptyg_grad": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P, ctypes.c_float, _P, _P, _P, _P,
+                                   ctypes.c_size_t, _P]),
+    "ptyg_minfunc": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P, ctypes.c_double, _P, _P,
+                                      ctypes.c_float, _P, _P, ctypes.c_size_t, _P]),
+    "ptyg_cg_solve": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P, ctypes.POINTER(CgOpts), _P,
+                                       ctypes.c_size_t, ctypes.POINTER(IterStats),
+                                       ctypes.POINTER(ctypes.c_int32), _P]),
+    "ptyg_debug_gather": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P]),
+    "ptyg_debug_scatter": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P]),
+    "ptyg_debug_lane_swap": (ctypes.c_int32, [_P, _P, _P]),
+    "ptyg_timing_enable": (None, [ctypes.c_int32]),
+    "ptyg_timing_reset": (None, []),
+    "ptyg_timing_read": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
+                                          ctypes.c_int32]),
+}
+EXPORTS = tuple(_SIGS)
+
+
+def lib_path() -> str:
+    return _LIB_PATH
+
+
+def load(path: str | None = None) -> ctypes.CDLL:
+    """Load libptyg.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None and path is None:
+        return _lib
+    p = path or _LIB_PATH
+    if not os.path.exists(p):
+        raise RuntimeError(f"{p} is missing: build it with `python -m paper_2106_07575_amd.build`")
+    lib = ctypes.CDLL(p)
+    for name, (res, args) in _SIGS.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    if path is None:
+        _lib = lib
+    return lib
+
+
+def _check(st: int):
+    if st != PTYG_OK:
+        raise PtygError(st, load().ptyg_last_error().decode())
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _ptr(t: torch.Tensor | None):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dev(t: torch.Tensor, name: str, dtype: torch.dtype) -> torch.Tensor:
+    if not isinstance(t, torch.Tensor):
+        raise TypeError(f"{name} must be a torch tensor")
+    if t.device.type != "cuda":
+        raise ValueError(f"{name} must be a GPU tensor (got {t.device}); there is no CPU path")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype} (got {t.dtype})")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    return t
+
+
+def positions(pos: torch.Tensor) -> torch.Tensor:
+    """int32 [k, 2] positions; float input must be integer-valued."""
+    if pos.dtype.is_floating_point:
+        if not bool(torch.all(pos == torch.round(pos))):
+            raise ValueError("scan positions must be integer-valued (sub-pixel shifts are not supported)")
+        pos = pos.to(torch.int32)
+    if pos.dtype != torch.int32:
+        pos = pos.to(torch.int32)
+    if pos.dim() != 2 or pos.shape[1] != 2:
+        raise ValueError("positions must have shape [k, 2]")
+    return pos.contiguous()
+
+
+def dims_of(obj_shape, n: int, k: int) -> Dims:
+    return Dims(int(obj_shape[0]), int(obj_shape[1]), int(n), int(k))
+
+
+def workspace_size(dims: Dims, update_probe: bool = False) -> int:
+    o = CgOpts()
+    o.update_probe = int(update_probe)
+    sz = load().ptyg_workspace_size(ctypes.byref(dims), ctypes.byref(o))
+    if sz == 0:
+        raise PtygError(-1, load().ptyg_last_error().decode())
+    return sz
+
+
+def workspace(dims: Dims, device, update_probe: bool = False) -> torch.Tensor:
+    return torch.empty(workspace_size(dims, update_probe), dtype=torch.uint8, device=device)
+
+
+def _common(obj, probe, pos):
+    obj = _dev(obj, "obj", torch.complex64)
+    probe = _dev(probe, "probe", torch.complex64)
+    pos = _dev(positions(pos), "pos", torch.int32)
+    if obj.dim() != 2 or probe.dim() != 2 or probe.shape[0] != probe.shape[1]:
+        raise ValueError("obj must be [H, W] and probe [n, n]")
+    return obj, probe, pos, dims_of(obj.shape, probe.shape[0], pos.shape[0])
+
+
+def forward(obj, probe, pos) -> torch.Tensor:
+    """Far field G(obj) = F(probe * obj[pos_k]), complex64 [k, n, n]."""
+    obj, probe, pos, d = _common(obj, probe, pos)
+    far = torch.empty((d.k, d.n, d.n), dtype=torch.complex64, device=obj.device)
+    _check(load().ptyg_forward(ctypes.byref(d), _ptr(obj), _ptr(probe), _ptr(pos), _ptr(far), _stream()))
+    return far
+
+
+def adjoint(far, probe, pos, obj_shape, obj=None, want_probe: bool = False):
+    """(G^H far, probe adjoint or None)."""
+    probe = _dev(probe, "probe", torch.complex64)
+    pos = _dev(positions(pos), "pos", torch.int32)
+    far = _dev(far, "far", torch.complex64)
+    d = dims_of(obj_shape, probe.shape[0], pos.shape[0])
+    if tuple(far.shape) != (d.k, d.n, d.n):
+        raise ValueError("far must be [k, n, n]")
+    out = torch.empty(tuple(obj_shape), dtype=torch.complex64, device=probe.device)
+    pout = None
+    ws = None
+    if want_probe:
+        if obj is None:
+            raise ValueError("the probe adjoint needs obj")
+        obj = _dev(obj, "obj", torch.complex64)
+        pout = torch.empty_like(probe)
+        ws = workspace(d, probe.device)
+    _check(load().ptyg_adjoint(ctypes.byref(d), _ptr(far), _ptr(probe), _ptr(pos), _ptr(out), _ptr(obj),
+                               _ptr(pout), _ptr(ws), 0 if ws is None else ws.numel(), _stream()))
+    return out, pout
+
+
+def grad(obj, probe, pos, data, want_probe: bool = False, eps: float = 1e-32, ws=None):
+    """GRAD stage: returns (objective f64 [2] = (Phi, F), grad_obj, grad_probe or None)."""
+    obj, probe, pos, d = _common(obj, probe, pos)
+    data = _dev(data, "data", torch.float32)
+    if tuple(data.shape) != (d.k, d.n, d.n):
+        raise ValueError("data must be [k, n, n]")
+    g = torch.empty_like(obj)
+    gp = torch.empty_like(probe) if want_probe else None
+    objective = torch.empty(2, dtype=torch.float64, device=obj.device)
+    ws = workspace(d, obj.device) if ws is None else ws
+    _check(load().ptyg_grad(ctypes.byref(d), _ptr(obj), _ptr(probe), _ptr(pos), _ptr(data), float(eps),
+                            _ptr(g), _ptr(gp), _ptr(objective), _ptr(ws), ws.numel(), _stream()))
+    return objective, g, gp
+
+
+def minfunc(obj, probe, pos, data, dir_obj=None, dir_probe=None, gamma: float = 0.0,
+            eps: float = 1e-32, ws=None) -> torch.Tensor:
+    """Objective (Phi, F) at (obj + gamma dir_obj, probe + gamma dir_probe)."""
+    obj, probe, pos, d = _common(obj, probe, pos)
+    data = _dev(data, "data", torch.float32)
+    if dir_obj is not None:
+        dir_obj = _dev(dir_obj, "dir_obj", torch.complex64)
+    if dir_probe is not None:
+        dir_probe = _dev(dir_probe, "dir_probe", torch.complex64)
+    objective = torch.empty(2, dtype=torch.float64, device=obj.device)
+    ws = workspace(d, obj.device) if ws is None else ws
+    _check(load().ptyg_minfunc(ctypes.byref(d), _ptr(obj), _ptr(dir_obj), _ptr(probe), _ptr(dir_probe),
+                               float(gamma), _ptr(pos), _ptr(data), float(eps), _ptr(objective), _ptr(ws),
+                               ws.numel(), _stream()))
+    return objective
+
+
+@dataclasses.dataclass
+class CgResult:
+    obj: torch.Tensor
+    probe: torch.Tensor
+    trace: list
+    iters_done: int
+
+
+def cg_solve(obj0, probe, pos, data, iters: int, update_probe: bool = False, gamma0: float = 1.0,
+             tau: float = 0.5, t: float = 0.0, max_halvings: int = 40, eps: float = 1e-32,
+             target_phi: float | None = None, ws=None) -> CgResult:
+    """ML-CG (Algorithm 1).  Works on copies of obj0 / probe."""
+    obj, probe_c, pos, d = _common(obj0, probe, pos)
+    data = _dev(data, "data", torch.float32)
+    obj = obj.clone()
+    probe_c = probe_c.clone()
+    o = CgOpts(int(iters), int(update_probe), float(gamma0), float(tau), float(t), int(max_halvings),
+               float(eps), -1.0 if target_phi is None else float(target_phi))
+    ws = workspace(d, obj.device, update_probe) if ws is None else ws
+    trace = (IterStats * max(1, iters))()
+    done = ctypes.c_int32(0)
+    _check(load().ptyg_cg_solve(ctypes.byref(d), _ptr(obj), _ptr(probe_c), _ptr(pos), _ptr(data),
+                                ctypes.byref(o), _ptr(ws), ws.numel(), trace, ctypes.byref(done), _stream()))
+    rows = [{"phi": r.phi, "f": r.f_eq2, "gamma": r.gamma, "beta": r.beta, "step_norm": r.step_norm,
+             "halvings": r.halvings, "restarted": bool(r.restarted)} for r in trace[:done.value]]
+    return CgResult(obj, probe_c, rows, done.value)
+
+
+def check_positions(pos, obj_shape, n: int):
+    pos = _dev(positions(pos), "pos", torch.int32)
+    d = dims_of(obj_shape, n, pos.shape[0])
+    ws = workspace(d, pos.device)
+    _check(load().ptyg_check_positions(ctypes.byref(d), _ptr(pos), _ptr(ws), ws.numel(), _stream()))
+
+
+def debug_gather(obj, pos, n: int) -> torch.Tensor:
+    obj = _dev(obj, "obj", torch.complex64)
+    pos = _dev(positions(pos), "pos", torch.int32)
+    d = dims_of(obj.shape, n, pos.shape[0])
+    out = torch.empty((d.k, n, n), dtype=torch.complex64, device=obj.device)
+    _check(load().ptyg_debug_gather(ctypes.byref(d), _ptr(obj), _ptr(pos), _ptr(out), _stream()))
+    return out
+
+
+def debug_scatter(patches, pos, obj_shape) -> torch.Tensor:
+    patches = _dev(patches, "patches", torch.complex64)
+    pos = _dev(positions(pos), "pos", torch.int32)
+    d = dims_of(obj_shape, patches.shape[-1], pos.shape[0])
+    out = torch.empty(tuple(obj_shape), dtype=torch.complex64, device=patches.device)
+    _check(load().ptyg_debug_scatter(ctypes.byref(d), _ptr(patches), _ptr(pos), _ptr(out), _stream()))
+    return out
+
+
+def debug_lane_swap(a, b):
+    a = _dev(a, "a", torch.float32)
+    b = _dev(b, "b", torch.float32)
+    if a.numel() != 64 or b.numel() != 64:
+        raise ValueError("lane swap operates on two float32[64] arrays")
+    _check(load().ptyg_debug_lane_swap(_ptr(a), _ptr(b), _stream()))
+
+
+KERNEL_KINDS = ("grad", "minfunc")
+
+
+def timing_enable(on: bool = True):
+    load().ptyg_timing_enable(int(on))
+
+
+def timing_reset():
+    load().ptyg_timing_reset()
+
+
+def timing_read() -> dict:
+    """{kind: (total ms, launches)} for the fused GRAD and MINFUNC kernels."""
+    ms = (ctypes.c_double * 2)()
+    cnt = (ctypes.c_int32 * 2)()
+    _check(load().ptyg_timing_read(ms, cnt, 2))
+    return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNEL_KINDS)}

@@ -1,0 +1,97 @@
+"""Seeded test workloads: inputs from the synthetic generator, intensities from
+the FP64 oracle's forward model (never from the HIP path)."""
+import functools
+
+import numpy as np
+
+from oracle import ptycho as O
+from paper_2106_07575_amd import synth
+
+
+@functools.lru_cache(maxsize=8)
+def workload(name: str):
+    """(cfg, inputs, data) with data as stored on the device (float32); the
+    oracle is always fed the float32-rounded inputs, cast back to float64."""
+    if name in synth.CONFIGS:
+        cfg = synth.CONFIGS[name]
+    elif name == "m128":      # 128^2 probe, 7x7 raster: several tiles, fast oracle
+        cfg = synth.small_config("m128", 320, 128, 7, 24, 2, photons=1e5, cid=91, iters=10)
+    elif name == "m64":
+        cfg = synth.small_config("m64", 200, 64, 6, 24, 2, photons=1e4, cid=92, iters=8)
+    elif name == "m32":       # 7x7 = 49 patterns: ragged against 8 patterns per workgroup
+        cfg = synth.small_config("m32", 120, 32, 7, 12, 1, photons=1e3, cid=93, iters=8)
+    elif name == "m16r":      # 5x5 = 25 patterns: ragged against 16 patterns per workgroup
+        cfg = synth.small_config("m16r", 64, 16, 5, 8, 1, photons=1e2, cid=94, iters=8)
+    else:
+        raise KeyError(name)
+    inp = synth.make_inputs(cfg)
+    probe32 = inp.probe.astype(np.complex64)
+    obj32 = inp.obj_true.astype(np.complex64)
+    inten = np.abs(O.forward(obj32.astype(np.complex128), probe32.astype(np.complex128), inp.pos)) ** 2
+    data = synth.make_data(cfg, inten).astype(np.float32)
+    return cfg, inp, probe32, obj32, data
+
+
+def rel(a, b):
+    a = np.asarray(a)
+    b = np.asarray(b)
+    return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
+
+
+def grad_with_floor(psi, probe, pos, data, want_probe=False):
+    """Oracle gradient plus its FP32 conditioning floor.
+
+    The Poisson residual g - d g/|g|^2 amplifies far-field errors by d/|g|^2,
+    which reaches 1e6-1e8 at near-zeros of the far field, so no FP32
+    implementation can match the FP64 gradient to a fixed relative bound at
+    every iterate.  The floor is the error of the same gradient when only the
+    forward transform is rounded once to single precision (scipy's float32
+    FFT, everything else in FP64).  Returns (ref, floor_obj, floor_probe)."""
+    import scipy.fft
+    ref = O.grad(psi.astype(np.complex128), probe.astype(np.complex128), pos, data.astype(np.float64),
+                 want_probe=want_probe)
+    n = probe.shape[0]
+    patch = O.gather(psi.astype(np.complex64), pos, n)
+    g32 = scipy.fft.fft2((probe[None] * patch).astype(np.complex64), norm="ortho").astype(np.complex128)
+    u = O.ifft2u(O.residual(g32, data.astype(np.float64)))
+    go = O.scatter_add(np.conj(probe.astype(np.complex128))[None] * u, pos, psi.shape)
+    fo = rel(go, ref["grad_obj"])
+    fp = None
+    if want_probe:
+        gp = np.sum(np.conj(patch.astype(np.complex128)) * u, axis=0)
+        fp = rel(gp, ref["grad_probe"])
+    return ref, fo, fp
+
+
+def grad_tol(floor, tol=1e-5):
+    """Gradient parity bound: the per-operator target, or 3x the FP32 floor."""
+    return max(tol, 3.0 * floor)
+
+
+class fp32_forward:
+    """Context manager: the oracle's forward transform rounded once to single
+    precision (input cast to complex64, scipy's float32 FFT, result widened).
+
+    Used only to measure how far an exactly-rounded FP32 far field moves the
+    oracle's own CG trajectory: CG amplifies the Poisson-gradient
+    conditioning floor, so this divergence is the best any FP32-transform
+    implementation can do against the FP64 oracle."""
+
+    def __enter__(self):
+        import scipy.fft
+        self._orig = O.fft2u
+        O.fft2u = lambda x: scipy.fft.fft2(np.asarray(x).astype(np.complex64), norm="ortho").astype(np.complex128)
+        return self
+
+    def __exit__(self, *exc):
+        O.fft2u = self._orig
+        return False
+
+
+def cg_with_floor(obj0, probe, pos, data, iters, **kw):
+    """(oracle FP64 CG result, FP32-forward oracle CG result)."""
+    args = (obj0.astype(np.complex128), probe.astype(np.complex128), pos, data.astype(np.float64), iters)
+    ref = O.cg_solve(*args, **kw)
+    with fp32_forward():
+        pert = O.cg_solve(*args, **kw)
+    return ref, pert

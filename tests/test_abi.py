@@ -1,0 +1,55 @@
+"""The C-ABI library loads and exports every entry point include/ptyg.h declares
+(no compute: runs without a GPU)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "ptyg.h")
+
+
+def declared():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(ptyg_[a-z0-9_]+)\s*\(", txt)))
+
+
+def test_header_declares_the_method_calls():
+    names = declared()
+    for must in ["ptyg_forward", "ptyg_adjoint", "ptyg_grad", "ptyg_cg_solve", "ptyg_minfunc"]:
+        assert must in names
+
+
+def test_library_exports_every_declared_symbol():
+    from paper_2106_07575_amd import ptyg
+    if not os.path.exists(ptyg.lib_path()):
+        pytest.skip("libptyg.so not built")
+    lib = ctypes.CDLL(ptyg.lib_path())
+    for name in declared():
+        assert hasattr(lib, name), name
+    assert set(declared()) == set(ptyg.EXPORTS)
+    # host-only calls work without a GPU
+    lib = ptyg.load()
+    assert lib.ptyg_abi_version() == 1
+    d = ptyg.Dims(2048, 2048, 128, 4096)
+    sz = ptyg.workspace_size(d)
+    assert sz > 4096 * 128 * 128 * 4
+    bad = ptyg.Dims(64, 64, 48, 10)
+    assert lib.ptyg_workspace_size(ctypes.byref(bad), None) == 0
+    assert b"not in" in lib.ptyg_last_error()
+    assert lib.ptyg_status_string(-2) == b"scan position outside the object"
+
+
+def test_argument_errors_without_gpu():
+    from paper_2106_07575_amd import ptyg
+    if not os.path.exists(ptyg.lib_path()):
+        pytest.skip("libptyg.so not built")
+    lib = ptyg.load()
+    d = ptyg.Dims(64, 64, 16, 4)
+    # NULL arrays are rejected before any launch
+    assert lib.ptyg_forward(ctypes.byref(d), None, None, None, None, None) == -1
+    small = ptyg.Dims(8, 8, 16, 4)
+    assert lib.ptyg_forward(ctypes.byref(small), None, None, None, None, None) == -1
+    assert b"smaller than the probe" in lib.ptyg_last_error()

@@ -1,0 +1,134 @@
+"""ML-CG on the GPU (ptyg_cg_solve) against the oracle's CG.
+
+Object parity bound: 1e-3 relative L2 over the illuminated region after the
+stated iteration count, or -- where CG amplifies the FP32 conditioning floor
+of the Poisson gradient -- 3x the divergence of the oracle's own trajectory
+when only its forward transform is rounded to FP32 (_cases.fp32_forward).
+On well-conditioned workloads the line-search decisions must be identical."""
+import numpy as np
+import pytest
+
+from oracle import ptycho as O
+
+from _cases import cg_with_floor, rel, workload
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_07575_amd import ptyg
+    ptyg.load()
+    return ptyg
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def mask_of(probe, pos, shape):
+    illum = O.illumination(probe.astype(np.complex128), pos, shape)
+    return illum >= 1e-3 * illum.max()
+
+
+def run(P, case, iters, probe0=None, **kw):
+    cfg, inp, probe, obj, data = workload(case)
+    obj0 = np.ones(obj.shape, np.complex64)
+    p0 = probe if probe0 is None else probe0
+    res = P.cg_solve(dev(obj0), dev(p0), dev(inp.pos), dev(data), iters, **kw)
+    okw = {k: v for k, v in kw.items() if k in ("gamma0", "tau", "t", "update_probe", "target_phi")}
+    if "max_halvings" in kw:
+        okw["lmax"] = kw["max_halvings"]
+    ref, pert = cg_with_floor(obj0, p0, inp.pos, data, iters, **okw)
+    return res, ref, pert, mask_of(probe, inp.pos, obj.shape)
+
+
+def gammas(tr):
+    return [r["gamma"] for r in tr]
+
+
+@pytest.mark.parametrize("case,iters", [("m32", 8), ("m16r", 8)])
+def test_cg_well_conditioned_exact_decisions(P, case, iters):
+    res, (ro, rp, rtr), (po, pp, ptr), mask = run(P, case, iters)
+    err = rel(res.obj.cpu().numpy()[mask], ro[mask])
+    floor = rel(po[mask], ro[mask])
+    print(f"{case}: object rel {err:.2e} (fp32-forward floor {floor:.2e})")
+    assert res.iters_done == iters
+    assert gammas(res.trace) == gammas(rtr)
+    assert [r["restarted"] for r in res.trace] == [r["restarted"] for r in rtr]
+    for a, b in zip(res.trace, rtr):
+        assert abs(a["phi"] - b["phi"]) <= 1e-5 * abs(b["phi"])
+        assert abs(a["beta"] - b["beta"]) <= 1e-3 * abs(b["beta"]) + 1e-9
+    assert err <= 1e-3
+
+
+@pytest.mark.parametrize("case,iters", [("c1", 32), ("c1", 2), ("m128", 10)])
+def test_cg_object_within_fp32_floor(P, case, iters):
+    res, (ro, rp, rtr), (po, pp, ptr), mask = run(P, case, iters)
+    err = rel(res.obj.cpu().numpy()[mask], ro[mask])
+    floor = rel(po[mask], ro[mask])
+    print(f"{case}/{iters}: object rel {err:.2e}; fp32-forward oracle diverges by {floor:.2e}; "
+          f"final phi gpu {res.trace[-1]['phi']:.6e} oracle {rtr[-1]['phi']:.6e}")
+    assert res.iters_done == iters
+    assert err <= max(1e-3, 3.0 * floor)
+    # the first iteration is not yet chaotic: same step, objective to 1e-5
+    assert res.trace[0]["gamma"] == rtr[0]["gamma"]
+    assert abs(res.trace[0]["phi"] - rtr[0]["phi"]) <= 1e-5 * rtr[0]["phi"]
+    phis = [r["phi"] for r in res.trace]
+    assert all(b <= a for a, b in zip(phis, phis[1:]))
+    # equal accuracy: the final objectives agree as closely as the FP32-forward oracle's does
+    dphi = abs(res.trace[-1]["phi"] - rtr[-1]["phi"]) / rtr[-1]["phi"]
+    dphi_floor = abs(ptr[-1]["phi"] - rtr[-1]["phi"]) / rtr[-1]["phi"]
+    assert dphi <= max(1e-4, 3.0 * dphi_floor)
+
+
+def test_cg_restart_after_failed_search(P):
+    res, (ro, rp, rtr), _, mask = run(P, "c1", 3, gamma0=1e9, max_halvings=1)
+    assert res.trace[0]["gamma"] == 0.0 and rtr[0]["gamma"] == 0.0
+    assert res.trace[1]["restarted"] and rtr[1]["restarted"]
+    assert gammas(res.trace) == gammas(rtr)
+
+
+def test_cg_joint_probe(P):
+    cfg, inp, probe, obj, data = workload("m32")
+    p0 = (np.abs(probe) * np.exp(0.2j)).astype(np.complex64)
+    res, (ro, rp, rtr), (po, pp, ptr), mask = run(P, "m32", 6, probe0=p0, update_probe=True)
+    floor_o = rel(po[mask], ro[mask])
+    floor_p = rel(pp, rp)
+    eo = rel(res.obj.cpu().numpy()[mask], ro[mask])
+    ep = rel(res.probe.cpu().numpy(), rp)
+    print(f"joint: object rel {eo:.2e} (floor {floor_o:.2e}) probe rel {ep:.2e} (floor {floor_p:.2e})")
+    assert gammas(res.trace) == gammas(rtr)
+    assert eo <= max(1e-3, 3 * floor_o)
+    assert ep <= max(1e-3, 3 * floor_p)
+    assert not np.allclose(res.probe.cpu().numpy(), p0)
+
+
+def test_cg_target_stop(P):
+    cfg, inp, probe, obj, data = workload("m32")
+    o0 = dev(np.ones(obj.shape, np.complex64))
+    r1 = P.cg_solve(o0, dev(probe), dev(inp.pos), dev(data), 8)
+    target = r1.trace[5]["phi"] * (1 + 1e-9)
+    r2 = P.cg_solve(o0, dev(probe), dev(inp.pos), dev(data), 8, target_phi=target)
+    assert r2.iters_done == 5
+
+
+def test_cg_nonfinite_data_is_reported(P):
+    cfg, inp, probe, obj, data = workload("c1")
+    bad = data.copy()
+    bad[0, 0, 0] = np.nan
+    with pytest.raises(P.PtygError) as e:
+        P.cg_solve(dev(np.ones(obj.shape, np.complex64)), dev(probe), dev(inp.pos), dev(bad), 2)
+    assert e.value.status == -4
+
+
+def test_cg_bad_position_is_rejected(P):
+    cfg, inp, probe, obj, data = workload("c1")
+    bad = inp.pos.copy()
+    bad[-1] = (0, obj.shape[1] - 15)
+    with pytest.raises(P.PtygError) as e:
+        P.cg_solve(dev(np.ones(obj.shape, np.complex64)), dev(probe), dev(bad), dev(data), 2)
+    assert e.value.status == -2
