@@ -84,7 +84,7 @@ typedef struct {
 /* One row per completed iteration m of ptyg_cg_solve. */
 typedef struct {
   double phi;       /* deviance form of Eq. ML at psi_m: sum d h((x-d)/d), h(u) = u - log(1+u) */
-  double f_eq2;     /* Eq. ML at psi_m (2 d log|g| written as d log|g|^2) */
+  double f_eq2;     /* Eq. ML at psi_m (2 d log|g| written as d log|g|^2), from the GRAD pass */
   double gamma;     /* accepted step gamma_m (0 if the line search failed) */
   double beta;      /* Dai-Yuan coefficient used for eta_m (0 on a restart) */
   double step_norm; /* ||psi_{m+1} - psi_m||_2 = gamma ||eta_m|| (the paper's convergence 2-norm) */
@@ -116,12 +116,14 @@ ptyg_status ptyg_forward(const ptyg_dims* dims, const ptyg_c64* obj, const ptyg_
 /* G^H (text after Eq. gradient): obj_out = sum_k place_k(conj(probe) * F^H far[k]),
  * overwritten.  If probe_out != NULL (then obj must be given):
  * probe_out = sum_k conj(obj[pos_k]) * F^H far[k] (the adjoint of the map
- * probe -> G(obj, probe)).  Summation order over k is unspecified (FP32 atomics). */
+ * probe -> G(obj, probe)).  Every output value is summed over k in a fixed
+ * order (ascending k per object pixel), so results are bit-reproducible. */
 ptyg_status ptyg_adjoint(const ptyg_dims* dims, const ptyg_c64* far, const ptyg_c64* probe,
                          const int32_t* pos, ptyg_c64* obj_out, const ptyg_c64* obj, ptyg_c64* probe_out,
                          void* ws, size_t ws_bytes, ptyg_stream_t stream);
 
-/* GRAD stage (Eq. gradient, Wirtinger derivative dF/d conj(psi), no factor 2):
+/* GRAD stage (Eq. gradient, Wirtinger derivative dF/d conj(psi), no factor 2;
+ * bit-reproducible like ptyg_adjoint):
  * grad_obj = G^H (g - d g / |g|^2) with g = G(obj) and the residual replaced
  * by g where |g|^2 < eps.  data: float32 intensities [k][n][n].
  * grad_probe (nullable): sum_k conj(obj[pos_k]) * F^H r_k.

@@ -6,6 +6,7 @@
 #include <cstdarg>
 #include <cstdio>
 #include <cstring>
+#include <algorithm>
 #include <string>
 #include <vector>
 
@@ -35,7 +36,6 @@ ptyg_status fail(ptyg_status st, const char* fmt, ...) {
   } while (0)
 
 constexpr size_t kAlign = 256;
-constexpr int kProbeCopies = 32;  // probe-gradient accumulators (spreads atomics)
 constexpr size_t kScalars = 32;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
@@ -55,7 +55,8 @@ ptyg_status check_dims(const ptyg_dims* d) {
 
 // Workspace regions (byte offsets, each 256-byte aligned).
 struct Layout {
-  size_t partials, scalars, flag, pcopies, eta_obj, grad_obj, eta_probe, grad_probe, data_t, total;
+  size_t partials, scalars, flag, pparts, eta_obj, grad_obj, eta_probe, grad_probe, data_t, ubuf, toff, tlist,
+      total;
   size_t n_partials;
 };
 
@@ -73,8 +74,8 @@ Layout layout(const ptyg_dims* d, bool joint) {
   o = align_up(o + kScalars * sizeof(double));
   L.flag = o;
   o = align_up(o + sizeof(int));
-  L.pcopies = o;
-  o = align_up(o + (size_t)kProbeCopies * probe_n * sizeof(float2));
+  L.pparts = o;
+  o = align_up(o + (size_t)kProbeChunks * probe_n * sizeof(float2));
   L.eta_obj = o;
   o = align_up(o + obj_n * sizeof(float2));
   L.grad_obj = o;
@@ -85,6 +86,14 @@ Layout layout(const ptyg_dims* d, bool joint) {
   o = align_up(o + (joint ? probe_n : 1) * sizeof(float2));
   L.data_t = o;
   o = align_up(o + (size_t)d->k * probe_n * sizeof(float));
+  L.ubuf = o;
+  o = align_up(o + (size_t)d->k * probe_n * sizeof(float2));
+  const size_t T = (size_t)tiles_x(d->obj_w) * tiles_y(d->obj_h);
+  L.toff = o;
+  o = align_up(o + (T + 1) * sizeof(int));
+  L.tlist = o;
+  const size_t nl = std::max(T, (size_t)d->k * tiles_per_patch(d->n));
+  o = align_up(o + nl * sizeof(int));
   L.total = o;
   return L;
 }
@@ -232,31 +241,28 @@ ptyg_status ptyg_adjoint(const ptyg_dims* dims, const ptyg_c64* far, const ptyg_
   if (!far || !probe || !pos || !obj_out) return fail(PTYG_E_INVAL, "NULL array argument");
   if (probe_out && !obj) return fail(PTYG_E_INVAL, "probe_out requires obj");
   Layout L;
-  if (probe_out) {
-    if (ptyg_status st = check_ws(dims, ws, ws_bytes, false, &L)) return st;
-  }
+  if (ptyg_status st = check_ws(dims, ws, ws_bytes, false, &L)) return st;
   const hipStream_t s = S(stream);
   PatArgs a = base_args(dims);
   a.far = const_cast<float2*>(reinterpret_cast<const float2*>(far));
   a.probe = reinterpret_cast<const float2*>(probe);
   a.pos = reinterpret_cast<const int2*>(pos);
   a.obj = reinterpret_cast<const float2*>(obj);
-  a.gobj = reinterpret_cast<float2*>(obj_out);
-  const int64_t pn = (int64_t)dims->n * dims->n;
-  PTYG_HIP(launch_zero(a.gobj, (int64_t)dims->obj_h * dims->obj_w, s));
-  if (probe_out) {
-    a.gprobe = at<float2>(ws, L.pcopies);
-    a.gprobe_copies = kProbeCopies;
-    PTYG_HIP(launch_zero(a.gprobe, kProbeCopies * pn, s));
-  }
-  PTYG_HIP(launch_adjoint(a, probe_out != nullptr, nullptr, s));
+  a.ubuf = at<float2>(ws, L.ubuf);
+  PTYG_HIP(launch_tile_lists(a.pos, dims->k, dims->obj_h, dims->obj_w, dims->n, at<int>(ws, L.toff),
+                             at<int>(ws, L.tlist), s));
+  PTYG_HIP(launch_adjoint(a, s));
+  PTYG_HIP(launch_tile_sum(a.ubuf, a.probe, a.pos, at<int>(ws, L.toff), at<int>(ws, L.tlist), dims->k, dims->obj_h,
+                           dims->obj_w, dims->n, reinterpret_cast<float2*>(obj_out), s));
   if (probe_out)
-    PTYG_HIP(launch_sum_copies(a.gprobe, kProbeCopies, pn, reinterpret_cast<float2*>(probe_out), s));
+    PTYG_HIP(launch_probe_grad(a.ubuf, a.obj, a.pos, dims->k, dims->obj_w, dims->n, at<float2>(ws, L.pparts),
+                               reinterpret_cast<float2*>(probe_out), s));
   return PTYG_OK;
 }
 
 namespace {
 // One fused GRAD pass; writes {phi, f} to `objective` (device) when given.
+// The tile lists of `pos` must already be in the workspace.
 ptyg_status run_grad(const ptyg_dims* dims, const float2* obj, const float2* probe, const int2* pos,
                      const float* data, DataLayout lay, float eps, float2* grad_obj, float2* grad_probe,
                      double* objective, void* ws, const Layout& L, hipStream_t s) {
@@ -266,22 +272,25 @@ ptyg_status run_grad(const ptyg_dims* dims, const float2* obj, const float2* pro
   a.pos = pos;
   a.data = data;
   a.eps = eps;
-  a.gobj = grad_obj;
+  a.ubuf = at<float2>(ws, L.ubuf);
   a.partials = at<double>(ws, L.partials);
-  const int64_t pn = (int64_t)dims->n * dims->n;
-  PTYG_HIP(launch_zero(grad_obj, (int64_t)dims->obj_h * dims->obj_w, s));
-  if (grad_probe) {
-    a.gprobe = at<float2>(ws, L.pcopies);
-    a.gprobe_copies = kProbeCopies;
-    PTYG_HIP(launch_zero(a.gprobe, kProbeCopies * pn, s));
-  }
   int nb = 0;
   {
     TimedLaunch tl(0, s);
-    PTYG_HIP(launch_grad(a, lay, grad_probe != nullptr, &nb, s));
+    PTYG_HIP(launch_grad(a, lay, &nb, s));
   }
   if (objective) PTYG_HIP(launch_finalize(a.partials, nb, 2, objective, s));
-  if (grad_probe) PTYG_HIP(launch_sum_copies(a.gprobe, kProbeCopies, pn, grad_probe, s));
+  PTYG_HIP(launch_tile_sum(a.ubuf, probe, pos, at<int>(ws, L.toff), at<int>(ws, L.tlist), dims->k, dims->obj_h,
+                           dims->obj_w, dims->n, grad_obj, s));
+  if (grad_probe)
+    PTYG_HIP(launch_probe_grad(a.ubuf, obj, pos, dims->k, dims->obj_w, dims->n, at<float2>(ws, L.pparts),
+                               grad_probe, s));
+  return PTYG_OK;
+}
+
+ptyg_status build_tiles(const ptyg_dims* dims, const int2* pos, void* ws, const Layout& L, hipStream_t s) {
+  PTYG_HIP(launch_tile_lists(pos, dims->k, dims->obj_h, dims->obj_w, dims->n, at<int>(ws, L.toff),
+                             at<int>(ws, L.tlist), s));
   return PTYG_OK;
 }
 
@@ -316,6 +325,7 @@ ptyg_status ptyg_grad(const ptyg_dims* dims, const ptyg_c64* obj, const ptyg_c64
   if (!(eps >= 0.0f)) return fail(PTYG_E_INVAL, "eps must be >= 0");
   Layout L;
   if (ptyg_status st = check_ws(dims, ws, ws_bytes, false, &L)) return st;
+  if (ptyg_status st = build_tiles(dims, reinterpret_cast<const int2*>(pos), ws, L, S(stream))) return st;
   return run_grad(dims, reinterpret_cast<const float2*>(obj), reinterpret_cast<const float2*>(probe),
                   reinterpret_cast<const int2*>(pos), data, DataLayout::Rows, eps,
                   reinterpret_cast<float2*>(grad_obj), reinterpret_cast<float2*>(grad_probe), objective, ws, L,
@@ -371,6 +381,7 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
   // the intensities are read by every pass: store them per pattern transposed
   // so that the row-layout reads are coalesced
   PTYG_HIP(launch_transpose_data(data, dt, dims->k, dims->n, s));
+  if (ptyg_status st = build_tiles(dims, pos, ws, L, s)) return st;
 
   // scalar slots
   enum { PHI = 0, FEQ = 1, N1O = 2, N2O = 3, N1P = 4, N2P = 5, N3O = 6, EEO = 7, N3P = 8, EEP = 9, PHIT = 10 };

@@ -162,37 +162,18 @@ __device__ __forceinline__ void gather_exit_wave(float2* v, const PatArgs& a, co
   __builtin_amdgcn_sched_barrier(0);
 }
 
-// Scatter conj(p) * v onto the object accumulator; joint mode also adds
-// conj(psi patch) * v onto a probe-gradient copy.
-template <int N, bool PROBE>
-__device__ __forceinline__ void scatter_adjoint(const float2* v, const PatArgs& a, const Lane& L, int2 rc,
-                                                bool valid, int copy) {
+// Store the back-propagated wave u_k (column layout, spatial slots) of
+// every pattern; the conj(p) multiply and the overlap sum follow in
+// k_tile_sum, the probe adjoint in k_probe_partial.
+template <int N>
+__device__ __forceinline__ void store_u(const float2* v, const PatArgs& a, const Lane& L, int k, bool valid) {
   using G = Geo<N>;
   constexpr int T = G::TPC;
   if (!valid) return;
-  const uint32_t lo = lane_off<N>(L, (uint32_t)a.W);
   const uint32_t plo = lane_off<N>(L, N);
-  const size_t corner = (size_t)rc.x * a.W + rc.y;
+  float2* uk = a.ubuf + (size_t)k * N * N;
 #pragma unroll
-  for (int c = 0; c < G::E; c += kChunk) {
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int m = c; m < c + kChunk; ++m) {
-      const size_t row = corner + (size_t)(m * T) * a.W;
-      const float2 p = (a.probe + m * T * N)[plo];
-      const float2 val = cmulc(p, v[m]);
-      float2* g = (a.gobj + row) + lo;
-      unsafeAtomicAdd(&g->x, val.x);
-      unsafeAtomicAdd(&g->y, val.y);
-      if constexpr (PROBE) {
-        const float2 o = (a.obj + row)[lo];
-        const float2 pv = cmulc(o, v[m]);
-        float2* gp = (a.gprobe + (size_t)copy * N * N + m * T * N) + plo;
-        unsafeAtomicAdd(&gp->x, pv.x);
-        unsafeAtomicAdd(&gp->y, pv.y);
-      }
-    }
-  }
+  for (int m = 0; m < G::E; ++m) (uk + m * T * N)[plo] = v[m];
 }
 
 // Pattern handled by this lane.  Lanes past the last pattern (only possible
@@ -246,7 +227,7 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_forward(PatArgs a) {
   }
 }
 
-template <int N, bool PROBE>
+template <int N>
 __global__ PTYG_PATTERN_KERNEL(N) void k_adjoint(PatArgs a) {
   using G = Geo<N>;
   __shared__ float2 lds[G::LDS_ELEMS];
@@ -269,10 +250,10 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_adjoint(PatArgs a) {
   inv_line<N>(v, L.h);
   transpose_r2c<N>(v, lds, L);
   inv_line<N>(v, L.h);
-  scatter_adjoint<N, PROBE>(v, a, L, rc, valid, blockIdx.x % (a.gprobe_copies > 0 ? a.gprobe_copies : 1));
+  store_u<N>(v, a, L, k, valid);
 }
 
-template <int N, DataLayout LAY, bool PROBE>
+template <int N, DataLayout LAY>
 __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
   using G = Geo<N>;
   __shared__ float2 lds[G::LDS_ELEMS];
@@ -312,7 +293,7 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
   inv_line<N>(v, L.h);
   transpose_r2c<N>(v, lds, L);
   inv_line<N>(v, L.h);
-  scatter_adjoint<N, PROBE>(v, a, L, rc, valid, blockIdx.x % (a.gprobe_copies > 0 ? a.gprobe_copies : 1));
+  store_u<N>(v, a, L, k, valid);
   if (!valid) {
     acc_phi = 0.0;
     acc_f = 0.0;
@@ -352,9 +333,11 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_minfunc(PatArgs a) {
     const float2 g = cscale(v[s], invN);
     const float x = fmaf(g.x, g.x, g.y * g.y);
     float phi, ft, fac;
-    pixel_terms<true>(x, d, a.eps, phi, ft, fac);
+    // the solver's line search (transposed intensities) needs only Phi
+    constexpr bool WANT_F = LAY == DataLayout::Rows;
+    pixel_terms<WANT_F>(x, d, a.eps, phi, ft, fac);
     acc_phi += (double)phi;
-    acc_f += (double)ft;
+    if constexpr (WANT_F) acc_f += (double)ft;
   }
   if (!valid) {
     acc_phi = 0.0;
@@ -451,6 +434,164 @@ __global__ void k_debug_lane_swap(float* a, float* b) {
   swap32(x, y);
   a[t] = x.x;
   b[t] = y.x;
+}
+
+// ------------------------------------------------- deterministic overlap sum
+__device__ __forceinline__ bool overlaps(int2 p, int N, int y0, int x0) {
+  return p.x < y0 + kTileH && p.x + N > y0 && p.y < x0 + kTileW && p.y + N > x0;
+}
+
+// counts[t] = number of patches overlapping tile t (one workgroup per tile).
+__global__ __launch_bounds__(256) void k_tile_count(const int2* __restrict__ pos, int K, int W, int N,
+                                                     int* __restrict__ counts) {
+  __shared__ int red[4];
+  const int ntx = tiles_x(W), t = blockIdx.x;
+  const int y0 = (t / ntx) * kTileH, x0 = (t % ntx) * kTileW;
+  int c = 0;
+  for (int k = threadIdx.x; k < K; k += 256) c += overlaps(pos[k], N, y0, x0) ? 1 : 0;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) counts[t] = red[0] + red[1] + red[2] + red[3];
+}
+
+// list[offsets[t] ...] = overlapping patterns of tile t in ascending order:
+// 256 candidates per step, compacted with a ballot prefix.
+__global__ __launch_bounds__(256) void k_tile_fill(const int2* __restrict__ pos, int K, int W, int N,
+                                                    const int* __restrict__ offsets, int* __restrict__ list) {
+  __shared__ int wsum[4];
+  const int ntx = tiles_x(W), t = blockIdx.x;
+  const int y0 = (t / ntx) * kTileH, x0 = (t % ntx) * kTileW;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  int base = offsets[t];
+  for (int k0 = 0; k0 < K; k0 += 256) {
+    const int k = k0 + threadIdx.x;
+    const bool f = k < K && overlaps(pos[k], N, y0, x0);
+    const unsigned long long m = __ballot(f);
+    const int before = __popcll(m & ((1ull << l) - 1ull));
+    if (l == 0) wsum[w] = __popcll(m);
+    __syncthreads();
+    int woff = 0;
+    for (int i = 0; i < w; ++i) woff += wsum[i];
+    const int tot = wsum[0] + wsum[1] + wsum[2] + wsum[3];
+    if (f) list[base + woff + before] = k;
+    base += tot;
+    __syncthreads();
+  }
+}
+
+// Exclusive scan of counts[0..T) into offsets[0..T] (one workgroup).
+__global__ __launch_bounds__(1024) void k_scan(const int* __restrict__ counts, int T, int* __restrict__ offsets) {
+  __shared__ int part[1024];
+  const int per = (T + 1023) / 1024;
+  const int lo = threadIdx.x * per, hi = min(T, lo + per);
+  int s = 0;
+  for (int i = lo; i < hi; ++i) s += counts[i];
+  part[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int v = threadIdx.x >= off ? part[threadIdx.x - off] : 0;
+    __syncthreads();
+    part[threadIdx.x] += v;
+    __syncthreads();
+  }
+  int run = part[threadIdx.x] - s;  // exclusive prefix of this chunk
+  for (int i = lo; i < hi; ++i) {
+    offsets[i] = run;
+    run += counts[i];
+  }
+  if (threadIdx.x == 1023) offsets[T] = part[1023];
+}
+
+// grad[y][x] = sum over the tile's patterns (ascending k) of conj(p) * u_k.
+// 256 threads: lane column x = x0 + (t & 63), rows y0 + (t >> 6) + 4 i.
+// The tile's pattern list and positions are staged in LDS (kTileStage at a
+// time) so the loop issues its loads without waiting on scalar loads.
+constexpr int kTileStage = 512;
+
+template <int R>
+__device__ __forceinline__ void tile_accumulate(float2 (&acc)[R], const float2* __restrict__ U,
+                                                const float2* __restrict__ probe, int k, int2 rc, int x, int yb,
+                                                int N) {
+  const int xx = x - rc.y;
+  if ((unsigned)xx >= (unsigned)N) return;
+  const float2* uk = U + (size_t)k * N * N + xx;
+  const float2* pk = probe + xx;
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int yy = yb + 4 * i - rc.x;
+    if ((unsigned)yy < (unsigned)N) acc[i] = cadd(acc[i], cmulc(pk[yy * N], uk[yy * N]));
+  }
+}
+
+__global__ __launch_bounds__(256) void k_tile_sum(const float2* __restrict__ U, const float2* __restrict__ probe,
+                                                   const int2* __restrict__ pos, const int* __restrict__ offsets,
+                                                   const int* __restrict__ list, int H, int W, int N,
+                                                   float2* __restrict__ out) {
+  __shared__ int sk[kTileStage];
+  __shared__ int2 sp[kTileStage];
+  const int ntx = tiles_x(W);
+  const int t = blockIdx.x;
+  const int x = (t % ntx) * kTileW + (threadIdx.x & 63);
+  const int yb = (t / ntx) * kTileH + (threadIdx.x >> 6);
+  constexpr int R = kTileH / 4;
+  float2 acc[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) acc[i] = make_float2(0.f, 0.f);
+  const int beg = offsets[t], end = offsets[t + 1];
+  for (int s0 = beg; s0 < end; s0 += kTileStage) {
+    const int n = min(kTileStage, end - s0);
+    __syncthreads();
+    for (int j = threadIdx.x; j < n; j += 256) {
+      const int k = list[s0 + j];
+      sk[j] = k;
+      sp[j] = pos[k];
+    }
+    __syncthreads();
+    int j = 0;
+    for (; j + 1 < n; j += 2) {
+      tile_accumulate<R>(acc, U, probe, sk[j], sp[j], x, yb, N);
+      tile_accumulate<R>(acc, U, probe, sk[j + 1], sp[j + 1], x, yb, N);
+    }
+    if (j < n) tile_accumulate<R>(acc, U, probe, sk[j], sp[j], x, yb, N);
+  }
+  if (x < W) {
+#pragma unroll
+    for (int i = 0; i < R; ++i) {
+      const int y = yb + 4 * i;
+      if (y < H) out[(size_t)y * W + x] = acc[i];
+    }
+  }
+}
+
+// partial[c][u][v] = sum over the patterns of chunk c (ascending) of
+// conj(obj[r_k + u][c_k + v]) u_k[u][v].
+__global__ __launch_bounds__(256) void k_probe_partial(const float2* __restrict__ U, const float2* __restrict__ obj,
+                                                        const int2* __restrict__ pos, int K, int W, int N,
+                                                        float2* __restrict__ partial) {
+  const int px = blockIdx.x * 256 + threadIdx.x;
+  const int nn = N * N;
+  if (px >= nn) return;
+  const int u = px / N, v = px % N;
+  const int chunk = (K + kProbeChunks - 1) / kProbeChunks;
+  const int k0 = blockIdx.y * chunk, k1 = min(K, k0 + chunk);
+  float2 acc = make_float2(0.f, 0.f);
+  for (int k = k0; k < k1; ++k) {
+    const int2 rc = pos[k];
+    const float2 o = obj[(size_t)(rc.x + u) * W + rc.y + v];
+    acc = cadd(acc, cmulc(o, U[(size_t)k * nn + px]));
+  }
+  partial[(size_t)blockIdx.y * nn + px] = acc;
+}
+
+__global__ __launch_bounds__(256) void k_probe_reduce(const float2* __restrict__ partial, int nn,
+                                                       float2* __restrict__ out) {
+  const int px = blockIdx.x * 256 + threadIdx.x;
+  if (px >= nn) return;
+  float2 acc = make_float2(0.f, 0.f);
+  for (int c = 0; c < kProbeChunks; ++c) acc = cadd(acc, partial[(size_t)c * nn + px]);
+  out[px] = acc;
 }
 
 // ------------------------------------------------------------ vector kernels
@@ -573,30 +714,22 @@ hipError_t launch_forward(const PatArgs& a, hipStream_t s) {
   });
 }
 
-hipError_t launch_adjoint(const PatArgs& a, bool probe, int* blocks_out, hipStream_t s) {
+hipError_t launch_adjoint(const PatArgs& a, hipStream_t s) {
   return dispatch_n(a.N, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
-    const int nb = pattern_blocks<N>(a.K);
-    if (blocks_out) *blocks_out = nb;
-    if (probe) hipLaunchKernelGGL((k_adjoint<N, true>), dim3(nb), dim3(Geo<N>::WG), 0, s, a);
-    else hipLaunchKernelGGL((k_adjoint<N, false>), dim3(nb), dim3(Geo<N>::WG), 0, s, a);
+    hipLaunchKernelGGL(k_adjoint<N>, dim3(pattern_blocks<N>(a.K)), dim3(Geo<N>::WG), 0, s, a);
     return hipGetLastError();
   });
 }
 
-hipError_t launch_grad(const PatArgs& a, DataLayout lay, bool probe, int* blocks_out, hipStream_t s) {
+hipError_t launch_grad(const PatArgs& a, DataLayout lay, int* blocks_out, hipStream_t s) {
   return dispatch_n(a.N, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
     const int nb = pattern_blocks<N>(a.K);
     if (blocks_out) *blocks_out = nb;
     const dim3 g(nb), b(Geo<N>::WG);
-    if (lay == DataLayout::Transposed) {
-      if (probe) hipLaunchKernelGGL((k_grad<N, DataLayout::Transposed, true>), g, b, 0, s, a);
-      else hipLaunchKernelGGL((k_grad<N, DataLayout::Transposed, false>), g, b, 0, s, a);
-    } else {
-      if (probe) hipLaunchKernelGGL((k_grad<N, DataLayout::Rows, true>), g, b, 0, s, a);
-      else hipLaunchKernelGGL((k_grad<N, DataLayout::Rows, false>), g, b, 0, s, a);
-    }
+    if (lay == DataLayout::Transposed) hipLaunchKernelGGL((k_grad<N, DataLayout::Transposed>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_grad<N, DataLayout::Rows>), g, b, 0, s, a);
     return hipGetLastError();
   });
 }
@@ -657,6 +790,33 @@ hipError_t launch_check_positions(const int2* pos, int K, int H, int W, int N, i
 
 hipError_t launch_debug_lane_swap(float* a, float* b, hipStream_t s) {
   hipLaunchKernelGGL(k_debug_lane_swap, dim3(1), dim3(64), 0, s, a, b);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_lists(const int2* pos, int K, int H, int W, int N, int* offsets, int* list, hipStream_t s) {
+  const int T = tiles_x(W) * tiles_y(H);
+  // counts are written into list[] scratch first (list holds >= T ints)
+  int* counts = list;
+  hipLaunchKernelGGL(k_tile_count, dim3(T), dim3(256), 0, s, pos, K, W, N, counts);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, T, offsets);
+  hipLaunchKernelGGL(k_tile_fill, dim3(T), dim3(256), 0, s, pos, K, W, N, offsets, list);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_sum(const float2* ubuf, const float2* probe, const int2* pos, const int* offsets,
+                           const int* list, int K, int H, int W, int N, float2* out, hipStream_t s) {
+  (void)K;
+  const int T = tiles_x(W) * tiles_y(H);
+  hipLaunchKernelGGL(k_tile_sum, dim3(T), dim3(256), 0, s, ubuf, probe, pos, offsets, list, H, W, N, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_probe_grad(const float2* ubuf, const float2* obj, const int2* pos, int K, int W, int N,
+                             float2* partial, float2* out, hipStream_t s) {
+  const int nn = N * N;
+  hipLaunchKernelGGL(k_probe_partial, dim3((nn + 255) / 256, kProbeChunks), dim3(256), 0, s, ubuf, obj, pos, K, W,
+                     N, partial);
+  hipLaunchKernelGGL(k_probe_reduce, dim3((nn + 255) / 256), dim3(256), 0, s, partial, nn, out);
   return hipGetLastError();
 }
 

@@ -19,9 +19,8 @@ struct PatArgs {
   const int2* pos;       // [K] (row, col)
   const float* data;     // intensities, [K][N][N] or per-pattern transposed
   float2* far;           // far field [K][N][N] (forward out / adjoint in)
-  float2* gobj;          // object gradient / adjoint accumulator [H][W]
-  float2* gprobe;        // probe gradient copies [copies][N][N]
-  int gprobe_copies;
+  float2* gobj;          // accumulator of the atomic debug scatter [H][W]
+  float2* ubuf;          // per-pattern back-propagated waves u_k = F^H r_k, [K][N][N]
   double* partials;      // per-workgroup (phi, f) pairs
   float eps;
 };
@@ -41,8 +40,31 @@ enum class DataLayout { Rows = 0, Transposed = 1 };
 // Launchers; each returns hipSuccess or the launch error.  `blocks_out`
 // receives the number of (phi, f) partial pairs written.
 hipError_t launch_forward(const PatArgs& a, hipStream_t s);
-hipError_t launch_adjoint(const PatArgs& a, bool probe, int* blocks_out, hipStream_t s);
-hipError_t launch_grad(const PatArgs& a, DataLayout lay, bool probe, int* blocks_out, hipStream_t s);
+// Both write u_k = F^H (far_k or residual_k) for every pattern into a.ubuf;
+// the object and probe adjoints are then formed by launch_tile_sum and
+// launch_probe_grad (no atomics, fixed summation order).
+hipError_t launch_adjoint(const PatArgs& a, hipStream_t s);
+hipError_t launch_grad(const PatArgs& a, DataLayout lay, int* blocks_out, hipStream_t s);
+
+// Object tiles of the deterministic scatter: kTileH x kTileW pixels.
+constexpr int kTileH = 32, kTileW = 64;
+__host__ __device__ inline int tiles_x(int W) { return (W + kTileW - 1) / kTileW; }
+__host__ __device__ inline int tiles_y(int H) { return (H + kTileH - 1) / kTileH; }
+// Upper bound of tiles one n x n patch overlaps.
+inline int tiles_per_patch(int n) { return ((n - 1) / kTileH + 2) * ((n - 1) / kTileW + 2); }
+// Per-tile lists of the patterns overlapping it, in ascending pattern order:
+// offsets [T + 1], list [sum of counts] (at most K * tiles_per_patch(N)).
+hipError_t launch_tile_lists(const int2* pos, int K, int H, int W, int N, int* offsets, int* list, hipStream_t s);
+// out[y][x] = sum over the tile's patterns k (ascending) of conj(p) * u_k at
+// (y - r_k, x - c_k); every object pixel is written.
+hipError_t launch_tile_sum(const float2* ubuf, const float2* probe, const int2* pos, const int* offsets,
+                           const int* list, int K, int H, int W, int N, float2* out, hipStream_t s);
+// out[u][v] = sum_k conj(obj[r_k + u][c_k + v]) u_k[u][v], in fixed order
+// (chunks of patterns, then chunks summed in order); partial holds
+// kProbeChunks * N * N values.
+constexpr int kProbeChunks = 64;
+hipError_t launch_probe_grad(const float2* ubuf, const float2* obj, const int2* pos, int K, int W, int N,
+                             float2* partial, float2* out, hipStream_t s);
 hipError_t launch_minfunc(const PatArgs& a, DataLayout lay, int* blocks_out, hipStream_t s);
 hipError_t launch_transpose_data(const float* d, float* dt, int K, int N, hipStream_t s);
 hipError_t launch_debug_gather(const PatArgs& a, float2* patches, hipStream_t s);

@@ -177,15 +177,14 @@ def adjoint(far, probe, pos, obj_shape, obj=None, want_probe: bool = False):
         raise ValueError("far must be [k, n, n]")
     out = torch.empty(tuple(obj_shape), dtype=torch.complex64, device=probe.device)
     pout = None
-    ws = None
     if want_probe:
         if obj is None:
             raise ValueError("the probe adjoint needs obj")
         obj = _dev(obj, "obj", torch.complex64)
         pout = torch.empty_like(probe)
-        ws = workspace(d, probe.device)
+    ws = workspace(d, probe.device)
     _check(load().ptyg_adjoint(ctypes.byref(d), _ptr(far), _ptr(probe), _ptr(pos), _ptr(out), _ptr(obj),
-                               _ptr(pout), _ptr(ws), 0 if ws is None else ws.numel(), _stream()))
+                               _ptr(pout), _ptr(ws), ws.numel(), _stream()))
     return out, pout
 
 

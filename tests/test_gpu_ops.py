@@ -132,3 +132,12 @@ def test_position_check(P):
     assert e.value.status == -2
     with pytest.raises(ValueError):
         P.positions(torch.tensor([[1.5, 2.0]]))
+
+
+def test_grad_and_adjoint_are_bit_reproducible(P):
+    cfg, inp, probe, obj, data = workload("m128")
+    psi = dev(obj)
+    a = P.grad(psi, dev(probe), dev(inp.pos), dev(data), want_probe=True)
+    b = P.grad(psi, dev(probe), dev(inp.pos), dev(data), want_probe=True)
+    for x, y in zip(a, b):
+        assert torch.equal(x, y)
