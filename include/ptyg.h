@@ -30,7 +30,7 @@
  *   - Scratch comes from a caller-provided device workspace of at least
  *     ptyg_workspace_size() bytes (256-byte aligned).  The calls allocate no
  *     device memory.  Concurrent calls must not share a workspace.
- *   - Supported probe sizes n: 16, 32, 64, 128.  obj_h * obj_w * 8 bytes and
+ *   - Supported probe sizes n: 16, 32, 64, 128, 256.  obj_h * obj_w * 8 bytes and
  *     n * n * k * 8 bytes must each stay below 2^31 elements' worth of
  *     indices (objects up to 32768 x 32768).
  *   - No C++ exception crosses the ABI; the last error text of the calling
@@ -65,7 +65,7 @@ typedef void* ptyg_stream_t;
 
 typedef struct {
   int32_t obj_h, obj_w; /* object rows, columns */
-  int32_t n;            /* probe side = detector side, in {16, 32, 64, 128} */
+  int32_t n;            /* probe side = detector side, in {16, 32, 64, 128, 256} */
   int32_t k;            /* number of scan positions = diffraction patterns, >= 1 */
 } ptyg_dims;
 
@@ -109,9 +109,11 @@ ptyg_status ptyg_check_positions(const ptyg_dims* dims, const int32_t* pos, void
                                  ptyg_stream_t stream);
 
 /* Eq. fwd_model: far[k] = F(probe * obj[pos_k]) for every position.
- * obj [obj_h][obj_w], probe [n][n], pos [k][2], far [k][n][n] (written). */
+ * obj [obj_h][obj_w], probe [n][n], pos [k][2], far [k][n][n] (written).
+ * ws: workspace of ptyg_workspace_size() bytes, required for n = 256 (the
+ * transform stages through it); may be NULL for n <= 128. */
 ptyg_status ptyg_forward(const ptyg_dims* dims, const ptyg_c64* obj, const ptyg_c64* probe,
-                         const int32_t* pos, ptyg_c64* far, ptyg_stream_t stream);
+                         const int32_t* pos, ptyg_c64* far, void* ws, size_t ws_bytes, ptyg_stream_t stream);
 
 /* G^H (text after Eq. gradient): obj_out = sum_k place_k(conj(probe) * F^H far[k]),
  * overwritten.  If probe_out != NULL (then obj must be given):

@@ -40,11 +40,11 @@ constexpr size_t kScalars = 32;
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
-bool n_supported(int n) { return n == 16 || n == 32 || n == 64 || n == 128; }
+bool n_supported(int n) { return n == 16 || n == 32 || n == 64 || n == 128 || n == 256; }
 
 ptyg_status check_dims(const ptyg_dims* d) {
   if (!d) return fail(PTYG_E_INVAL, "dims is NULL");
-  if (!n_supported(d->n)) return fail(PTYG_E_INVAL, "probe size n=%d not in {16,32,64,128}", d->n);
+  if (!n_supported(d->n)) return fail(PTYG_E_INVAL, "probe size n=%d not in {16,32,64,128,256}", d->n);
   if (d->k < 1) return fail(PTYG_E_INVAL, "k=%d must be >= 1", d->k);
   if (d->obj_h < d->n || d->obj_w < d->n)
     return fail(PTYG_E_INVAL, "object %dx%d smaller than the probe %d", d->obj_h, d->obj_w, d->n);
@@ -64,9 +64,9 @@ Layout layout(const ptyg_dims* d, bool joint) {
   Layout L{};
   const size_t obj_n = (size_t)d->obj_h * d->obj_w;
   const size_t probe_n = (size_t)d->n * d->n;
-  // partial (phi, f) pairs: pattern kernels use <= 8*ceil(k/8)+8 blocks,
-  // vector kernels <= 2048
-  L.n_partials = (size_t)d->k + 16 + 4096;
+  // partial (phi, f) pairs: pattern kernels use <= k + 8 blocks, the 256^2
+  // radix stage <= 8192, vector kernels <= 2048
+  L.n_partials = std::max<size_t>((size_t)d->k + 16, 8192) + 16;
   size_t o = 0;
   L.partials = o;
   o = align_up(o + L.n_partials * 2 * sizeof(double));
@@ -222,7 +222,7 @@ ptyg_status ptyg_check_positions(const ptyg_dims* dims, const int32_t* pos, void
 }
 
 ptyg_status ptyg_forward(const ptyg_dims* dims, const ptyg_c64* obj, const ptyg_c64* probe,
-                         const int32_t* pos, ptyg_c64* far, ptyg_stream_t stream) {
+                         const int32_t* pos, ptyg_c64* far, void* ws, size_t ws_bytes, ptyg_stream_t stream) {
   if (ptyg_status st = check_dims(dims)) return st;
   if (!obj || !probe || !pos || !far) return fail(PTYG_E_INVAL, "NULL array argument");
   PatArgs a = base_args(dims);
@@ -230,6 +230,11 @@ ptyg_status ptyg_forward(const ptyg_dims* dims, const ptyg_c64* obj, const ptyg_
   a.probe = reinterpret_cast<const float2*>(probe);
   a.pos = reinterpret_cast<const int2*>(pos);
   a.far = reinterpret_cast<float2*>(far);
+  if (dims->n == 256) {
+    Layout L;
+    if (ptyg_status st = check_ws(dims, ws, ws_bytes, false, &L)) return st;
+    a.ubuf = at<float2>(ws, L.ubuf);
+  }
   PTYG_HIP(launch_forward(a, S(stream)));
   return PTYG_OK;
 }
@@ -307,6 +312,7 @@ ptyg_status run_minfunc(const ptyg_dims* dims, const float2* obj, const float2* 
   a.data = data;
   a.eps = eps;
   a.partials = at<double>(ws, L.partials);
+  a.ubuf = at<float2>(ws, L.ubuf);  // staging of the 256^2 transforms
   int nb = 0;
   {
     TimedLaunch tl(1, s);

@@ -17,6 +17,7 @@
 
 #include "kernels.hpp"
 #include "pattern.hpp"
+#include "pixel.hpp"
 
 namespace ptyg {
 
@@ -27,8 +28,6 @@ namespace {
 // the scheduler from hoisting every gather load at once.
 #define PTYG_PATTERN_KERNEL(N) \
   __launch_bounds__(Geo<N>::WG) __attribute__((amdgpu_waves_per_eu(Geo<N>::WAVES_PER_EU, Geo<N>::WAVES_PER_EU)))
-
-constexpr float kLn2 = 0.69314718055994530942f;
 
 // Block-wide sum of two doubles; the result is valid in thread 0.
 template <int WG>
@@ -53,42 +52,6 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* red) {
       b += red[2 * i + 1];
     }
   }
-}
-
-// Per-pixel objective terms and residual factor (Eqs. ML, gradient).
-//   phi   : deviance x - d - d log(max(x,eps)/d)  (x for d = 0)
-//   fterm : x - d log max(x, eps)                  (x for d = 0)
-//   fac   : 1 - d/x for x >= eps, 1 otherwise      (r = g * fac)
-// The deviance is d * h with h = delta - log(1 + delta), delta = (x-d)/d:
-// a series for |delta| < 0.1 (no cancellation near a fit), otherwise the
-// log of the ratio x/d itself (1 + delta would round to 0 for x << d).
-// A NaN intensity propagates into every term.
-template <bool WANT_F>
-__device__ __forceinline__ void pixel_terms(float x, float d, float eps, float& phi, float& fterm,
-                                            float& fac) {
-  const bool dpos = !(d <= 0.0f);  // NaN counts as positive so that it propagates
-  const bool big = x >= eps;
-  const float rd = __builtin_amdgcn_rcpf(dpos ? d : 1.0f);
-  const float xg = big ? x : eps;
-  const float delta = (xg - d) * rd;
-  // series of delta - log1p(delta)
-  float s = fmaf(-delta, 1.0f / 9.0f, 1.0f / 8.0f);
-  s = fmaf(-delta, s, 1.0f / 7.0f);
-  s = fmaf(-delta, s, 1.0f / 6.0f);
-  s = fmaf(-delta, s, 1.0f / 5.0f);
-  s = fmaf(-delta, s, 1.0f / 4.0f);
-  s = fmaf(-delta, s, 1.0f / 3.0f);
-  s = fmaf(-delta, s, 0.5f);
-  const float hser = delta * delta * s;
-  // x/d, scaled by 2^64 under the guard so that eps/d stays a normal number
-  const float lr = __log2f(xg * rd * (big ? 1.0f : 0x1p64f)) - (big ? 0.0f : 64.0f);
-  const float hlog = delta - lr * kLn2;
-  const float h = fabsf(delta) < 0.1f ? hser : hlog;
-  const float ph = d * h + (x - xg);
-  phi = dpos ? ph : x;
-  if constexpr (WANT_F) fterm = dpos ? x - d * __log2f(xg) * kLn2 : x;
-  const float rx = __builtin_amdgcn_rcpf(big ? x : 1.0f);
-  fac = (big && dpos) ? 1.0f - d * rx : 1.0f;
 }
 
 // Addressing: every global access is written as a pointer that is uniform
@@ -421,6 +384,27 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_debug_scatter(PatArgs a, const float2* 
   }
 }
 
+// Element-per-thread versions of the debug hooks (any probe size).
+__global__ void k_debug_gather_any(PatArgs a, float2* patches) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nn = (int64_t)a.N * a.N;
+  if (i >= (int64_t)a.K * nn) return;
+  const int k = (int)(i / nn), r = (int)(i % nn), u = r / a.N, v = r % a.N;
+  const int2 rc = a.pos[k];
+  patches[i] = a.obj[(size_t)(rc.x + u) * a.W + rc.y + v];
+}
+
+__global__ void k_debug_scatter_any(PatArgs a, const float2* patches) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nn = (int64_t)a.N * a.N;
+  if (i >= (int64_t)a.K * nn) return;
+  const int k = (int)(i / nn), r = (int)(i % nn), u = r / a.N, v = r % a.N;
+  const int2 rc = a.pos[k];
+  const size_t idx = (size_t)(rc.x + u) * a.W + rc.y + v;
+  unsafeAtomicAdd(&a.gobj[idx].x, patches[i].x);
+  unsafeAtomicAdd(&a.gobj[idx].y, patches[i].y);
+}
+
 __global__ void k_check_positions(const int2* pos, int K, int H, int W, int N, int* flag) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= K) return;
@@ -510,21 +494,30 @@ __global__ __launch_bounds__(1024) void k_scan(const int* __restrict__ counts, i
 // time) so the loop issues its loads without waiting on scalar loads.
 constexpr int kTileStage = 512;
 
-template <int R>
+// Offset of u_k[yy][xx] inside pattern k's block of U: natural row-major, or
+// for 256^2 patterns the polyphase layout [2 (yy&1) + (xx&1)][yy/2][xx/2].
+template <bool POLY>
+__device__ __forceinline__ int u_off(int yy, int xx, int N) {
+  if constexpr (POLY) return (((yy & 1) << 1) | (xx & 1)) * (N * N / 4) + (yy >> 1) * (N / 2) + (xx >> 1);
+  else return yy * N + xx;
+}
+
+template <int R, bool POLY>
 __device__ __forceinline__ void tile_accumulate(float2 (&acc)[R], const float2* __restrict__ U,
                                                 const float2* __restrict__ probe, int k, int2 rc, int x, int yb,
                                                 int N) {
   const int xx = x - rc.y;
   if ((unsigned)xx >= (unsigned)N) return;
-  const float2* uk = U + (size_t)k * N * N + xx;
+  const float2* uk = U + (size_t)k * N * N;
   const float2* pk = probe + xx;
 #pragma unroll
   for (int i = 0; i < R; ++i) {
     const int yy = yb + 4 * i - rc.x;
-    if ((unsigned)yy < (unsigned)N) acc[i] = cadd(acc[i], cmulc(pk[yy * N], uk[yy * N]));
+    if ((unsigned)yy < (unsigned)N) acc[i] = cadd(acc[i], cmulc(pk[yy * N], uk[u_off<POLY>(yy, xx, N)]));
   }
 }
 
+template <bool POLY>
 __global__ __launch_bounds__(256) void k_tile_sum(const float2* __restrict__ U, const float2* __restrict__ probe,
                                                    const int2* __restrict__ pos, const int* __restrict__ offsets,
                                                    const int* __restrict__ list, int H, int W, int N,
@@ -551,10 +544,10 @@ __global__ __launch_bounds__(256) void k_tile_sum(const float2* __restrict__ U, 
     __syncthreads();
     int j = 0;
     for (; j + 1 < n; j += 2) {
-      tile_accumulate<R>(acc, U, probe, sk[j], sp[j], x, yb, N);
-      tile_accumulate<R>(acc, U, probe, sk[j + 1], sp[j + 1], x, yb, N);
+      tile_accumulate<R, POLY>(acc, U, probe, sk[j], sp[j], x, yb, N);
+      tile_accumulate<R, POLY>(acc, U, probe, sk[j + 1], sp[j + 1], x, yb, N);
     }
-    if (j < n) tile_accumulate<R>(acc, U, probe, sk[j], sp[j], x, yb, N);
+    if (j < n) tile_accumulate<R, POLY>(acc, U, probe, sk[j], sp[j], x, yb, N);
   }
   if (x < W) {
 #pragma unroll
@@ -567,6 +560,7 @@ __global__ __launch_bounds__(256) void k_tile_sum(const float2* __restrict__ U, 
 
 // partial[c][u][v] = sum over the patterns of chunk c (ascending) of
 // conj(obj[r_k + u][c_k + v]) u_k[u][v].
+template <bool POLY>
 __global__ __launch_bounds__(256) void k_probe_partial(const float2* __restrict__ U, const float2* __restrict__ obj,
                                                         const int2* __restrict__ pos, int K, int W, int N,
                                                         float2* __restrict__ partial) {
@@ -580,7 +574,7 @@ __global__ __launch_bounds__(256) void k_probe_partial(const float2* __restrict_
   for (int k = k0; k < k1; ++k) {
     const int2 rc = pos[k];
     const float2 o = obj[(size_t)(rc.x + u) * W + rc.y + v];
-    acc = cadd(acc, cmulc(o, U[(size_t)k * nn + px]));
+    acc = cadd(acc, cmulc(o, U[(size_t)k * nn + u_off<POLY>(u, v, N)]));
   }
   partial[(size_t)blockIdx.y * nn + px] = acc;
 }
@@ -707,6 +701,8 @@ hipError_t dispatch_n(int n, F&& f) {
 }  // namespace
 
 hipError_t launch_forward(const PatArgs& a, hipStream_t s) {
+  if (!a.far || !a.obj || !a.probe || !a.pos) return hipErrorInvalidValue;
+  if (a.N == 256) return launch_forward256(a, s);
   return dispatch_n(a.N, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
     hipLaunchKernelGGL(k_forward<N>, dim3(pattern_blocks<N>(a.K)), dim3(Geo<N>::WG), 0, s, a);
@@ -715,6 +711,8 @@ hipError_t launch_forward(const PatArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_adjoint(const PatArgs& a, hipStream_t s) {
+  if (!a.ubuf || !a.far || !a.pos) return hipErrorInvalidValue;
+  if (a.N == 256) return launch_adjoint256(a, s);
   return dispatch_n(a.N, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
     hipLaunchKernelGGL(k_adjoint<N>, dim3(pattern_blocks<N>(a.K)), dim3(Geo<N>::WG), 0, s, a);
@@ -723,6 +721,8 @@ hipError_t launch_adjoint(const PatArgs& a, hipStream_t s) {
 }
 
 hipError_t launch_grad(const PatArgs& a, DataLayout lay, int* blocks_out, hipStream_t s) {
+  if (!a.ubuf || !a.data || !a.partials || !a.obj || !a.probe || !a.pos) return hipErrorInvalidValue;
+  if (a.N == 256) return launch_grad256(a, lay, blocks_out, s);
   return dispatch_n(a.N, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
     const int nb = pattern_blocks<N>(a.K);
@@ -735,6 +735,8 @@ hipError_t launch_grad(const PatArgs& a, DataLayout lay, int* blocks_out, hipStr
 }
 
 hipError_t launch_minfunc(const PatArgs& a, DataLayout lay, int* blocks_out, hipStream_t s) {
+  if (!a.data || !a.partials || !a.obj || !a.probe || !a.pos) return hipErrorInvalidValue;
+  if (a.N == 256) return launch_minfunc256(a, lay, blocks_out, s);
   return dispatch_n(a.N, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
     const int nb = pattern_blocks<N>(a.K);
@@ -768,6 +770,11 @@ hipError_t launch_transpose_data(const float* d, float* dt, int K, int N, hipStr
 }
 
 hipError_t launch_debug_gather(const PatArgs& a, float2* patches, hipStream_t s) {
+  if (a.N == 256) {
+    const int64_t tot = (int64_t)a.K * a.N * a.N;
+    hipLaunchKernelGGL(k_debug_gather_any, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, a, patches);
+    return hipGetLastError();
+  }
   return dispatch_n(a.N, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
     hipLaunchKernelGGL(k_debug_gather<N>, dim3(pattern_blocks<N>(a.K)), dim3(Geo<N>::WG), 0, s, a, patches);
@@ -776,6 +783,11 @@ hipError_t launch_debug_gather(const PatArgs& a, float2* patches, hipStream_t s)
 }
 
 hipError_t launch_debug_scatter(const PatArgs& a, const float2* patches, hipStream_t s) {
+  if (a.N == 256) {
+    const int64_t tot = (int64_t)a.K * a.N * a.N;
+    hipLaunchKernelGGL(k_debug_scatter_any, dim3((unsigned)((tot + 255) / 256)), dim3(256), 0, s, a, patches);
+    return hipGetLastError();
+  }
   return dispatch_n(a.N, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
     hipLaunchKernelGGL(k_debug_scatter<N>, dim3(pattern_blocks<N>(a.K)), dim3(Geo<N>::WG), 0, s, a, patches);
@@ -807,15 +819,22 @@ hipError_t launch_tile_sum(const float2* ubuf, const float2* probe, const int2* 
                            const int* list, int K, int H, int W, int N, float2* out, hipStream_t s) {
   (void)K;
   const int T = tiles_x(W) * tiles_y(H);
-  hipLaunchKernelGGL(k_tile_sum, dim3(T), dim3(256), 0, s, ubuf, probe, pos, offsets, list, H, W, N, out);
+  if (N == 256)
+    hipLaunchKernelGGL(k_tile_sum<true>, dim3(T), dim3(256), 0, s, ubuf, probe, pos, offsets, list, H, W, N, out);
+  else
+    hipLaunchKernelGGL(k_tile_sum<false>, dim3(T), dim3(256), 0, s, ubuf, probe, pos, offsets, list, H, W, N, out);
   return hipGetLastError();
 }
 
 hipError_t launch_probe_grad(const float2* ubuf, const float2* obj, const int2* pos, int K, int W, int N,
                              float2* partial, float2* out, hipStream_t s) {
   const int nn = N * N;
-  hipLaunchKernelGGL(k_probe_partial, dim3((nn + 255) / 256, kProbeChunks), dim3(256), 0, s, ubuf, obj, pos, K, W,
-                     N, partial);
+  if (N == 256)
+    hipLaunchKernelGGL(k_probe_partial<true>, dim3((nn + 255) / 256, kProbeChunks), dim3(256), 0, s, ubuf, obj, pos,
+                       K, W, N, partial);
+  else
+    hipLaunchKernelGGL(k_probe_partial<false>, dim3((nn + 255) / 256, kProbeChunks), dim3(256), 0, s, ubuf, obj, pos,
+                       K, W, N, partial);
   hipLaunchKernelGGL(k_probe_reduce, dim3((nn + 255) / 256), dim3(256), 0, s, partial, nn, out);
   return hipGetLastError();
 }

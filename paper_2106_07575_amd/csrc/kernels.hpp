@@ -46,6 +46,13 @@ hipError_t launch_forward(const PatArgs& a, hipStream_t s);
 hipError_t launch_adjoint(const PatArgs& a, hipStream_t s);
 hipError_t launch_grad(const PatArgs& a, DataLayout lay, int* blocks_out, hipStream_t s);
 
+// 256^2 patterns (kernels256.hip): four polyphase 128^2 sub-transforms and
+// a pointwise radix stage; u_k is left in the polyphase layout.
+hipError_t launch_forward256(const PatArgs& a, hipStream_t s);
+hipError_t launch_adjoint256(const PatArgs& a, hipStream_t s);
+hipError_t launch_grad256(const PatArgs& a, DataLayout lay, int* blocks_out, hipStream_t s);
+hipError_t launch_minfunc256(const PatArgs& a, DataLayout lay, int* blocks_out, hipStream_t s);
+
 // Object tiles of the deterministic scatter: kTileH x kTileW pixels.
 constexpr int kTileH = 32, kTileW = 64;
 __host__ __device__ inline int tiles_x(int W) { return (W + kTileW - 1) / kTileW; }

@@ -1,0 +1,280 @@
+// 256 x 256 patterns (the large one-GPU share: 8192^2 object, 256^2 probe).
+//
+// A 256^2 pattern (512 KiB) fits neither in LDS nor in one workgroup's
+// registers, so its 2-D DFT is split by decimation in both axes into four
+// 128^2 polyphase sub-transforms, Y_pq = DFT128(x[2u'+p][2v'+q]), p, q in
+// {0, 1}, each run by the 128^2 register/LDS pipeline, followed by a
+// pointwise 2x2 radix stage
+//   X[a + 128 al][b + 128 be] = sum_pq (-1)^(al p + be q) W256^(a p + b q) Y_pq[a][b].
+// The GRAD pass is three kernels sharing one per-pattern buffer U:
+//   k_sub_fwd    gather (stride 2) * probe -> Y_pq (per sub-grid transposed)
+//   k_combine    radix stage -> Poisson residual + objective (FP64) ->
+//                adjoint radix stage (1/256 folded in) -> R_pq, in place
+//   k_sub_inv    inverse sub-transforms -> u_pq, in place (polyphase layout)
+// after which k_tile_sum / k_probe_partial form G^H with the polyphase
+// index map.  A line-search trial is k_sub_fwd (psi + gamma eta) followed by
+// the objective-only combine.
+#include <hip/hip_runtime.h>
+
+#include "kernels.hpp"
+#include "pattern.hpp"
+#include "pixel.hpp"
+
+namespace ptyg {
+namespace {
+
+constexpr int NS = 128;                 // sub-transform size
+constexpr int NB = 256;                 // pattern size
+constexpr int SUB = NS * NS;            // elements per sub-grid
+using G = Geo<NS>;
+
+#define PTYG_SUB_KERNEL __launch_bounds__(G::WG) __attribute__((amdgpu_waves_per_eu(G::WAVES_PER_EU, G::WAVES_PER_EU)))
+
+// W256^e, e in [0, 256)
+__device__ __forceinline__ float2 w256(int e, int sign) {
+  return make_float2(kTwCosDev[e & 255], sign * kTwSinDev[e & 255]);
+}
+
+// Gather the (p, q) sub-grid of (p + gamma dp) * (psi + gamma eta) patch k.
+template <bool LINC_O, bool LINC_P>
+__device__ __forceinline__ void gather_sub(float2* v, const PatArgs& a, const Lane& L, int2 rc, int p, int q) {
+  // slot m -> sub-row u' = 2m + h, sub-col v' = line -> patch (2u' + p, 2v' + q)
+  const uint32_t lo = (L.h ? 2u * (uint32_t)a.W : 0u) + 2u * (uint32_t)L.line;
+  const size_t corner = (size_t)(rc.x + p) * a.W + rc.y + q;
+#pragma unroll
+  for (int c = 0; c < G::E; c += 16) {
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int m = c; m < c + 16; ++m) {
+      const size_t row = corner + (size_t)(4 * m) * a.W;
+      float2 o = (a.obj + row)[lo];
+      if constexpr (LINC_O) {
+        const float2 e = (a.dobj + row)[lo];
+        o = make_float2(fmaf(a.gamma, e.x, o.x), fmaf(a.gamma, e.y, o.y));
+      }
+      v[m] = o;
+    }
+  }
+  const uint32_t plo = (L.h ? 2u * NB : 0u) + 2u * (uint32_t)L.line;
+  const float2* pb = a.probe + p * NB + q;
+  const float2* dpb = LINC_P ? a.dprobe + p * NB + q : nullptr;
+#pragma unroll
+  for (int c = 0; c < G::E; c += 8) {
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int m = c; m < c + 8; ++m) {
+      float2 pr = (pb + 4 * m * NB)[plo];
+      if constexpr (LINC_P) {
+        const float2 dp = (dpb + 4 * m * NB)[plo];
+        pr = make_float2(fmaf(a.gamma, dp.x, pr.x), fmaf(a.gamma, dp.y, pr.y));
+      }
+      v[m] = cmul(pr, v[m]);
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// U layout per pattern: [pq][b][a] for Y / R (transposed sub-grids, coalesced
+// for the row layout), [pq][u'][v'] for u (natural sub-grids).
+template <bool LINC_O, bool LINC_P>
+__global__ PTYG_SUB_KERNEL void k_sub_fwd(PatArgs a) {
+  __shared__ float2 lds[G::LDS_ELEMS];
+  const int blk = blockIdx.x;
+  const int k = blk >> 2, pq = blk & 3, p = pq >> 1, q = pq & 1;
+  if (k >= a.K) return;
+  const Lane L = lane_info<NS>();
+  const int2 rc = a.pos[k];
+  float2 v[G::E];
+  gather_sub<LINC_O, LINC_P>(v, a, L, rc, p, q);
+  fwd_line<NS>(v, L.h);
+  transpose_c2r<NS>(v, lds, L);
+  fwd_line<NS>(v, L.h);
+  float2* y = a.ubuf + (size_t)k * NB * NB + (size_t)pq * SUB;
+  const uint32_t lo = (L.h ? (uint32_t)(G::E / 2) * NS : 0u) + (uint32_t)L.line;
+#pragma unroll
+  for (int s = 0; s < G::E; ++s) (y + (size_t)kFreq<NS>.f[s] * NS)[lo] = v[s];
+}
+
+__global__ PTYG_SUB_KERNEL void k_sub_inv(PatArgs a) {
+  __shared__ float2 lds[G::LDS_ELEMS];
+  const int blk = blockIdx.x;
+  const int k = blk >> 2, pq = blk & 3;
+  if (k >= a.K) return;
+  const Lane L = lane_info<NS>();
+  float2 v[G::E];
+  float2* y = a.ubuf + (size_t)k * NB * NB + (size_t)pq * SUB;
+  const uint32_t lo = (L.h ? (uint32_t)(G::E / 2) * NS : 0u) + (uint32_t)L.line;
+#pragma unroll
+  for (int s = 0; s < G::E; ++s) v[s] = (y + (size_t)kFreq<NS>.f[s] * NS)[lo];
+  inv_line<NS>(v, L.h);
+  transpose_r2c<NS>(v, lds, L);
+  inv_line<NS>(v, L.h);
+  // every lane of the workgroup has read its R values (the transposes hold
+  // barriers), so the sub-grid can be overwritten in place
+  const uint32_t plo = (L.h ? (uint32_t)NS : 0u) + (uint32_t)L.line;
+#pragma unroll
+  for (int m = 0; m < G::E; ++m) (y + 2 * m * NS)[plo] = v[m];
+}
+
+// Pointwise radix-2x2 stage.  Thread item i: a = i & 127, b = (i >> 7) & 127,
+// k = i >> 14.  MODE 0: forward only (writes far, unitary).  MODE 1: GRAD
+// (objective partials, residual adjoint written back as R).  MODE 2:
+// objective only.  MODE 3: adjoint of a given far field (writes R).
+template <int MODE, DataLayout LAY>
+__global__ __launch_bounds__(256) void k_combine(PatArgs a, int64_t items) {
+  __shared__ double red[8];
+  double acc_phi = 0.0, acc_f = 0.0;
+  const float inv = 1.0f / NB;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < items; i += (int64_t)gridDim.x * 256) {
+    const int ai = (int)(i & 127), bi = (int)((i >> 7) & 127);
+    const int64_t k = i >> 14;
+    float2* y = a.ubuf + (size_t)k * NB * NB + (size_t)bi * NS + ai;
+    float2 g[4];  // index al * 2 + be
+    if constexpr (MODE != 3) {
+      const float2 y00 = y[0], y01 = y[SUB], y10 = y[2 * SUB], y11 = y[3 * SUB];
+      const float2 t00 = y00;
+      const float2 t01 = cmul(w256(bi, -1), y01);
+      const float2 t10 = cmul(w256(ai, -1), y10);
+      const float2 t11 = cmul(w256(ai + bi, -1), y11);
+      const float2 s0 = cadd(t00, t10), s1 = csub(t00, t10);  // al = 0 / 1 over p
+      const float2 e0 = cadd(t01, t11), e1 = csub(t01, t11);
+      g[0] = cscale(cadd(s0, e0), inv);  // al 0 be 0
+      g[1] = cscale(csub(s0, e0), inv);  // al 0 be 1
+      g[2] = cscale(cadd(s1, e1), inv);  // al 1 be 0
+      g[3] = cscale(csub(s1, e1), inv);  // al 1 be 1
+    }
+    if constexpr (MODE == 0) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int A = ai + 128 * (j >> 1), B = bi + 128 * (j & 1);
+        a.far[(size_t)k * NB * NB + (size_t)A * NB + B] = g[j];
+      }
+      continue;
+    }
+    float2 r[4];
+    if constexpr (MODE == 3) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int A = ai + 128 * (j >> 1), B = bi + 128 * (j & 1);
+        r[j] = a.far[(size_t)k * NB * NB + (size_t)A * NB + B];
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int A = ai + 128 * (j >> 1), B = bi + 128 * (j & 1);
+        const float d = (LAY == DataLayout::Transposed) ? a.data[(size_t)k * NB * NB + (size_t)B * NB + A]
+                                                        : a.data[(size_t)k * NB * NB + (size_t)A * NB + B];
+        const float x = fmaf(g[j].x, g[j].x, g[j].y * g[j].y);
+        float phi, ft, fac;
+        pixel_terms<MODE == 1 || LAY == DataLayout::Rows>(x, d, a.eps, phi, ft, fac);
+        acc_phi += (double)phi;
+        if constexpr (MODE == 1 || LAY == DataLayout::Rows) acc_f += (double)ft;
+        r[j] = cscale(g[j], fac);
+      }
+    }
+    if constexpr (MODE == 1 || MODE == 3) {
+      // adjoint radix stage: R_pq = conj(W^(ap+bq)) sum (-1)^(al p + be q) r / 256
+      const float2 s0 = cadd(r[0], r[2]), s1 = csub(r[0], r[2]);  // over al
+      const float2 u0 = cadd(r[1], r[3]), u1 = csub(r[1], r[3]);
+      const float2 r00 = cadd(s0, u0);        // p 0 q 0
+      const float2 r01 = csub(s0, u0);        // p 0 q 1
+      const float2 r10 = cadd(s1, u1);        // p 1 q 0
+      const float2 r11 = csub(s1, u1);        // p 1 q 1
+      y[0] = cscale(r00, inv);
+      y[SUB] = cscale(cmul(w256(bi, +1), r01), inv);
+      y[2 * SUB] = cscale(cmul(w256(ai, +1), r10), inv);
+      y[3 * SUB] = cscale(cmul(w256(ai + bi, +1), r11), inv);
+    }
+  }
+  if constexpr (MODE == 1 || MODE == 2) {
+    asm volatile("" : "+v"(acc_phi), "+v"(acc_f));
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      acc_phi += __shfl_xor(acc_phi, off);
+      acc_f += __shfl_xor(acc_f, off);
+    }
+    if ((threadIdx.x & 63) == 0) {
+      red[2 * (threadIdx.x >> 6)] = acc_phi;
+      red[2 * (threadIdx.x >> 6) + 1] = acc_f;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      a.partials[2 * blockIdx.x] = red[0] + red[2] + red[4] + red[6];
+      a.partials[2 * blockIdx.x + 1] = red[1] + red[3] + red[5] + red[7];
+    }
+  }
+}
+
+constexpr int kCombineBlocks = 8192;
+
+int combine_blocks(int K) {
+  const int64_t items = (int64_t)K * SUB;
+  const int64_t nb = (items + 255) / 256;
+  return (int)(nb < kCombineBlocks ? nb : kCombineBlocks);
+}
+
+template <int MODE>
+hipError_t combine(const PatArgs& a, DataLayout lay, int* blocks_out, hipStream_t s) {
+  const int nb = combine_blocks(a.K);
+  const int64_t items = (int64_t)a.K * SUB;
+  if (blocks_out) *blocks_out = nb;
+  if (lay == DataLayout::Transposed)
+    hipLaunchKernelGGL((k_combine<MODE, DataLayout::Transposed>), dim3(nb), dim3(256), 0, s, a, items);
+  else
+    hipLaunchKernelGGL((k_combine<MODE, DataLayout::Rows>), dim3(nb), dim3(256), 0, s, a, items);
+  return hipGetLastError();
+}
+
+hipError_t sub_fwd(const PatArgs& a, hipStream_t s) {
+  const dim3 g(4 * a.K), b(G::WG);
+  const bool lo = a.dobj != nullptr, lp = a.dprobe != nullptr;
+  if (lo && lp) hipLaunchKernelGGL((k_sub_fwd<true, true>), g, b, 0, s, a);
+  else if (lo) hipLaunchKernelGGL((k_sub_fwd<true, false>), g, b, 0, s, a);
+  else if (lp) hipLaunchKernelGGL((k_sub_fwd<false, true>), g, b, 0, s, a);
+  else hipLaunchKernelGGL((k_sub_fwd<false, false>), g, b, 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t sub_inv(const PatArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(k_sub_inv, dim3(4 * a.K), dim3(G::WG), 0, s, a);
+  return hipGetLastError();
+}
+
+}  // namespace
+
+// Every 256^2 launcher stages through a.ubuf (and the forward writes
+// a.far): refuse null buffers on the host instead of launching.
+bool staged_ok(const PatArgs& a) { return a.ubuf != nullptr && a.pos != nullptr; }
+
+hipError_t launch_forward256(const PatArgs& a, hipStream_t s) {
+  if (!staged_ok(a) || !a.far || !a.obj || !a.probe) return hipErrorInvalidValue;
+  PatArgs b = a;
+  b.dobj = nullptr;
+  b.dprobe = nullptr;
+  if (hipError_t e = sub_fwd(b, s)) return e;
+  return combine<0>(b, DataLayout::Rows, nullptr, s);
+}
+
+hipError_t launch_adjoint256(const PatArgs& a, hipStream_t s) {
+  if (!staged_ok(a) || !a.far) return hipErrorInvalidValue;
+  if (hipError_t e = combine<3>(a, DataLayout::Rows, nullptr, s)) return e;
+  return sub_inv(a, s);
+}
+
+hipError_t launch_grad256(const PatArgs& a, DataLayout lay, int* blocks_out, hipStream_t s) {
+  if (!staged_ok(a) || !a.data || !a.partials || !a.obj || !a.probe) return hipErrorInvalidValue;
+  PatArgs b = a;
+  b.dobj = nullptr;
+  b.dprobe = nullptr;
+  if (hipError_t e = sub_fwd(b, s)) return e;
+  if (hipError_t e = combine<1>(b, lay, blocks_out, s)) return e;
+  return sub_inv(b, s);
+}
+
+hipError_t launch_minfunc256(const PatArgs& a, DataLayout lay, int* blocks_out, hipStream_t s) {
+  if (!staged_ok(a) || !a.data || !a.partials || !a.obj || !a.probe) return hipErrorInvalidValue;
+  if (hipError_t e = sub_fwd(a, s)) return e;
+  return combine<2>(a, lay, blocks_out, s);
+}
+
+}  // namespace ptyg

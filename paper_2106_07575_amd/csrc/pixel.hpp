@@ -1,0 +1,52 @@
+// Per-pixel Poisson objective terms (Eqs. ML, gradient) and the device
+// twiddle tables shared by the pattern kernels.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "twiddles.h"
+
+namespace ptyg {
+
+constexpr float kLn2 = 0.69314718055994530942f;
+
+// cos / sin (2 pi e / 256) for run-time indices
+static __device__ const float kTwCosDev[kTwM] = PTYG_TW_COS;
+static __device__ const float kTwSinDev[kTwM] = PTYG_TW_SIN;
+
+// Per-pixel objective terms and residual factor (Eqs. ML, gradient).
+//   phi   : deviance x - d - d log(max(x,eps)/d)  (x for d = 0)
+//   fterm : x - d log max(x, eps)                  (x for d = 0)
+//   fac   : 1 - d/x for x >= eps, 1 otherwise      (r = g * fac)
+// The deviance is d * h with h = delta - log(1 + delta), delta = (x-d)/d:
+// a series for |delta| < 0.1 (no cancellation near a fit), otherwise the
+// log of the ratio x/d itself (1 + delta would round to 0 for x << d).
+// A NaN intensity propagates into every term.
+template <bool WANT_F>
+__device__ __forceinline__ void pixel_terms(float x, float d, float eps, float& phi, float& fterm,
+                                            float& fac) {
+  const bool dpos = !(d <= 0.0f);  // NaN counts as positive so that it propagates
+  const bool big = x >= eps;
+  const float rd = __builtin_amdgcn_rcpf(dpos ? d : 1.0f);
+  const float xg = big ? x : eps;
+  const float delta = (xg - d) * rd;
+  // series of delta - log1p(delta)
+  float s = fmaf(-delta, 1.0f / 9.0f, 1.0f / 8.0f);
+  s = fmaf(-delta, s, 1.0f / 7.0f);
+  s = fmaf(-delta, s, 1.0f / 6.0f);
+  s = fmaf(-delta, s, 1.0f / 5.0f);
+  s = fmaf(-delta, s, 1.0f / 4.0f);
+  s = fmaf(-delta, s, 1.0f / 3.0f);
+  s = fmaf(-delta, s, 0.5f);
+  const float hser = delta * delta * s;
+  // x/d, scaled by 2^64 under the guard so that eps/d stays a normal number
+  const float lr = __log2f(xg * rd * (big ? 1.0f : 0x1p64f)) - (big ? 0.0f : 64.0f);
+  const float hlog = delta - lr * kLn2;
+  const float h = fabsf(delta) < 0.1f ? hser : hlog;
+  const float ph = d * h + (x - xg);
+  phi = dpos ? ph : x;
+  if constexpr (WANT_F) fterm = dpos ? x - d * __log2f(xg) * kLn2 : x;
+  const float rx = __builtin_amdgcn_rcpf(big ? x : 1.0f);
+  fac = (big && dpos) ? 1.0f - d * rx : 1.0f;
+}
+
+}  // namespace ptyg

@@ -53,7 +53,7 @@ _SIGS = {
     "ptyg_last_error": (ctypes.c_char_p, []),
     "ptyg_workspace_size": (ctypes.c_size_t, [ctypes.POINTER(Dims), ctypes.POINTER(CgOpts)]),
     "ptyg_check_positions": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, ctypes.c_size_t, _P]),
-    "ptyg_forward": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P, _P]),
+    "ptyg_forward": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "ptyg_adjoint": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "ptyg_grad": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P, ctypes.c_float, _P, _P, _P, _P,
                                    ctypes.c_size_t, _P]),
@@ -163,7 +163,9 @@ def forward(obj, probe, pos) -> torch.Tensor:
     """Far field G(obj) = F(probe * obj[pos_k]), complex64 [k, n, n]."""
     obj, probe, pos, d = _common(obj, probe, pos)
     far = torch.empty((d.k, d.n, d.n), dtype=torch.complex64, device=obj.device)
-    _check(load().ptyg_forward(ctypes.byref(d), _ptr(obj), _ptr(probe), _ptr(pos), _ptr(far), _stream()))
+    ws = workspace(d, obj.device) if d.n == 256 else None
+    _check(load().ptyg_forward(ctypes.byref(d), _ptr(obj), _ptr(probe), _ptr(pos), _ptr(far), _ptr(ws),
+                               0 if ws is None else ws.numel(), _stream()))
     return far
 
 

@@ -20,6 +20,8 @@ def workload(name: str):
         cfg = synth.small_config("m64", 200, 64, 6, 24, 2, photons=1e4, cid=92, iters=8)
     elif name == "m32":       # 7x7 = 49 patterns: ragged against 8 patterns per workgroup
         cfg = synth.small_config("m32", 120, 32, 7, 12, 1, photons=1e3, cid=93, iters=8)
+    elif name == "m256":      # 256^2 probe (polyphase path), 4x4 raster step 48 +-3
+        cfg = synth.small_config("m256", 480, 256, 4, 48, 3, photons=1e6, cid=95, iters=4)
     elif name == "m16r":      # 5x5 = 25 patterns: ragged against 16 patterns per workgroup
         cfg = synth.small_config("m16r", 64, 16, 5, 8, 1, photons=1e2, cid=94, iters=8)
     else:

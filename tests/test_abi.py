@@ -49,7 +49,7 @@ def test_argument_errors_without_gpu():
     lib = ptyg.load()
     d = ptyg.Dims(64, 64, 16, 4)
     # NULL arrays are rejected before any launch
-    assert lib.ptyg_forward(ctypes.byref(d), None, None, None, None, None) == -1
+    assert lib.ptyg_forward(ctypes.byref(d), None, None, None, None, None, 0, None) == -1
     small = ptyg.Dims(8, 8, 16, 4)
-    assert lib.ptyg_forward(ctypes.byref(small), None, None, None, None, None) == -1
+    assert lib.ptyg_forward(ctypes.byref(small), None, None, None, None, None, 0, None) == -1
     assert b"smaller than the probe" in lib.ptyg_last_error()

@@ -65,7 +65,7 @@ def test_cg_well_conditioned_exact_decisions(P, case, iters):
     assert err <= 1e-3
 
 
-@pytest.mark.parametrize("case,iters", [("c1", 32), ("c1", 2), ("m128", 10)])
+@pytest.mark.parametrize("case,iters", [("c1", 32), ("c1", 2), ("m128", 10), ("m256", 4)])
 def test_cg_object_within_fp32_floor(P, case, iters):
     res, (ro, rp, rtr), (po, pp, ptr), mask = run(P, case, iters)
     err = rel(res.obj.cpu().numpy()[mask], ro[mask])
@@ -148,3 +148,20 @@ def test_cg_is_bit_reproducible(P):
     r2 = P.cg_solve(o0, dev(probe), dev(inp.pos), dev(data), 4)
     assert torch.equal(r1.obj, r2.obj)
     assert r1.trace == r2.trace
+
+
+def test_cg_joint_probe_256(P):
+    # joint mode on the polyphase 256^2 path from a probe with 5% amplitude
+    # errors (a start from |p| alone puts the first line search on a knife
+    # edge: FP64 and FP32-rounded transforms pick 2^-22 vs 2^-20)
+    cfg, inp, probe, obj, data = workload("m256")
+    rng = np.random.default_rng(3)
+    p0 = (probe * (1 + 0.05 * rng.standard_normal(probe.shape))).astype(np.complex64)
+    res, (ro, rp, rtr), (po, pp, ptr), mask = run(P, "m256", 3, probe0=p0, update_probe=True)
+    eo = rel(res.obj.cpu().numpy()[mask], ro[mask])
+    ep = rel(res.probe.cpu().numpy(), rp)
+    fo, fp = rel(po[mask], ro[mask]), rel(pp, rp)
+    print(f"joint 256: object rel {eo:.2e} (floor {fo:.2e}) probe rel {ep:.2e} (floor {fp:.2e})")
+    assert gammas(res.trace) == gammas(rtr)
+    assert eo <= max(1e-3, FLOOR_FACTOR * fo)
+    assert ep <= max(1e-3, FLOOR_FACTOR * fp)

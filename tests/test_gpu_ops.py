@@ -15,7 +15,7 @@ pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
 
 TOL = 1e-5
-CASES = ["c1", "m16r", "m32", "m64", "m128"]
+CASES = ["c1", "m16r", "m32", "m64", "m128", "m256"]
 
 
 @pytest.fixture(scope="module")
@@ -40,7 +40,8 @@ def test_lane_swap_layout(P):
     assert np.array_equal(b[:32], 32 + np.arange(32)) and np.array_equal(b[32:], 100 + 32 + np.arange(32))
 
 
-@pytest.mark.parametrize("n,h,w,k", [(16, 40, 57, 13), (32, 90, 70, 9), (64, 130, 100, 5), (128, 300, 260, 11)])
+@pytest.mark.parametrize("n,h,w,k", [(16, 40, 57, 13), (32, 90, 70, 9), (64, 130, 100, 5), (128, 300, 260, 11),
+                                     (256, 400, 300, 3)])
 def test_gather_scatter_bit_exact(P, n, h, w, k):
     rng = np.random.default_rng(n)
     pos = np.stack([rng.integers(0, h - n + 1, k), rng.integers(0, w - n + 1, k)], 1).astype(np.int32)
@@ -77,7 +78,7 @@ def test_forward_adjoint_parity(P, case):
     assert abs(lhs - rhs) <= TOL * abs(lhs)
 
 
-@pytest.mark.parametrize("case", ["c1", "m128"])
+@pytest.mark.parametrize("case", ["c1", "m128", "m256"])
 def test_normal_operator_illumination(P, case):
     cfg, inp, probe, obj, data = workload(case)
     far = P.forward(dev(obj), dev(probe), dev(inp.pos))
