@@ -101,7 +101,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100, help="timed CG iterations")
     ap.add_argument("--warmup", type=int, default=5)
-    ap.add_argument("--config", default="c2")
+    ap.add_argument("--config", default="c2",
+                    help="c2 (default: 2048^2, 128^2 probe, object-only) or c5 (8192^2, 256^2 probe, joint "
+                         "object+probe from |p|)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
@@ -117,17 +119,20 @@ def main():
     torch.cuda.set_device(device)
     cfg, inp, probe, pos, data = make_inputs(args.config, device)
     K = cfg.k
+    joint = args.config == "c5"
+    if joint:
+        probe = probe.abs().to(torch.complex64)   # amplitude known, phase unknown
     obj0 = torch.ones((cfg.obj_h, cfg.obj_w), dtype=torch.complex64, device=device)
-    ws = ptyg.workspace(ptyg.dims_of(obj0.shape, cfg.n, K), device)
+    ws = ptyg.workspace(ptyg.dims_of(obj0.shape, cfg.n, K), device, update_probe=joint)
 
     if args.warmup > 0:
-        ptyg.cg_solve(obj0, probe, pos, data, args.warmup, ws=ws)
+        ptyg.cg_solve(obj0, probe, pos, data, args.warmup, update_probe=joint, ws=ws)
     torch.cuda.synchronize()
     ptyg.timing_reset()
     ptyg.timing_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = ptyg.cg_solve(obj0, probe, pos, data, args.steps, ws=ws)
+    res = ptyg.cg_solve(obj0, probe, pos, data, args.steps, update_probe=joint, ws=ws)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ptyg.timing_enable(False)
@@ -167,9 +172,11 @@ def main():
         "data": "synthetic",
         "config": {"workload": f"{args.config}: {cfg.obj_h}x{cfg.obj_w} complex64 object, {cfg.n}x{cfg.n} probe, "
                                f"{K} positions ({cfg.grid[0]}x{cfg.grid[1]} raster, step {cfg.step}, "
-                               f"+-{cfg.jitter} px), Poisson at {cfg.photons:g} photons, object-only ML-CG",
+                               f"+-{cfg.jitter} px), Poisson at {cfg.photons:g} photons, "
+                               + ("joint object+probe ML-CG" if joint else "object-only ML-CG"),
                    "iterations": iters, "patterns": K},
         "cg_iters_per_s": round(iters / dt, 3),
+        "grad_patterns_per_s": round(K / (kinds["grad"]["avg_us"] * 1e-6), 1) if "grad" in kinds else None,
         "pattern_passes_per_s": round(K * (iters + halvings) / dt, 1),
         "mean_halvings": round(halvings / max(iters, 1), 3),
         "final_phi": res.trace[-1]["phi"] if res.trace else None,
@@ -177,7 +184,7 @@ def main():
                     for k, v in kinds.items()},
         "roofline": roofline,
     }
-    if not args.no_cpu_baseline:
+    if not args.no_cpu_baseline and not joint:
         out["cpu_baseline"] = cpu_baseline(args.config, halvings / max(iters, 1))
     print(json.dumps(out))
 

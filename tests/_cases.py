@@ -100,3 +100,36 @@ def cg_with_floor(obj0, probe, pos, data, iters, **kw):
     with fp32_transforms():
         pert = O.cg_solve(*args, **kw)
     return ref, pert
+
+
+_C5 = {}
+
+
+def c5_workload():
+    """The large one-GPU share (8192^2 object, 256^2 probe, 16384 positions,
+    Poisson at 1e6 photons): intensities from the oracle's forward model in
+    chunks of 256 patterns (FP64), then Poisson counts (float32, 4 GiB).
+    Also returns Phi at psi_0 = 1 per chunk (every patch of ones gives the
+    same exit wave p, so one transform serves all patterns)."""
+    if "w" in _C5:
+        return _C5["w"]
+    cfg = synth.CONFIGS["c5"]
+    inp = synth.make_inputs(cfg)
+    probe32 = inp.probe.astype(np.complex64)
+    obj32 = inp.obj_true.astype(np.complex64)
+    p64 = probe32.astype(np.complex128)
+    truth = obj32.astype(np.complex128)
+    K, n = cfg.k, cfg.n
+    data = np.empty((K, n, n), np.float32)
+    chunk = 256
+    children = np.random.SeedSequence(cfg.seed("poisson")).spawn((K + chunk - 1) // chunk)
+    x0 = np.abs(O.fft2u(p64)) ** 2
+    phi0 = 0.0
+    for ci, lo in enumerate(range(0, K, chunk)):
+        sl = slice(lo, min(K, lo + chunk))
+        inten = np.abs(O.forward(truth, p64, inp.pos[sl])) ** 2
+        rng = np.random.default_rng(children[ci])
+        data[sl] = rng.poisson(inten).astype(np.float32)
+        phi0 += float(np.sum(O.objective_terms(np.broadcast_to(x0, data[sl].shape), data[sl].astype(np.float64))[1]))
+    _C5["w"] = (cfg, inp, probe32, obj32, data, phi0)
+    return _C5["w"]
