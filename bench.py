@@ -105,6 +105,9 @@ def main():
                     help="c2 (default: 2048^2, 128^2 probe, object-only) or c5 (8192^2, 256^2 probe, joint "
                          "object+probe from |p|)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="after the timed run, copy a MIB-MiB device buffer 3 times (a reference kernel of known "
+                         "traffic for the HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py runs on one GPU: the ML-CG hot path here is single-GPU "
@@ -184,6 +187,13 @@ def main():
                     for k, v in kinds.items()},
         "roofline": roofline,
     }
+    if args.copy_calibration:
+        src = torch.empty(args.copy_calibration << 20, dtype=torch.uint8, device=device).fill_(1)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        out["copy_calibration_bytes"] = src.numel()
     if not args.no_cpu_baseline and not joint:
         out["cpu_baseline"] = cpu_baseline(args.config, halvings / max(iters, 1))
     print(json.dumps(out))

@@ -14,7 +14,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libptyg.so")
 BUILD = os.path.join(PKG, "_build")
-SOURCES = ["kernels.hip", "kernels256.hip", "api.hip"]
+SOURCES = ["kernels.hip", "kernels256.hip", "nn.hip", "api.hip"]
 ARCH = os.environ.get("PTYG_OFFLOAD_ARCH", "gfx950")
 
 FLAGS = [

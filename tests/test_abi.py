@@ -53,3 +53,19 @@ def test_argument_errors_without_gpu():
     small = ptyg.Dims(8, 8, 16, 4)
     assert lib.ptyg_forward(ctypes.byref(small), None, None, None, None, None, 0, None) == -1
     assert b"smaller than the probe" in lib.ptyg_last_error()
+
+
+def test_nn_library_exports():
+    """include/ptyg_nn.h: every declared entry point is exported and bound."""
+    from paper_2106_07575_amd import nn, ptyg
+    if not os.path.exists(ptyg.lib_path()):
+        pytest.skip("libptyg.so not built")
+    txt = re.sub(r"/\*.*?\*/", "", open(os.path.join(ROOT, "include", "ptyg_nn.h")).read(), flags=re.S)
+    names = set(re.findall(r"\b(ptyg_[a-z0-9_]+)\s*\(", txt))
+    lib = ctypes.CDLL(ptyg.lib_path())
+    for name in names:
+        assert hasattr(lib, name), name
+    assert names == set(nn.EXPORTS)
+    assert nn.weight_sizes(1, 32) == (32 * 96, 8 * 288)
+    with pytest.raises(RuntimeError):
+        nn.weight_sizes(0, 32)

@@ -1,0 +1,398 @@
+"""Warm-start kernels (include/ptyg_nn.h) against plain float64 PyTorch CPU
+definitions of the same operations.
+
+The convolution kernels take bf16 operands and accumulate in FP32; the
+reference uses the same bf16-rounded operands in float64, so the only
+differences are FP32 accumulation order (~1e-6 relative) and the rounding of
+a bf16 output (relative 2^-9).  Tolerances: bf16 outputs |e| <= 2^-8 |ref| +
+1e-4 max|ref|, FP32 outputs |e| <= 1e-4 max|ref|.  Elementwise kernels whose
+result is one rounding of an exactly computed value are compared bit for bit.
+"""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+F = torch.nn.functional
+
+
+@pytest.fixture(scope="module")
+def NN():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_07575_amd import nn
+    nn.lib()
+    return nn
+
+
+def cp(c):
+    return (c + 7) // 8 * 8
+
+
+def rand_act(g, B, H, W, c, relu=False):
+    x = torch.zeros((B, H, W, cp(c)), dtype=torch.float32)
+    x[..., :c] = torch.randn((B, H, W, c), generator=g)
+    if relu:
+        x.clamp_(min=0)
+    return x.to(torch.bfloat16)
+
+
+def tw(w32, cin, cout):
+    """w32 [cout][9][cin] -> torch conv weight [cout][cin][3][3]."""
+    return w32.view(cout, 3, 3, cin).permute(0, 3, 1, 2)
+
+
+def nchw(x, c):
+    return x[..., :c].permute(0, 3, 1, 2).double()
+
+
+def close_bf16(got, ref):
+    got, ref = got.double(), ref.double()
+    tol = 2.0 ** -8 * ref.abs() + 1e-4 * ref.abs().max()
+    return bool(((got - ref).abs() <= tol).all()), float(((got - ref).abs() - tol).max())
+
+
+def packed(NN, w32, cin, cout):
+    nw, nwt = NN.weight_sizes(cin, cout)
+    w = torch.empty(nw, dtype=torch.bfloat16, device="cuda")
+    wt = torch.empty(nwt, dtype=torch.bfloat16, device="cuda")
+    NN.pack_weights(w32.cuda(), cin, cout, w, wt)
+    return w, wt
+
+
+CONV = [(2, 16, 16, 1, 32, True, False), (2, 12, 20, 32, 64, True, False), (1, 8, 8, 256, 128, False, True),
+        (3, 10, 6, 64, 2, False, True), (4, 32, 32, 32, 64, True, False), (1, 5, 7, 8, 8, True, False)]
+
+
+@pytest.mark.parametrize("B,H,W,cin,cout,relu,f32", CONV)
+def test_conv_forward(NN, B, H, W, cin, cout, relu, f32):
+    print(f"conv fwd B{B} {H}x{W} {cin}->{cout}", flush=True)
+    g = torch.Generator().manual_seed(11 + cin + cout)
+    x = rand_act(g, B, H, W, cin)
+    w32 = torch.randn((cout, 9, cin), generator=g) / np.sqrt(9 * cin)
+    bias = torch.randn(cout, generator=g)
+    w, _ = packed(NN, w32, cin, cout)
+    y = torch.empty((B, H, W, cp(cout)), dtype=torch.float32 if f32 else torch.bfloat16, device="cuda")
+    NN.conv_fwd(x.cuda(), w, bias.cuda(), y, B, H, W, cin, cout, relu, out_f32=f32)
+    ref = F.conv2d(nchw(x, cin), tw(w32.to(torch.bfloat16).double(), cin, cout), bias.double(), padding=1)
+    if relu:
+        ref = ref.clamp(min=0)
+    got = y.cpu()
+    assert torch.all(got[..., cout:] == 0), "padded channels must be zero"
+    got = got[..., :cout].permute(0, 3, 1, 2)
+    if f32:
+        err = (got.double() - ref).abs().max() / ref.abs().max()
+        assert err <= 1e-4, err
+    else:
+        ok, excess = close_bf16(got, ref)
+        assert ok, excess
+
+
+@pytest.mark.parametrize("B,H,W,cin,cout,relu,f32", CONV)
+def test_conv_backward_data(NN, B, H, W, cin, cout, relu, f32):
+    print(f"conv bwd-data B{B} {H}x{W} {cin}->{cout}", flush=True)
+    g = torch.Generator().manual_seed(23 + cin + cout)
+    dz = rand_act(g, B, H, W, cout)
+    w32 = torch.randn((cout, 9, cin), generator=g) / np.sqrt(9 * cin)
+    _, wt = packed(NN, w32, cin, cout)
+    dx = torch.empty((B, H, W, cp(cin)), dtype=torch.bfloat16, device="cuda")
+    NN.conv_bwd_data(dz.cuda(), wt, dx, B, H, W, cin, cout)
+    xr = torch.zeros((B, cin, H, W), dtype=torch.float64, requires_grad=True)
+    F.conv2d(xr, tw(w32.to(torch.bfloat16).double(), cin, cout), padding=1).backward(nchw(dz, cout))
+    got = dx.cpu()
+    assert torch.all(got[..., cin:] == 0)
+    ok, excess = close_bf16(got[..., :cin].permute(0, 3, 1, 2), xr.grad)
+    assert ok, excess
+
+
+@pytest.mark.parametrize("B,H,W,cin,cout,relu,f32", CONV)
+def test_conv_backward_weight(NN, B, H, W, cin, cout, relu, f32):
+    print(f"conv bwd-weight B{B} {H}x{W} {cin}->{cout}", flush=True)
+    if (B * H * W) % 8:
+        pytest.skip("B*H*W must be a multiple of 8")
+    g = torch.Generator().manual_seed(37 + cin + cout)
+    x = rand_act(g, B, H, W, cin, relu=True)
+    dz = rand_act(g, B, H, W, cout)
+    dw = torch.empty((cout, 9, cin), dtype=torch.float32, device="cuda")
+    db = torch.empty(cout, dtype=torch.float32, device="cuda")
+    scratch = torch.empty(NN.wgrad_scratch(B, H, W, cin, cout), dtype=torch.uint8, device="cuda")
+    NN.conv_bwd_weight(x.cuda(), dz.cuda(), dw, db, B, H, W, cin, cout, scratch)
+    wr = torch.zeros((cout, cin, 3, 3), dtype=torch.float64, requires_grad=True)
+    br = torch.zeros(cout, dtype=torch.float64, requires_grad=True)
+    F.conv2d(nchw(x, cin), wr, br, padding=1).backward(nchw(dz, cout))
+    ref_w = wr.grad.permute(0, 2, 3, 1).reshape(cout, 9, cin)
+    err_w = (dw.cpu().double() - ref_w).abs().max() / ref_w.abs().max()
+    err_b = (db.cpu().double() - br.grad).abs().max() / br.grad.abs().max()
+    assert err_w <= 1e-4 and err_b <= 1e-4, (float(err_w), float(err_b))
+
+
+def test_conv_backward_weight_reproducible(NN):
+    B, H, W, cin, cout = 4, 32, 32, 32, 64
+    g = torch.Generator().manual_seed(3)
+    x = rand_act(g, B, H, W, cin).cuda()
+    dz = rand_act(g, B, H, W, cout).cuda()
+    scratch = torch.empty(NN.wgrad_scratch(B, H, W, cin, cout), dtype=torch.uint8, device="cuda")
+    outs = []
+    for _ in range(2):
+        dw = torch.empty((cout, 9, cin), dtype=torch.float32, device="cuda")
+        db = torch.empty(cout, dtype=torch.float32, device="cuda")
+        NN.conv_bwd_weight(x, dz, dw, db, B, H, W, cin, cout, scratch)
+        outs.append((dw.cpu(), db.cpu()))
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+
+
+@pytest.mark.parametrize("c", [2, 32, 256])
+def test_pool_up_relu(NN, c):
+    g = torch.Generator().manual_seed(c)
+    B, H, W = 2, 8, 12
+    x = rand_act(g, B, H, W, c)
+    xc = x.cuda()
+    y = torch.empty((B, H // 2, W // 2, cp(c)), dtype=torch.bfloat16, device="cuda")
+    NN.pool2(xc, y, B, H, W, c)
+    xf = x.float()
+    ref = (0.25 * (xf[:, 0::2, 0::2] + xf[:, 1::2, 0::2] + xf[:, 0::2, 1::2] + xf[:, 1::2, 1::2])).to(torch.bfloat16)
+    assert torch.equal(y.cpu(), ref)
+    dx = torch.empty_like(xc)
+    NN.pool2(y, dx, B, H, W, c, backward=True)
+    ref_dx = (0.25 * y.cpu().float()).repeat_interleave(2, 1).repeat_interleave(2, 2).to(torch.bfloat16)
+    assert torch.equal(dx.cpu(), ref_dx)
+    u = torch.empty((B, 2 * H, 2 * W, cp(c)), dtype=torch.bfloat16, device="cuda")
+    NN.up2(xc, u, B, H, W, c)
+    assert torch.equal(u.cpu(), x.repeat_interleave(2, 1).repeat_interleave(2, 2))
+    du = rand_act(g, B, 2 * H, 2 * W, c)
+    dxu = torch.empty_like(xc)
+    NN.up2(du.cuda(), dxu, B, H, W, c, backward=True)
+    df = du.float()
+    ref_u = (df[:, 0::2, 0::2] + df[:, 0::2, 1::2] + df[:, 1::2, 0::2] + df[:, 1::2, 1::2]).to(torch.bfloat16)
+    assert torch.equal(dxu.cpu(), ref_u)
+    dy = rand_act(g, B, H, W, c)
+    dz = torch.empty_like(xc)
+    NN.relu_bwd(dy.cuda(), xc, dz)
+    assert torch.equal(dz.cpu(), torch.where(x.float() > 0, dy, torch.zeros_like(dy)))
+
+
+def test_input_mse_adam(NN):
+    g = torch.Generator().manual_seed(5)
+    d = torch.poisson(torch.rand((3, 16, 16), generator=g) * 50, generator=g)
+    x = torch.empty((3, 16, 16, 8), dtype=torch.bfloat16, device="cuda")
+    NN.net_input(d.cuda(), x, 0.1)
+    ref = (0.1 * torch.log1p(torch.fft.fftshift(d, dim=(-2, -1)).double())).float().to(torch.bfloat16)
+    got = x.cpu()
+    assert torch.all(got[..., 1:] == 0)
+    # one bf16 step of slack for the FP32 log1p rounding ahead of the bf16 one
+    assert ((got[..., 0].float() - ref.float()).abs() <= 2.0 ** -8 * ref.float().abs() + 1e-7).all()
+
+    npx = 3 * 64
+    out = torch.randn((npx, 8), generator=g)
+    tgt = torch.randn((npx, 2), generator=g)
+    dz = torch.empty((npx, 8), dtype=torch.bfloat16, device="cuda")
+    parts = torch.empty(16, dtype=torch.float64, device="cuda")
+    NN.mse(out.cuda(), tgt.cuda(), dz, parts)
+    e = (out[:, :2] - tgt).double()          # the difference is taken in FP32
+    assert abs(float(parts.sum()) - float((e ** 2).sum())) <= 1e-12 * float((e ** 2).sum())
+    assert torch.equal(dz.cpu()[:, :2], (2.0 * (out[:, :2] - tgt) * np.float32(1.0 / (2 * npx))).to(torch.bfloat16))
+    assert torch.all(dz.cpu()[:, 2:] == 0)
+
+    n = 1000
+    w = torch.randn(n, generator=g)
+    m = torch.zeros(n)
+    v = torch.zeros(n)
+    wd, md, vd = w.cuda(), m.cuda(), v.cuda()
+    wr, mr, vr = w.double(), m.double(), v.double()
+    lr, b1, b2, eps = 1e-2, 0.9, 0.999, 1e-8
+    for step in range(1, 4):
+        gr = torch.randn(n, generator=g)
+        NN.adam(wd, gr.cuda(), md, vd, lr, step, b1, b2, eps)
+        # Adam (Kingma & Ba): bias-corrected first and second moments
+        mr = b1 * mr + (1 - b1) * gr.double()
+        vr = b2 * vr + (1 - b2) * gr.double() ** 2
+        wr = wr - lr * (mr / (1 - b1 ** step)) / (torch.sqrt(vr / (1 - b2 ** step)) + eps)
+    assert (wd.cpu().double() - wr).abs().max() <= 1e-5
+
+
+# ------------------------------------------------------------ stitching
+def _grid_positions(K_side, step, q, margin=5):
+    r, c = np.meshgrid(np.arange(K_side) * step + margin, np.arange(K_side) * step + margin, indexing="ij")
+    pos = np.stack([r.ravel(), c.ravel()], 1).astype(np.int32)
+    H = W = int((K_side - 1) * step + q + 2 * margin + 3)
+    return pos, H, W
+
+
+def _smooth_field(rng, H, W):
+    f = rng.standard_normal((H, W)) + 1j * rng.standard_normal((H, W))
+    ky = np.fft.fftfreq(H)[:, None]
+    kx = np.fft.fftfreq(W)[None, :]
+    f = np.fft.ifft2(np.fft.fft2(f) * np.exp(-2 * (np.pi * 3) ** 2 * (ky ** 2 + kx ** 2)))
+    return (0.9 + 0.1 * np.abs(f) / np.abs(f).max()) * np.exp(1j * np.angle(f))
+
+
+def stitch_reference(P, z, wpos, H, W, q):
+    acc = np.zeros((H, W), np.complex128)
+    cnt = np.zeros((H, W), np.int64)
+    for k in range(len(wpos)):
+        r, c = wpos[k]
+        acc[r:r + q, c:c + q] += z[k] * P[k]
+        cnt[r:r + q, c:c + q] += 1
+    out = np.ones((H, W), np.complex128)
+    out[cnt > 0] = acc[cnt > 0] / cnt[cnt > 0]
+    return out, cnt
+
+
+@pytest.mark.parametrize("K_side,step,q", [(6, 20, 32), (9, 24, 64)])
+def test_phase_sync_and_stitch(NN, K_side, step, q):
+    rng = np.random.default_rng(K_side)
+    wpos, H, W = _grid_positions(K_side, step, q)
+    K = len(wpos)
+    T = _smooth_field(rng, H, W)
+    theta = rng.uniform(-np.pi, np.pi, K)
+    P = np.stack([T[r:r + q, c:c + q] * np.exp(-1j * theta[k]) for k, (r, c) in enumerate(wpos)])
+    out = np.zeros((K, q, q, 8), np.float32)
+    out[..., 0] = np.abs(P)
+    out[..., 1] = np.angle(P)
+    outd = torch.from_numpy(out).cuda()
+    Pd = torch.empty((K, q, q), dtype=torch.complex64, device="cuda")
+    NN.patches(outd, Pd)
+    assert np.abs(Pd.cpu().numpy() - P).max() <= 1e-5
+    wposd = torch.from_numpy(wpos).cuda()
+    maxnb = 32
+    scratch = {"cnt": torch.empty(K, dtype=torch.int32, device="cuda"),
+               "nb": torch.empty(K * maxnb, dtype=torch.int32, device="cuda"),
+               "c": torch.empty((K * maxnb, 2), dtype=torch.float64, device="cuda"),
+               "ztmp": torch.empty((K, 2), dtype=torch.float64, device="cuda")}
+    z = NN.phase_sync(Pd, wposd, q, maxnb, 300, scratch).cpu().numpy()
+    z = z[:, 0] + 1j * z[:, 1]
+    assert np.allclose(np.abs(z), 1.0, atol=1e-12)
+    # z_k e^{-i theta_k} is one global phase for every window
+    rel = z * np.exp(-1j * theta)
+    assert np.abs(np.angle(rel / rel[0])).max() <= 1e-4
+    offsets, lst = NN.tile_lists(wposd, H, W, q)
+    zd = torch.from_numpy(np.stack([z.real, z.imag], 1)).cuda()
+    psi0 = torch.empty((H, W), dtype=torch.complex64, device="cuda")
+    NN.stitch(Pd, zd, wposd, offsets, lst, H, W, q, psi0)
+    ref, cnt = stitch_reference(P, z, wpos, H, W, q)
+    assert np.abs(psi0.cpu().numpy() - ref).max() <= 1e-5
+    covered = cnt > 0
+    assert np.abs(psi0.cpu().numpy()[covered] - T[covered] * rel[0]).max() <= 1e-4
+    count = torch.empty((H, W), dtype=torch.int32, device="cuda")
+    NN.cover_count(wposd, H, W, q, offsets, lst, count)
+    assert np.array_equal(count.cpu().numpy(), cnt)
+
+
+def test_stitch_adjoint(NN):
+    """<dz, d> = 2 Re <g, dpsi> for a direction d of the network output
+    (amplitude, phase), with dpsi the central difference of the float64
+    reference stitch."""
+    rng = np.random.default_rng(8)
+    q = 16
+    wpos, H, W = _grid_positions(4, 10, q)
+    K = len(wpos)
+    out = np.zeros((K, q, q, 8), np.float32)
+    out[..., 0] = rng.uniform(0.8, 1.0, (K, q, q))
+    out[..., 1] = rng.uniform(-1, 1, (K, q, q))
+    z = np.exp(1j * rng.uniform(-np.pi, np.pi, K))
+    g = (rng.standard_normal((H, W)) + 1j * rng.standard_normal((H, W))).astype(np.complex64)
+    wposd = torch.from_numpy(wpos).cuda()
+    offsets, lst = NN.tile_lists(wposd, H, W, q)
+    count = torch.empty((H, W), dtype=torch.int32, device="cuda")
+    NN.cover_count(wposd, H, W, q, offsets, lst, count)
+    dz = torch.empty((K * q * q, 8), dtype=torch.bfloat16, device="cuda")
+    zd = torch.from_numpy(np.stack([z.real, z.imag], 1)).cuda()
+    NN.stitch_adjoint(torch.from_numpy(g).cuda(), torch.from_numpy(out).cuda(), zd, wposd, count, W, q, 1.0, dz)
+    dzn = dz.cpu().float().numpy().reshape(K, q, q, 8)
+    assert np.all(dzn[..., 2:] == 0)
+    o64 = out.astype(np.float64)
+
+    def S(o):
+        return stitch_reference(o[..., 0] * np.exp(1j * o[..., 1]), z, wpos, H, W, q)[0]
+
+    for trial in range(3):
+        d = np.zeros_like(o64)
+        d[..., 0] = rng.standard_normal((K, q, q))
+        d[..., 1] = rng.standard_normal((K, q, q))
+        h = 1e-6
+        dpsi = (S(o64 + h * d) - S(o64 - h * d)) / (2 * h)
+        lhs = float((dzn.astype(np.float64) * d).sum())
+        rhs = 2.0 * float(np.real(np.vdot(g.astype(np.complex128), dpsi)))
+        assert abs(lhs - rhs) <= 1e-2 * np.sqrt((dzn.astype(np.float64) ** 2).sum() * (d ** 2).sum()), (lhs, rhs)
+
+
+def _reference_net(WS, net, x_bf16):
+    """float64 CPU model of the same layers, weights rounded to bf16 as the
+    kernels see them (activations are not rounded: the comparison bound
+    allows for the kernels' per-layer bf16 activations)."""
+    params = []
+    h = x_bf16[..., :1].permute(0, 3, 1, 2).double()
+    for spec, p in zip(WS.LAYERS, net.params):
+        if spec[0] == "conv":
+            _, cin, cout, relu = spec
+            w = tw(p["w32"].cpu().to(torch.bfloat16).double(), cin, cout).clone().requires_grad_(True)
+            b = p["b"].cpu().double().clone().requires_grad_(True)
+            params.append((w, b))
+            h = F.conv2d(h, w, b, padding=1)
+            if relu:
+                h = h.clamp(min=0)
+        elif spec[0] == "pool":
+            h = F.avg_pool2d(h, 2)
+        else:
+            h = F.interpolate(h, scale_factor=2, mode="nearest")
+    return h, params
+
+
+def test_net_gradient_matches_reference(NN):
+    """Whole-network forward and weight gradients (every layer's kernels
+    chained as in training) against the float64 CPU model: relative L2
+    error <= 5e-2 (bf16 activations at 15 layers), far below what a layout,
+    index or sign error gives (O(1))."""
+    from paper_2106_07575_amd import warmstart as WS
+    dev = torch.device("cuda")
+    net = WS.Net(dev, seed=3)
+    g = torch.Generator().manual_seed(4)
+    B = 2
+    d = torch.poisson(torch.rand((B, 128, 128), generator=g) * 200, generator=g)
+    tgt = torch.stack([0.9 + 0.05 * torch.rand((B, 64, 64), generator=g),
+                       0.4 * torch.rand((B, 64, 64), generator=g) - 0.2], -1).contiguous()
+    out = net.forward(d.cuda())
+    dout = torch.empty(out.shape, dtype=torch.bfloat16, device=dev)
+    parts = torch.empty(32, dtype=torch.float64, device=dev)
+    NN.mse(out, tgt.cuda(), dout, parts)
+    net.backward(dout)
+    x = torch.empty((B, 128, 128, 8), dtype=torch.bfloat16, device=dev)
+    NN.net_input(d.cuda(), x, WS.INPUT_SCALE)
+    ref, params = _reference_net(WS, net, x.cpu())
+    got = out.cpu()[..., :2].permute(0, 3, 1, 2).double()
+    e_out = float((got - ref).norm() / ref.norm())
+    loss = ((ref - tgt.permute(0, 3, 1, 2).double()) ** 2).mean()
+    loss.backward()
+    errs = []
+    convs = [p for p in net.params if p]
+    for p, (w, b) in zip(convs, params):
+        gw_ref = w.grad.permute(0, 2, 3, 1).reshape(p["gw"].shape)
+        errs.append((float((p["gw"].cpu().double() - gw_ref).norm() / gw_ref.norm()),
+                     float((p["gb"].cpu().double() - b.grad).norm() / b.grad.norm())))
+    print(f"net output rel {e_out:.2e}; weight/bias grad rel per layer {[(round(a, 4), round(c, 4)) for a, c in errs]}")
+    assert e_out <= 5e-2
+    assert all(a <= 5e-2 and c <= 5e-2 for a, c in errs), errs
+
+
+def test_net_train_steps(NN):
+    """Adam steps on a fixed batch with a learnable (constant) target reduce
+    the window loss; outputs stay finite with the documented shape."""
+    from paper_2106_07575_amd import warmstart as WS
+    dev = torch.device("cuda")
+    net = WS.Net(dev, seed=1)
+    g = torch.Generator(device=dev).manual_seed(2)
+    d = torch.poisson(torch.rand((4, 128, 128), device=dev, generator=g) * 100, generator=g)
+    t = torch.stack([torch.full((4, 64, 64), 0.9, device=dev), torch.full((4, 64, 64), 0.3, device=dev)],
+                    -1).contiguous()
+    parts = torch.empty(64, dtype=torch.float64, device=dev)
+    losses = []
+    for _ in range(40):
+        out = net.forward(d)
+        assert out.shape == (4, 64, 64, 8) and torch.isfinite(out).all()
+        dout = torch.empty(out.shape, dtype=torch.bfloat16, device=dev)
+        NN.mse(out, t, dout, parts)
+        losses.append(float(parts.sum()))
+        net.backward(dout)
+        net.adam_step(1e-4)
+    print("losses", [round(v, 2) for v in losses[::5]])
+    assert min(losses[-5:]) < 0.5 * losses[0], losses
