@@ -27,10 +27,36 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
-# per-pattern-pixel algorithmic bytes: patch read 8 B (+ direction patch 8 B
-# for a line-search trial), intensity read 4 B, gradient accumulate 8 B
-BYTES_PER_PX = {"grad": 20, "minfunc": 20}
+# Algorithmic bytes per launch (what each kernel must move; overlapping patch
+# re-reads served by caches still count), P = K n^2 pattern pixels:
+#   GRAD: patch 8 B + intensity 4 B + per-pattern back-propagated wave 8 B
+#         per pixel (+ 8 B stored G psi in the batched search)
+#   sequential line-search trial: psi and eta patches 16 B + intensity 4 B
+#   batched line-search pass: per listed (d > 0) element index 4 B + A 8 B +
+#         B 8 B + intensity 4 B
+#   direction forward: eta patch 8 B + far field 8 B + stored A read 8 B
+#   overlap sum: back-propagated waves 8 B per pixel + object gradient write
+def kernel_bytes(kind: str, cfg, batched: bool, nnz: int) -> int:
+    px = cfg.k * cfg.n * cfg.n
+    if kind == "grad":
+        return (28 if batched else 20) * px
+    if kind == "minfunc":
+        return 24 * nnz if batched else 20 * px
+    if kind == "dir_forward":
+        return 24 * px
+    if kind == "tile_sum":
+        return 8 * px + 8 * cfg.obj_h * cfg.obj_w
+    raise KeyError(kind)
+
+
+KERNEL_NAMES = {"grad": "k_grad (fused GRAD)", "minfunc": "k_minfunc (line-search trial)",
+                "ls_batched": "k_ls_batch (batched line-search pass)", "dir_forward": "k_fwd_t (G eta)",
+                "tile_sum": "k_tile_sum (ordered overlap sum)"}
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per launch (FETCH_SIZE x 2 + WRITE_SIZE x 1, the factors from a
+# 512 MiB device copy measured by the same counters) of the current kernels,
+# from the rocprofv3 --pmc runs summarised in profiles/; absent = not measured
+TRAFFIC_BYTES = {}
 FP32_PEAK_TFLOPS = 157.3
 
 
@@ -104,6 +130,9 @@ def main():
     ap.add_argument("--config", default="c2",
                     help="c2 (default: 2048^2, 128^2 probe, object-only) or c5 (8192^2, 256^2 probe, joint "
                          "object+probe from |p|)")
+    ap.add_argument("--line-search", default="batched", choices=["batched", "sequential"],
+                    help="batched: trials from stored far fields, up to 16 per streaming pass (default); "
+                         "sequential: one forward pass per trial")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the timed run, copy a MIB-MiB device buffer 3 times (a reference kernel of known "
@@ -126,16 +155,17 @@ def main():
     if joint:
         probe = probe.abs().to(torch.complex64)   # amplitude known, phase unknown
     obj0 = torch.ones((cfg.obj_h, cfg.obj_w), dtype=torch.complex64, device=device)
-    ws = ptyg.workspace(ptyg.dims_of(obj0.shape, cfg.n, K), device, update_probe=joint)
+    ls = args.line_search
+    ws = ptyg.workspace(ptyg.dims_of(obj0.shape, cfg.n, K), device, update_probe=joint, line_search=ls)
 
     if args.warmup > 0:
-        ptyg.cg_solve(obj0, probe, pos, data, args.warmup, update_probe=joint, ws=ws)
+        ptyg.cg_solve(obj0, probe, pos, data, args.warmup, update_probe=joint, ws=ws, line_search=ls)
     torch.cuda.synchronize()
     ptyg.timing_reset()
     ptyg.timing_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = ptyg.cg_solve(obj0, probe, pos, data, args.steps, update_probe=joint, ws=ws)
+    res = ptyg.cg_solve(obj0, probe, pos, data, args.steps, update_probe=joint, ws=ws, line_search=ls)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ptyg.timing_enable(False)
@@ -145,19 +175,24 @@ def main():
     halvings = sum(r["halvings"] for r in res.trace)
     value = K * iters / dt
     px = K * cfg.n * cfg.n
+    nnz = int((~(data <= 0)).sum())
+    batched = ls == "batched"
     kinds = {}
     for kind, (ms, cnt) in kt.items():
         if cnt:
+            name = "ls_batched" if (kind == "minfunc" and batched) else kind
             avg_s = ms / cnt / 1e3
-            kinds[kind] = {"launches": cnt, "avg_us": avg_s * 1e6, "total_ms": ms,
-                           "alg_GBs": BYTES_PER_PX[kind] * px / avg_s / 1e9,
-                           "fft_TFLOPs": (1 if kind == "minfunc" else 2) * K * fft_flops(cfg.n) / avg_s / 1e12}
+            ffts = {"grad": 2, "minfunc": 1, "dir_forward": 1 + int(joint), "ls_batched": 0, "tile_sum": 0}[name]
+            kinds[name] = {"launches": cnt, "avg_us": avg_s * 1e6, "total_ms": ms,
+                           "bytes_per_launch": kernel_bytes(kind, cfg, batched, nnz),
+                           "alg_GBs": kernel_bytes(kind, cfg, batched, nnz) / avg_s / 1e9,
+                           "fft_TFLOPs": ffts * K * fft_flops(cfg.n) / avg_s / 1e12}
     dom = max(kinds, key=lambda k: kinds[k]["total_ms"])
     d = kinds[dom]
+    bpl = d["bytes_per_launch"]
     roofline = {"bound": "hbm", "achieved": round(d["alg_GBs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(d["alg_GBs"] / HBM_PEAK_GBS, 4), "traffic": None,
-                "kernel": "k_minfunc (line-search trial)" if dom == "minfunc" else "k_grad (fused GRAD)",
-                "bytes_per_launch": BYTES_PER_PX[dom] * px, "avg_launch_us": round(d["avg_us"], 2),
+                "frac": round(d["alg_GBs"] / HBM_PEAK_GBS, 4), "traffic": TRAFFIC_BYTES.get((dom, args.config)),
+                "kernel": KERNEL_NAMES[dom], "bytes_per_launch": bpl, "avg_launch_us": round(d["avg_us"], 2),
                 "fft_tflops": round(d["fft_TFLOPs"], 2), "fft_frac_of_fp32_peak":
                     round(d["fft_TFLOPs"] / FP32_PEAK_TFLOPS, 4)}
     out = {
@@ -173,7 +208,8 @@ def main():
         "vs_baseline": None,
         "dtype": "fp32 transforms, fp64 reductions",
         "data": "synthetic",
-        "config": {"workload": f"{args.config}: {cfg.obj_h}x{cfg.obj_w} complex64 object, {cfg.n}x{cfg.n} probe, "
+        "config": {"line_search": ls,
+                   "workload": f"{args.config}: {cfg.obj_h}x{cfg.obj_w} complex64 object, {cfg.n}x{cfg.n} probe, "
                                f"{K} positions ({cfg.grid[0]}x{cfg.grid[1]} raster, step {cfg.step}, "
                                f"+-{cfg.jitter} px), Poisson at {cfg.photons:g} photons, "
                                + ("joint object+probe ML-CG" if joint else "object-only ML-CG"),
@@ -182,6 +218,7 @@ def main():
         "grad_patterns_per_s": round(K / (kinds["grad"]["avg_us"] * 1e-6), 1) if "grad" in kinds else None,
         "pattern_passes_per_s": round(K * (iters + halvings) / dt, 1),
         "mean_halvings": round(halvings / max(iters, 1), 3),
+        "listed_fraction": round(nnz / px, 4),
         "final_phi": res.trace[-1]["phi"] if res.trace else None,
         "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items()}
                     for k, v in kinds.items()},

@@ -79,7 +79,18 @@ typedef struct {
   int32_t max_halvings; /* line-search trials before giving up (gamma = 0, restart); e.g. 40 */
   double eps;           /* guard on |G psi|^2 for log and division (e.g. 1e-32) */
   double target_phi;    /* stop before an iteration whose deviance is <= target; < 0 disables */
+  int32_t line_search;  /* PTYG_LS_SEQUENTIAL: one MINFUNC pass (forward transform of
+                           psi + gamma eta) per trial, as Algorithm 1 states it;
+                           PTYG_LS_BATCHED: G is linear, so trial j's far field is
+                           G psi + gamma_j G eta (+ gamma_j^2 G(eta_p eta) in joint
+                           mode): the GRAD pass stores G psi, one forward pass forms
+                           G eta, and up to 16 trials are evaluated per streaming pass
+                           over the stored far fields (no transforms); the accepted
+                           trial is the first that passes, as in the sequential order.
+                           Needs 2 (joint: 3) extra k*n*n complex64 of workspace. */
 } ptyg_cg_opts;
+
+enum { PTYG_LS_SEQUENTIAL = 0, PTYG_LS_BATCHED = 1 };
 
 /* One row per completed iteration m of ptyg_cg_solve. */
 typedef struct {
@@ -88,7 +99,8 @@ typedef struct {
   double gamma;     /* accepted step gamma_m (0 if the line search failed) */
   double beta;      /* Dai-Yuan coefficient used for eta_m (0 on a restart) */
   double step_norm; /* ||psi_{m+1} - psi_m||_2 = gamma ||eta_m|| (the paper's convergence 2-norm) */
-  int32_t halvings; /* line-search trials (objective evaluations) */
+  int32_t halvings; /* index j of the accepted trial gamma0 tau^j (max_halvings if none passed):
+                       the number of objective evaluations of the sequential search */
   int32_t restarted;/* 1 if eta_m = -grad_m (first iteration, bad denominator or failed search) */
 } ptyg_cg_iter_stats;
 
@@ -99,8 +111,10 @@ const char* ptyg_status_string(ptyg_status s);
 const char* ptyg_last_error(void);
 
 /* Bytes of workspace needed by every call below for these dims; `opts` may be
- * NULL (then the object-only solver is assumed).  Includes a transposed copy
- * of the intensities (k*n*n floats) used by ptyg_cg_solve. */
+ * NULL (then the object-only solver with the sequential line search is
+ * assumed).  Includes a transposed copy of the intensities (k*n*n floats)
+ * used by ptyg_cg_solve, and the stored far fields of the batched line search
+ * when opts->line_search is PTYG_LS_BATCHED. */
 size_t ptyg_workspace_size(const ptyg_dims* dims, const ptyg_cg_opts* opts);
 
 /* Checks that every scan position keeps its patch inside the object.
@@ -148,7 +162,8 @@ ptyg_status ptyg_minfunc(const ptyg_dims* dims, const ptyg_c64* obj, const ptyg_
  * linesearch).  obj: in psi_0, out psi_iters.  probe: read, and updated when
  * opts->update_probe.  trace: HOST array of opts->iters rows (nullable).
  * iters_done: HOST (nullable).  Synchronous: it waits on `stream` once per
- * iteration and once per line-search trial (a few bytes read back each time).
+ * iteration and once per line-search trial (sequential search) or per pass of
+ * up to 16 trials (batched search), a few bytes read back each time.
  * Returns PTYG_E_BOUNDS for a bad scan position and PTYG_E_NONFINITE if the
  * objective at an iterate is not finite. */
 ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj, ptyg_c64* probe, const int32_t* pos,
@@ -156,11 +171,14 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj, ptyg_c64* probe,
                           ptyg_cg_iter_stats* trace, int32_t* iters_done, ptyg_stream_t stream);
 
 /* Opt-in kernel timing for benchmarks: when enabled, the fused GRAD kernel
- * (kind 0) and the line-search MINFUNC kernel (kind 1) launched by any call
- * above are bracketed by HIP events on their stream.  ptyg_timing_read
- * waits for the recorded events and returns, per kind, the total elapsed
- * milliseconds and the number of launches since the last reset (arrays of
- * `kinds` entries, kinds <= 2).  Timing is per process and not thread-safe. */
+ * (kind 0), the line-search kernel (kind 1: a MINFUNC pass, or a batched
+ * pass over stored far fields), the forward transform of the search
+ * direction of the batched line search (kind 2) and the ordered overlap sum
+ * of the object gradient (kind 3) launched by the solver and the GRAD call
+ * are bracketed by HIP events on their stream.  ptyg_timing_read waits for
+ * the recorded events and returns, per kind, the total elapsed milliseconds
+ * and the number of launches since the last reset (arrays of `kinds`
+ * entries, kinds <= 4).  Timing is per process and not thread-safe. */
 void ptyg_timing_enable(int32_t on);
 void ptyg_timing_reset(void);
 ptyg_status ptyg_timing_read(double* ms, int32_t* count, int32_t kinds);

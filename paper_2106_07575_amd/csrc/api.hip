@@ -56,11 +56,14 @@ ptyg_status check_dims(const ptyg_dims* d) {
 // Workspace regions (byte offsets, each 256-byte aligned).
 struct Layout {
   size_t partials, scalars, flag, pparts, eta_obj, grad_obj, eta_probe, grad_probe, data_t, ubuf, toff, tlist,
-      total;
+      far_a, far_b, far_c, lsparts, lsphi, nz_counts, nz_offsets, nz_idx, zparts, zsums, total;
+  size_t nz_blocks, z_blocks;
   size_t n_partials;
 };
 
-Layout layout(const ptyg_dims* d, bool joint) {
+// The regions of the batched line search come last, so the offsets of the
+// others do not depend on it.
+Layout layout(const ptyg_dims* d, bool joint, bool batched = false) {
   Layout L{};
   const size_t obj_n = (size_t)d->obj_h * d->obj_w;
   const size_t probe_n = (size_t)d->n * d->n;
@@ -94,12 +97,44 @@ Layout layout(const ptyg_dims* d, bool joint) {
   L.tlist = o;
   const size_t nl = std::max(T, (size_t)d->k * tiles_per_patch(d->n));
   o = align_up(o + nl * sizeof(int));
+  L.far_a = L.far_b = L.far_c = L.lsparts = L.lsphi = L.nz_counts = L.nz_offsets = L.nz_idx = L.zparts = L.zsums = 0;
+  L.nz_blocks = L.z_blocks = 0;
+  if (batched) {
+    const size_t elems = (size_t)d->k * probe_n;
+    L.nz_blocks = (elems + kNzChunk - 1) / kNzChunk;
+    L.z_blocks = (size_t)fwd_t_blocks(d->n, d->k);
+    L.nz_counts = o;
+    o = align_up(o + L.nz_blocks * sizeof(int));
+    L.nz_offsets = o;
+    o = align_up(o + (L.nz_blocks + 1) * sizeof(int));
+    L.nz_idx = o;
+    o = align_up(o + elems * sizeof(int));
+    // GRAD sums of |G psi|^2 (one per block), then the direction passes' rows
+    L.zparts = o;
+    o = align_up(o + (L.n_partials + 2 * L.z_blocks * 4) * sizeof(double));
+    L.zsums = o;
+    o = align_up(o + 16 * sizeof(double));
+    const size_t far_bytes = (size_t)d->k * probe_n * sizeof(float2);
+    L.far_a = o;
+    o = align_up(o + far_bytes);
+    L.far_b = o;
+    o = align_up(o + far_bytes);
+    if (joint) {
+      L.far_c = o;
+      o = align_up(o + far_bytes);
+    }
+    L.lsparts = o;
+    o = align_up(o + (size_t)kLsBlocks * kLsRow * sizeof(double));
+    L.lsphi = o;
+    o = align_up(o + kLsRow * sizeof(double));
+  }
   L.total = o;
   return L;
 }
 
-ptyg_status check_ws(const ptyg_dims* d, void* ws, size_t ws_bytes, bool joint, Layout* out) {
-  *out = layout(d, joint);
+ptyg_status check_ws(const ptyg_dims* d, void* ws, size_t ws_bytes, bool joint, Layout* out,
+                     bool batched = false) {
+  *out = layout(d, joint, batched);
   if (!ws) return fail(PTYG_E_INVAL, "workspace is NULL");
   if (((uintptr_t)ws) % kAlign) return fail(PTYG_E_INVAL, "workspace not 256-byte aligned");
   if (ws_bytes < out->total)
@@ -133,8 +168,8 @@ struct Timing {
   };
   std::vector<Rec> pending;
   std::vector<hipEvent_t> pool;
-  double ms[2] = {0.0, 0.0};
-  int count[2] = {0, 0};
+  double ms[4] = {0.0, 0.0, 0.0, 0.0};
+  int count[4] = {0, 0, 0, 0};
   hipEvent_t get() {
     if (!pool.empty()) {
       hipEvent_t e = pool.back();
@@ -182,7 +217,7 @@ struct TimedLaunch {
 
 extern "C" {
 
-int32_t ptyg_abi_version(void) { return 1; }
+int32_t ptyg_abi_version(void) { return 2; }
 
 const char* ptyg_status_string(ptyg_status s) {
   switch (s) {
@@ -200,7 +235,11 @@ const char* ptyg_last_error(void) { return g_last_error.c_str(); }
 
 size_t ptyg_workspace_size(const ptyg_dims* dims, const ptyg_cg_opts* opts) {
   if (check_dims(dims) != PTYG_OK) return 0;
-  return layout(dims, opts && opts->update_probe).total;
+  if (opts && opts->line_search != PTYG_LS_SEQUENTIAL && opts->line_search != PTYG_LS_BATCHED) {
+    fail(PTYG_E_INVAL, "line_search=%d is not a PTYG_LS_* value", opts->line_search);
+    return 0;
+  }
+  return layout(dims, opts && opts->update_probe, opts && opts->line_search == PTYG_LS_BATCHED).total;
 }
 
 ptyg_status ptyg_check_positions(const ptyg_dims* dims, const int32_t* pos, void* ws, size_t ws_bytes,
@@ -270,8 +309,11 @@ namespace {
 // The tile lists of `pos` must already be in the workspace.
 ptyg_status run_grad(const ptyg_dims* dims, const float2* obj, const float2* probe, const int2* pos,
                      const float* data, DataLayout lay, float eps, float2* grad_obj, float2* grad_probe,
-                     double* objective, void* ws, const Layout& L, hipStream_t s) {
+                     double* objective, void* ws, const Layout& L, hipStream_t s, float2* gstore = nullptr,
+                     double* gsum = nullptr) {
   PatArgs a = base_args(dims);
+  a.gstore = gstore;
+  if (gstore) a.zs_part = at<double>(ws, L.zparts);
   a.obj = obj;
   a.probe = probe;
   a.pos = pos;
@@ -285,8 +327,12 @@ ptyg_status run_grad(const ptyg_dims* dims, const float2* obj, const float2* pro
     PTYG_HIP(launch_grad(a, lay, &nb, s));
   }
   if (objective) PTYG_HIP(launch_finalize(a.partials, nb, 2, objective, s));
-  PTYG_HIP(launch_tile_sum(a.ubuf, probe, pos, at<int>(ws, L.toff), at<int>(ws, L.tlist), dims->k, dims->obj_h,
-                           dims->obj_w, dims->n, grad_obj, s));
+  if (gstore && gsum) PTYG_HIP(launch_finalize(a.zs_part, nb, 1, gsum, s));
+  {
+    TimedLaunch tl(3, s);
+    PTYG_HIP(launch_tile_sum(a.ubuf, probe, pos, at<int>(ws, L.toff), at<int>(ws, L.tlist), dims->k,
+                             dims->obj_h, dims->obj_w, dims->n, grad_obj, s));
+  }
   if (grad_probe)
     PTYG_HIP(launch_probe_grad(a.ubuf, obj, pos, dims->k, dims->obj_w, dims->n, at<float2>(ws, L.pparts),
                                grad_probe, s));
@@ -363,9 +409,12 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
   if (!(opts->gamma0 > 0.0) || !std::isfinite(opts->gamma0)) return fail(PTYG_E_INVAL, "gamma0 must be > 0");
   if (opts->max_halvings < 1) return fail(PTYG_E_INVAL, "max_halvings must be >= 1");
   if (!(opts->eps >= 0.0)) return fail(PTYG_E_INVAL, "eps must be >= 0");
+  if (opts->line_search != PTYG_LS_SEQUENTIAL && opts->line_search != PTYG_LS_BATCHED)
+    return fail(PTYG_E_INVAL, "line_search=%d is not a PTYG_LS_* value", opts->line_search);
   const bool joint = opts->update_probe != 0;
+  const bool batched = opts->line_search == PTYG_LS_BATCHED;
   Layout L;
-  if (ptyg_status st = check_ws(dims, ws, ws_bytes, joint, &L)) return st;
+  if (ptyg_status st = check_ws(dims, ws, ws_bytes, joint, &L, batched)) return st;
   if (iters_done) *iters_done = 0;
   if (ptyg_status st = ptyg_check_positions(dims, pos_i, ws, ws_bytes, stream)) return st;
 
@@ -383,11 +432,29 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
   double* partials = at<double>(ws, L.partials);
   double* sc = at<double>(ws, L.scalars);
   const float eps = (float)opts->eps;
+  float2* far_a = batched ? at<float2>(ws, L.far_a) : nullptr;  // G psi_m (from the GRAD pass)
+  float2* far_b = batched ? at<float2>(ws, L.far_b) : nullptr;  // first-order far field of the direction
+  float2* far_c = batched && joint ? at<float2>(ws, L.far_c) : nullptr;  // G(eta_p, eta) (joint)
+  double* lsparts = batched ? at<double>(ws, L.lsparts) : nullptr;
+  double* lsphi = batched ? at<double>(ws, L.lsphi) : nullptr;
+  int last_trials = kLsBatch;  // batched search: the previous accepted index sizes the first pass
 
   // the intensities are read by every pass: store them per pattern transposed
   // so that the row-layout reads are coalesced
   PTYG_HIP(launch_transpose_data(data, dt, dims->k, dims->n, s));
   if (ptyg_status st = build_tiles(dims, pos, ws, L, s)) return st;
+  // batched line search: the elements with d > 0 (or NaN) are evaluated per
+  // trial; the d <= 0 ones through the zero-pixel sums
+  int64_t nnz = 0;
+  if (batched) {
+    int* offs = at<int>(ws, L.nz_offsets);
+    PTYG_HIP(launch_nz_compact(dt, (int64_t)dims->k * dims->n * dims->n, at<int>(ws, L.nz_counts), offs,
+                               at<int>(ws, L.nz_idx), s));
+    int h_nnz = 0;
+    PTYG_HIP(hipMemcpyAsync(&h_nnz, offs + L.nz_blocks, sizeof(int), hipMemcpyDeviceToHost, s));
+    PTYG_HIP(hipStreamSynchronize(s));
+    nnz = h_nnz;
+  }
 
   // scalar slots
   enum { PHI = 0, FEQ = 1, N1O = 2, N2O = 3, N1P = 4, N2P = 5, N3O = 6, EEO = 7, N3P = 8, EEP = 9, PHIT = 10 };
@@ -399,7 +466,7 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
   for (int m = 0; m < opts->iters; ++m) {
     // GRAD stage
     if (ptyg_status st = run_grad(dims, obj, probe, pos, dt, DataLayout::Transposed, eps, grad_o, grad_p,
-                                  sc + PHI, ws, L, s))
+                                  sc + PHI, ws, L, s, far_a, batched ? at<double>(ws, L.zsums) : nullptr))
       return st;
     VecArgs v{};
     v.n = on;
@@ -464,7 +531,114 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
     bool accepted = false;
     int trials = 0;
     double eta2 = 0.0, n3 = 0.0;
-    for (int j = 1; j <= opts->max_halvings; ++j) {
+    if (batched) {
+      // far fields of the direction: Phi(psi + g eta [, p + g eta_p]) is the
+      // deviance of A + g B (+ g^2 C), A = G psi stored by the GRAD pass
+      PatArgs fa = base_args(dims);
+      fa.pos = pos;
+      fa.ubuf = at<float2>(ws, L.ubuf);  // staging of the 256^2 transforms
+      fa.far = far_b;
+      double* zparts = at<double>(ws, L.zparts) + L.n_partials;
+      double* zsums = at<double>(ws, L.zsums);
+      fa.zs_p = far_a;  // sums (Re a b*, 0, |b|^2, 0)
+      fa.zs_part = zparts;
+      {
+        TimedLaunch tl_fwd(2, s);
+        if (!joint) {
+          fa.obj = eta_o;
+          fa.probe = probe;
+          PTYG_HIP(launch_fwd_t(fa, false, s));
+        } else {
+          fa.obj = obj;
+          fa.dobj = eta_o;
+          fa.probe = probe;
+          fa.dprobe = eta_p;
+          PTYG_HIP(launch_fwd_t(fa, true, s));
+          PatArgs fc = fa;  // (Re a c*, Re b c*, |c|^2, 0)
+          fc.far = far_c;
+          fc.obj = eta_o;
+          fc.probe = eta_p;
+          fc.dobj = nullptr;
+          fc.dprobe = nullptr;
+          fc.zs_q = far_b;
+          fc.zs_part = zparts + 4 * L.z_blocks;
+          PTYG_HIP(launch_fwd_t(fc, false, s));
+        }
+      }
+      PTYG_HIP(launch_finalize(zparts, (int)L.z_blocks, 4, zsums + 4, s));
+      if (joint) PTYG_HIP(launch_finalize(zparts + 4 * L.z_blocks, (int)L.z_blocks, 4, zsums + 8, s));
+      LsArgs la{};
+      la.A = far_a;
+      la.B = far_b;
+      la.C = far_c;
+      la.d = dt;
+      la.idx = at<int>(ws, L.nz_idx);
+      la.n = nnz;
+      la.eps = eps;
+      // whole-array sums: [0] |a|^2 (GRAD), [4..7] direction pass, [8..11] joint pass
+      double zs[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      double zc[6] = {0, 0, 0, 0, 0, 0};  // d <= 0 parts: aa, ab, bb, ac, bc, cc
+      la.partials = lsparts;
+      int j0 = 1;
+      bool first = true;
+      double g_run = opts->gamma0;
+      while (j0 <= opts->max_halvings && !accepted) {
+        // the first pass covers up to two trials past the previous accepted index
+        int J = std::min(kLsBatch, opts->max_halvings - j0 + 1);
+        if (first) J = std::min(J, std::max(4, last_trials + 2));
+        double gam[kLsBatch];
+        for (int i = 0; i < J; ++i) {
+          g_run *= opts->tau;  // the same sequence of doubles as the sequential search
+          gam[i] = g_run;
+          la.g[i] = (float)g_run;
+        }
+        la.J = J;
+        int nb = 0;
+        {
+          TimedLaunch tl(1, s);
+          PTYG_HIP(launch_ls_batch(la, &nb, s));
+        }
+        PTYG_HIP(launch_ls_finalize(lsparts, nb, lsphi, s));
+        double phis[kLsRow];
+        PTYG_HIP(hipMemcpyAsync(phis, lsphi, kLsRow * sizeof(double), hipMemcpyDeviceToHost, s));
+        if (first) {
+          PTYG_HIP(hipMemcpyAsync(h + N3O, sc + N3O, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
+          PTYG_HIP(hipMemcpyAsync(zs, zsums, 12 * sizeof(double), hipMemcpyDeviceToHost, s));
+        }
+        PTYG_HIP(hipStreamSynchronize(s));
+        if (first) {
+          n3 = h[N3O] + (joint ? h[N3P] : 0.0);
+          eta2 = h[EEO] + (joint ? h[EEP] : 0.0);
+          // whole-array sums minus the listed elements' shares (the same FP32
+          // values summed in FP64): the d <= 0 parts
+          const double* sh = phis + kLsBatch;
+          zc[0] = zs[0] - sh[0];
+          zc[1] = zs[4] - sh[1];
+          zc[2] = zs[6] - sh[2];
+          if (joint) {
+            zc[3] = zs[8] - sh[3];
+            zc[4] = zs[9] - sh[4];
+            zc[5] = zs[10] - sh[5];
+          }
+        }
+        for (int i = 0; i < J; ++i) {
+          trials = j0 + i;
+          gamma = gam[i];
+          // d <= 0 pixels: sum |a + g b + g^2 c|^2 at the trial's FP32 step
+          const double g = (double)la.g[i];
+          double zero = zc[0] + 2.0 * g * zc[1] + g * g * zc[2];
+          if (joint) zero += 2.0 * g * g * zc[3] + 2.0 * g * g * g * zc[4] + g * g * g * g * zc[5];
+          if (phis[i] + zero <= phi_m + gamma * opts->t) {
+            accepted = true;
+            break;
+          }
+        }
+        j0 += J;
+        first = false;
+      }
+      if (accepted) last_trials = trials;
+    }
+    for (int j = 1; !batched && j <= opts->max_halvings; ++j) {
       gamma *= opts->tau;
       trials = j;
       if (ptyg_status st = run_minfunc(dims, obj, eta_o, probe, eta_p, gamma, pos, dt, DataLayout::Transposed,
@@ -521,12 +695,14 @@ void ptyg_timing_enable(int32_t on) { g_timing.on = on != 0; }
 
 void ptyg_timing_reset(void) {
   g_timing.drain();
-  g_timing.ms[0] = g_timing.ms[1] = 0.0;
-  g_timing.count[0] = g_timing.count[1] = 0;
+  for (int i = 0; i < 4; ++i) {
+    g_timing.ms[i] = 0.0;
+    g_timing.count[i] = 0;
+  }
 }
 
 ptyg_status ptyg_timing_read(double* ms, int32_t* count, int32_t kinds) {
-  if (!ms || !count || kinds < 0 || kinds > 2) return fail(PTYG_E_INVAL, "bad timing arguments");
+  if (!ms || !count || kinds < 0 || kinds > 4) return fail(PTYG_E_INVAL, "bad timing arguments");
   g_timing.drain();
   for (int i = 0; i < kinds; ++i) {
     ms[i] = g_timing.ms[i];

@@ -54,6 +54,26 @@ __device__ __forceinline__ void block_sum2(double& a, double& b, double* red) {
   }
 }
 
+// Block-wide sums of four doubles written to out[0..3] by thread 0.
+template <int WG>
+__device__ __forceinline__ void block_sum4_store(double (&v)[4], double* red, double* out) {
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_xor(v[i], off);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0)
+#pragma unroll
+    for (int i = 0; i < 4; ++i) red[4 * w + i] = v[i];
+  __syncthreads();
+  if (threadIdx.x < 4) {
+    double t = 0.0;
+#pragma unroll
+    for (int i = 0; i < WG / 64; ++i) t += red[4 * i + threadIdx.x];
+    out[threadIdx.x] = t;
+  }
+}
+
 // Addressing: every global access is written as a pointer that is uniform
 // across the wave (computed from the pattern index and a compile-time slot
 // offset) plus a 32-bit lane offset, so the loads use the scalar-base form
@@ -216,7 +236,95 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_adjoint(PatArgs a) {
   store_u<N>(v, a, L, k, valid);
 }
 
-template <int N, DataLayout LAY>
+// Exit-wave direction p * eta + dp * psi (first-order term of the joint
+// trial (p + g dp)(psi + g eta)), column-layout spatial slots: the p * eta
+// gather, then dp * psi added in chunks.
+template <int N>
+__device__ __forceinline__ void gather_lin(float2* v, const PatArgs& a, const Lane& L, int2 rc, bool valid) {
+  using G = Geo<N>;
+  constexpr int T = G::TPC;
+  PatArgs b = a;
+  b.obj = a.dobj;
+  gather_exit_wave<N, false, false>(v, b, L, rc, valid);
+  const uint32_t lo = lane_off<N>(L, (uint32_t)a.W);
+  const uint32_t plo = lane_off<N>(L, N);
+  const size_t corner = (size_t)rc.x * a.W + rc.y;
+#pragma unroll
+  for (int c = 0; c < G::E; c += kChunk) {
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int m = c; m < c + kChunk; ++m) {
+      const float2 o = (a.obj + corner + (size_t)(m * T) * a.W)[lo];
+      float2 dp = (a.dprobe + m * T * N)[plo];
+      if (!valid) dp = make_float2(0.f, 0.f);
+      v[m] = cadd(v[m], cmul(dp, o));
+    }
+  }
+  __builtin_amdgcn_sched_barrier(0);
+}
+
+// Forward transform of a direction, stored per pattern transposed (the
+// element order of the transposed intensities and of the stored G psi).
+// ZS: also the sums over this workgroup's elements of Re(P conj y),
+// Re(Q conj y) (Q nullable) and |y|^2 (P = a.zs_p, Q = a.zs_q stored far
+// fields, y = the result).  They are formed before any store: loads wait on
+// every earlier memory operation, stores included.
+template <int N, bool LIN, int ZS>
+__global__ PTYG_PATTERN_KERNEL(N) void k_fwd_t(PatArgs a) {
+  using G = Geo<N>;
+  __shared__ float2 lds[G::LDS_ELEMS];
+  __shared__ double red[4 * (G::WG / 64)];
+  const Lane L = lane_info<N>();
+  int k;
+  bool valid;
+  int2 rc;
+  if (!pattern_of<N>(a, L, k, valid, rc)) {
+    if (ZS > 0 && threadIdx.x < 4) a.zs_part[4 * blockIdx.x + threadIdx.x] = 0.0;
+    return;
+  }
+  float2 v[G::E];
+  if constexpr (LIN) gather_lin<N>(v, a, L, rc, valid);
+  else gather_exit_wave<N, false, false>(v, a, L, rc, valid);
+  fwd_line<N>(v, L.h);
+  transpose_c2r<N>(v, lds, L);
+  fwd_line<N>(v, L.h);
+  const float invN = 1.0f / N;
+  const size_t kb = (size_t)k * N * N;
+  const uint32_t lo = lane_off<N>(L, (G::E / 2) * N);
+#pragma unroll
+  for (int s = 0; s < G::E; ++s) v[s] = cscale(v[s], invN);
+  if constexpr (ZS > 0) {
+    // lanes of a missing pattern hold y = 0 (zero probe): no masking needed
+    double z[4] = {0.0, 0.0, 0.0, 0.0};
+    constexpr int CH = ZS == 1 ? 8 : 4;
+#pragma unroll
+    for (int c = 0; c < G::E; c += CH) {
+      __builtin_amdgcn_sched_barrier(0);
+      float2 P[CH], Q[CH];
+#pragma unroll
+      for (int s = c; s < c + CH; ++s) {
+        const size_t off = kb + (size_t)kFreq<N>.f[s] * N;
+        P[s - c] = (a.zs_p + off)[lo];
+        if constexpr (ZS == 2) Q[s - c] = (a.zs_q + off)[lo];
+      }
+#pragma unroll
+      for (int s = c; s < c + CH; ++s) {
+        const float2 y = v[s];
+        z[0] += (double)P[s - c].x * y.x + (double)P[s - c].y * y.y;
+        if constexpr (ZS == 2) z[1] += (double)Q[s - c].x * y.x + (double)Q[s - c].y * y.y;
+        z[2] += (double)y.x * y.x + (double)y.y * y.y;
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    block_sum4_store<G::WG>(z, red, a.zs_part + 4 * blockIdx.x);
+  }
+  if (G::PPW == 1 || valid) {
+#pragma unroll
+    for (int s = 0; s < G::E; ++s) (a.far + kb + (size_t)kFreq<N>.f[s] * N)[lo] = v[s];
+  }
+}
+
+template <int N, DataLayout LAY, bool SG>
 __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
   using G = Geo<N>;
   __shared__ float2 lds[G::LDS_ELEMS];
@@ -227,6 +335,7 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
   int2 rc;
   if (!pattern_of<N>(a, L, k, valid, rc)) {
     write_zero_partials(a);
+    if (SG && threadIdx.x == 0) a.zs_part[blockIdx.x] = 0.0;
     return;
   }
   float2 v[G::E];
@@ -235,13 +344,30 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
   transpose_c2r<N>(v, lds, L);
   fwd_line<N>(v, L.h);
   const float invN = 1.0f / N;
-  double acc_phi = 0.0, acc_f = 0.0;
+  double acc_phi = 0.0, acc_f = 0.0, acc_aa = 0.0;
+  if constexpr (SG) {
+    // G psi for the batched line search, in the element order of the
+    // transposed intensities, with sum |G psi|^2.  All stores go out before
+    // the intensity loads below: a load waits on every earlier memory
+    // operation, so stores interleaved with the loads would add a wait each.
+    // (Lanes of a missing pattern hold 0: zero probe.)
+    const uint32_t lo = lane_off<N>(L, (G::E / 2) * N);
+    float2* gk = a.gstore + (size_t)k * N * N;
+#pragma unroll
+    for (int s = 0; s < G::E; ++s) {
+      if (s % 8 == 0) __builtin_amdgcn_sched_barrier(0);
+      v[s] = cscale(v[s], invN);  // scaled in place: v now holds G psi
+      acc_aa += (double)v[s].x * v[s].x + (double)v[s].y * v[s].y;
+      if (G::PPW == 1 || valid) (gk + (size_t)kFreq<N>.f[s] * N)[lo] = v[s];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  }
 #pragma unroll
   for (int s = 0; s < G::E; ++s) {
     if (s % kResChunk == 0) __builtin_amdgcn_sched_barrier(0);
     const int b = fidx<N>(s, L.h);
     const float d = load_data<N, LAY>(a.data, k, L, s);
-    const float2 g = cscale(v[s], invN);
+    const float2 g = SG ? v[s] : cscale(v[s], invN);
     const float x = fmaf(g.x, g.x, g.y * g.y);
     float phi, ft, fac;
     pixel_terms<true>(x, d, a.eps, phi, ft, fac);
@@ -252,7 +378,7 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
   // The sums are only consumed by the final reduction; without this the
   // compiler sinks the objective terms past the inverse transform and keeps
   // every pixel's (x, d) alive across it.
-  asm volatile("" : "+v"(acc_phi), "+v"(acc_f));
+  asm volatile("" : "+v"(acc_phi), "+v"(acc_f), "+v"(acc_aa));
   inv_line<N>(v, L.h);
   transpose_r2c<N>(v, lds, L);
   inv_line<N>(v, L.h);
@@ -265,6 +391,12 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
   if (threadIdx.x == 0) {
     a.partials[2 * blockIdx.x] = acc_phi;
     a.partials[2 * blockIdx.x + 1] = acc_f;
+  }
+  if constexpr (SG) {
+    double zero = 0.0;
+    __syncthreads();
+    block_sum2<G::WG>(acc_aa, zero, red);
+    if (threadIdx.x == 0) a.zs_part[blockIdx.x] = acc_aa;
   }
 }
 
@@ -663,6 +795,116 @@ __global__ __launch_bounds__(kVecWG) void k_sum_copies(const float2* src, int co
   }
 }
 
+// Batched line search (linearity of G): trial j's far field is
+// A + g_j B (+ g_j^2 C), evaluated with the same per-pixel deviance as a
+// MINFUNC pass for every listed element (d > 0 or NaN), FP64 accumulation
+// per trial, per-workgroup partials in a fixed order.
+template <bool QUAD>
+__global__ __launch_bounds__(256) void k_ls_batch(LsArgs a) {
+  __shared__ double red[4][kLsRow];
+  double acc[kLsRow];
+#pragma unroll
+  for (int j = 0; j < kLsRow; ++j) acc[j] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * 256) {
+    const int e = a.idx[i];
+    const float2 av = a.A[e], bv = a.B[e];
+    float2 cv = make_float2(0.f, 0.f);
+    if constexpr (QUAD) cv = a.C[e];
+    const float dv = a.d[e];
+    // this element's share of the whole-array sums (the rest is d <= 0)
+    acc[kLsBatch + 0] += (double)av.x * av.x + (double)av.y * av.y;
+    acc[kLsBatch + 1] += (double)av.x * bv.x + (double)av.y * bv.y;
+    acc[kLsBatch + 2] += (double)bv.x * bv.x + (double)bv.y * bv.y;
+    if constexpr (QUAD) {
+      acc[kLsBatch + 3] += (double)av.x * cv.x + (double)av.y * cv.y;
+      acc[kLsBatch + 4] += (double)bv.x * cv.x + (double)bv.y * cv.y;
+      acc[kLsBatch + 5] += (double)cv.x * cv.x + (double)cv.y * cv.y;
+    }
+#pragma unroll
+    for (int j = 0; j < kLsBatch; ++j) {
+      if (j < a.J) {
+        const float gm = a.g[j];
+        float xr = fmaf(gm, bv.x, av.x), xi = fmaf(gm, bv.y, av.y);
+        if constexpr (QUAD) {
+          const float g2 = gm * gm;
+          xr = fmaf(g2, cv.x, xr);
+          xi = fmaf(g2, cv.y, xi);
+        }
+        float phi, ft, fac;
+        pixel_terms<false>(fmaf(xr, xr, xi * xi), dv, a.eps, phi, ft, fac);
+        acc[j] += (double)phi;
+      }
+    }
+  }
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+  for (int j = 0; j < kLsRow; ++j) {
+    double v = acc[j];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off);
+    if (l == 0) red[w][j] = v;
+  }
+  __syncthreads();
+  if (threadIdx.x < kLsRow)
+    a.partials[(size_t)blockIdx.x * kLsRow + threadIdx.x] =
+        red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+}
+
+// Compaction of the elements with !(d <= 0): per-block counts, then the
+// indices in ascending order (wave ballots, waves in order, 256-element rounds).
+__global__ __launch_bounds__(256) void k_nz_count(const float* __restrict__ d, int64_t n, int* counts) {
+  __shared__ int red[4];
+  const int64_t base = (int64_t)blockIdx.x * kNzChunk;
+  int c = 0;
+  for (int r = 0; r < kNzChunk / 256; ++r) {
+    const int64_t e = base + r * 256 + threadIdx.x;
+    c += (e < n && !(d[e] <= 0.0f)) ? 1 : 0;
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) counts[blockIdx.x] = red[0] + red[1] + red[2] + red[3];
+}
+
+__global__ __launch_bounds__(256) void k_nz_fill(const float* __restrict__ d, int64_t n,
+                                                 const int* __restrict__ offsets, int* __restrict__ idx) {
+  __shared__ int wcnt[4];
+  const int64_t base = (int64_t)blockIdx.x * kNzChunk;
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  const uint64_t below = (l == 0) ? 0ull : (~0ull >> (64 - l));
+  int run = offsets[blockIdx.x];
+  for (int r = 0; r < kNzChunk / 256; ++r) {
+    const int64_t e = base + r * 256 + threadIdx.x;
+    const bool nz = e < n && !(d[e] <= 0.0f);
+    const uint64_t m = __ballot(nz);
+    if (l == 0) wcnt[w] = __popcll(m);
+    __syncthreads();
+    int pre = 0;
+    for (int i = 0; i < w; ++i) pre += wcnt[i];
+    if (nz) idx[run + pre + __popcll(m & below)] = (int)e;
+    run += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
+    __syncthreads();
+  }
+}
+
+// out[j] = sum over rows (in order) of partials[row][j]; one workgroup per j.
+__global__ __launch_bounds__(256) void k_ls_finalize(const double* partials, int count, double* out) {
+  __shared__ double red[256];
+  const int j = blockIdx.x;
+  const int per = (count + 255) / 256;
+  const int lo = threadIdx.x * per, hi = min(count, lo + per);
+  double acc = 0.0;
+  for (int i = lo; i < hi; ++i) acc += partials[(size_t)i * kLsRow + j];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[j] = red[0];
+}
+
 // In-order reduction of `count` rows of `width` (<= 4) doubles, one workgroup.
 __global__ __launch_bounds__(256) void k_finalize(const double* partials, int count, int width, double* out) {
   __shared__ double red[256 * 4];
@@ -722,16 +964,81 @@ hipError_t launch_adjoint(const PatArgs& a, hipStream_t s) {
 
 hipError_t launch_grad(const PatArgs& a, DataLayout lay, int* blocks_out, hipStream_t s) {
   if (!a.ubuf || !a.data || !a.partials || !a.obj || !a.probe || !a.pos) return hipErrorInvalidValue;
+  if (a.gstore && lay != DataLayout::Transposed) return hipErrorInvalidValue;
   if (a.N == 256) return launch_grad256(a, lay, blocks_out, s);
   return dispatch_n(a.N, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
     const int nb = pattern_blocks<N>(a.K);
     if (blocks_out) *blocks_out = nb;
     const dim3 g(nb), b(Geo<N>::WG);
-    if (lay == DataLayout::Transposed) hipLaunchKernelGGL((k_grad<N, DataLayout::Transposed>), g, b, 0, s, a);
-    else hipLaunchKernelGGL((k_grad<N, DataLayout::Rows>), g, b, 0, s, a);
+    if (lay == DataLayout::Transposed) {
+      if (a.gstore) hipLaunchKernelGGL((k_grad<N, DataLayout::Transposed, true>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((k_grad<N, DataLayout::Transposed, false>), g, b, 0, s, a);
+    } else {
+      hipLaunchKernelGGL((k_grad<N, DataLayout::Rows, false>), g, b, 0, s, a);
+    }
     return hipGetLastError();
   });
+}
+
+hipError_t launch_fwd_t(const PatArgs& a, bool lin, hipStream_t s) {
+  if (!a.far || !a.obj || !a.probe || !a.pos) return hipErrorInvalidValue;
+  if (lin && (!a.dobj || !a.dprobe)) return hipErrorInvalidValue;
+  const bool zs = a.zs_part != nullptr;
+  if (zs && !a.zs_p) return hipErrorInvalidValue;
+  if (a.N == 256) return launch_fwd_t256(a, lin, s);
+  return dispatch_n(a.N, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    const dim3 g(pattern_blocks<N>(a.K)), b(Geo<N>::WG);
+    const int z = zs ? (a.zs_q ? 2 : 1) : 0;
+    if (lin) {
+      if (z == 1) hipLaunchKernelGGL((k_fwd_t<N, true, 1>), g, b, 0, s, a);
+      else if (z == 2) hipLaunchKernelGGL((k_fwd_t<N, true, 2>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((k_fwd_t<N, true, 0>), g, b, 0, s, a);
+    } else {
+      if (z == 1) hipLaunchKernelGGL((k_fwd_t<N, false, 1>), g, b, 0, s, a);
+      else if (z == 2) hipLaunchKernelGGL((k_fwd_t<N, false, 2>), g, b, 0, s, a);
+      else hipLaunchKernelGGL((k_fwd_t<N, false, 0>), g, b, 0, s, a);
+    }
+    return hipGetLastError();
+  });
+}
+
+int fwd_t_blocks(int N, int K) {
+  if (N == 256) return fwd_t256_blocks(K);
+  int nb = 0;
+  dispatch_n(N, [&](auto nc) {
+    nb = pattern_blocks<decltype(nc)::value>(K);
+    return hipSuccess;
+  });
+  return nb;
+}
+
+hipError_t launch_nz_compact(const float* d, int64_t n, int* counts, int* offsets, int* idx, hipStream_t s) {
+  if (!d || !counts || !offsets || !idx || n < 1) return hipErrorInvalidValue;
+  const int64_t blocks = (n + kNzChunk - 1) / kNzChunk;
+  if (blocks > (1 << 30)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_nz_count, dim3((unsigned)blocks), dim3(256), 0, s, d, n, counts);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, (int)blocks, offsets);
+  hipLaunchKernelGGL(k_nz_fill, dim3((unsigned)blocks), dim3(256), 0, s, d, n, offsets, idx);
+  return hipGetLastError();
+}
+
+hipError_t launch_ls_batch(const LsArgs& a, int* blocks_out, hipStream_t s) {
+  if (!a.A || !a.B || !a.d || !a.idx || !a.partials || a.n < 0 || a.J < 1 || a.J > kLsBatch)
+    return hipErrorInvalidValue;
+  const int64_t want = (a.n + 255) / 256;
+  const int nb = (int)(want < 1 ? 1 : (want < kLsBlocks ? want : kLsBlocks));
+  if (blocks_out) *blocks_out = nb;
+  if (a.C) hipLaunchKernelGGL(k_ls_batch<true>, dim3(nb), dim3(256), 0, s, a);
+  else hipLaunchKernelGGL(k_ls_batch<false>, dim3(nb), dim3(256), 0, s, a);
+  return hipGetLastError();
+}
+
+hipError_t launch_ls_finalize(const double* partials, int count, double* out, hipStream_t s) {
+  if (!partials || !out || count < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_ls_finalize, dim3(kLsRow), dim3(256), 0, s, partials, count, out);
+  return hipGetLastError();
 }
 
 hipError_t launch_minfunc(const PatArgs& a, DataLayout lay, int* blocks_out, hipStream_t s) {

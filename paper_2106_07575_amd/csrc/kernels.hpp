@@ -23,9 +23,41 @@ struct PatArgs {
   float2* ubuf;          // per-pattern back-propagated waves u_k = F^H r_k, [K][N][N]
   double* partials;      // per-workgroup (phi, f) pairs
   float eps;
+  float2* gstore;        // GRAD: far field G psi, per-pattern transposed (batched line search); nullable
+  // batched line search: GRAD with gstore writes per-workgroup sums of
+  // |G psi|^2 to zs_part; the direction forward writes rows of 4:
+  // sum Re(P conj y), sum Re(Q conj y) (0 if Q is null), sum |y|^2, 0
+  // (y = its far field; P, Q stored far fields in the same element order)
+  const float2* zs_p;
+  const float2* zs_q;
+  double* zs_part;
 };
 
-// Object-sized vector kernels (complex64 arrays of length n).
+// Batched line search over stored far fields: trial j evaluates the
+// deviance at A + g_j B (+ g_j^2 C in joint mode) against the intensities d,
+// all four arrays in the same per-pattern element order, over the elements
+// listed in idx (those with d > 0 or NaN; the d <= 0 ones contribute
+// |A + g B + g^2 C|^2, a polynomial in g formed from the zero-pixel sums).
+constexpr int kLsBatch = 16;   // trials per pass
+// Per-block row: kLsBatch trial sums, then the listed elements' shares of
+// sum |A|^2, Re A B*, |B|^2, Re A C*, Re B C*, |C|^2, and padding.
+constexpr int kLsRow = kLsBatch + 8;
+constexpr int kLsBlocks = 4096;
+struct LsArgs {
+  const float2* A;
+  const float2* B;
+  const float2* C;  // joint mode only (else null)
+  const float* d;
+  const int* idx;   // compacted element indices
+  int64_t n;        // number of listed elements
+  int J;            // trials in this pass, 1..kLsBatch
+  float eps;
+  float g[kLsBatch];
+  double* partials;  // [blocks][kLsRow]
+};
+// Elements per block of the compaction of the d > 0 elements.
+constexpr int kNzChunk = 4096;
+
 struct VecArgs {
   int64_t n;
   float2* a;
@@ -73,6 +105,22 @@ constexpr int kProbeChunks = 64;
 hipError_t launch_probe_grad(const float2* ubuf, const float2* obj, const int2* pos, int K, int W, int N,
                              float2* partial, float2* out, hipStream_t s);
 hipError_t launch_minfunc(const PatArgs& a, DataLayout lay, int* blocks_out, hipStream_t s);
+// far (per-pattern transposed) = G applied to the direction: lin = false:
+// F(probe * obj[pos]); lin = true: F(probe * dobj[pos] + dprobe * obj[pos])
+// (the first-order term of (p + g dp)(psi + g eta)).
+hipError_t launch_fwd_t(const PatArgs& a, bool lin, hipStream_t s);
+hipError_t launch_fwd_t256(const PatArgs& a, bool lin, hipStream_t s);
+int fwd_t256_blocks(int K);
+// Objective partials of a.J trials; `blocks_out` rows of kLsRow doubles.
+hipError_t launch_ls_batch(const LsArgs& a, int* blocks_out, hipStream_t s);
+// idx = ascending indices e < n with !(d[e] <= 0), count in offsets[blocks]
+// (blocks = ceil(n / kNzChunk); offsets holds blocks + 1 ints, counts
+// blocks ints of scratch).
+hipError_t launch_nz_compact(const float* d, int64_t n, int* counts, int* offsets, int* idx, hipStream_t s);
+// Zero-pixel sums of the direction forward: rows of 4 doubles per block.
+int fwd_t_blocks(int N, int K);
+// out[j] = in-order sum over `count` rows of partials[row][j], j < kLsRow.
+hipError_t launch_ls_finalize(const double* partials, int count, double* out, hipStream_t s);
 hipError_t launch_transpose_data(const float* d, float* dt, int K, int N, hipStream_t s);
 hipError_t launch_debug_gather(const PatArgs& a, float2* patches, hipStream_t s);
 hipError_t launch_debug_scatter(const PatArgs& a, const float2* patches, hipStream_t s);

@@ -35,12 +35,31 @@ __device__ __forceinline__ float2 w256(int e, int sign) {
   return make_float2(kTwCosDev[e & 255], sign * kTwSinDev[e & 255]);
 }
 
-// Gather the (p, q) sub-grid of (p + gamma dp) * (psi + gamma eta) patch k.
-template <bool LINC_O, bool LINC_P>
+// Gather the (p, q) sub-grid of (p + gamma dp) * (psi + gamma eta) patch k,
+// or with LIN of the first-order direction term p * eta + dp * psi.
+template <bool LINC_O, bool LINC_P, bool LIN = false>
 __device__ __forceinline__ void gather_sub(float2* v, const PatArgs& a, const Lane& L, int2 rc, int p, int q) {
   // slot m -> sub-row u' = 2m + h, sub-col v' = line -> patch (2u' + p, 2v' + q)
   const uint32_t lo = (L.h ? 2u * (uint32_t)a.W : 0u) + 2u * (uint32_t)L.line;
   const size_t corner = (size_t)(rc.x + p) * a.W + rc.y + q;
+  if constexpr (LIN) {
+    const uint32_t plo = (L.h ? 2u * NB : 0u) + 2u * (uint32_t)L.line;
+    const float2* pb = a.probe + p * NB + q;
+    const float2* dpb = a.dprobe + p * NB + q;
+#pragma unroll
+    for (int c = 0; c < G::E; c += 8) {
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int m = c; m < c + 8; ++m) {
+        const size_t row = corner + (size_t)(4 * m) * a.W;
+        const float2 o = (a.obj + row)[lo], e = (a.dobj + row)[lo];
+        const float2 pr = (pb + 4 * m * NB)[plo], dp = (dpb + 4 * m * NB)[plo];
+        v[m] = cadd(cmul(pr, e), cmul(dp, o));
+      }
+    }
+    __builtin_amdgcn_sched_barrier(0);
+    return;
+  }
 #pragma unroll
   for (int c = 0; c < G::E; c += 16) {
     __builtin_amdgcn_sched_barrier(0);
@@ -76,7 +95,7 @@ __device__ __forceinline__ void gather_sub(float2* v, const PatArgs& a, const La
 
 // U layout per pattern: [pq][b][a] for Y / R (transposed sub-grids, coalesced
 // for the row layout), [pq][u'][v'] for u (natural sub-grids).
-template <bool LINC_O, bool LINC_P>
+template <bool LINC_O, bool LINC_P, bool LIN = false>
 __global__ PTYG_SUB_KERNEL void k_sub_fwd(PatArgs a) {
   __shared__ float2 lds[G::LDS_ELEMS];
   const int blk = blockIdx.x;
@@ -85,7 +104,7 @@ __global__ PTYG_SUB_KERNEL void k_sub_fwd(PatArgs a) {
   const Lane L = lane_info<NS>();
   const int2 rc = a.pos[k];
   float2 v[G::E];
-  gather_sub<LINC_O, LINC_P>(v, a, L, rc, p, q);
+  gather_sub<LINC_O, LINC_P, LIN>(v, a, L, rc, p, q);
   fwd_line<NS>(v, L.h);
   transpose_c2r<NS>(v, lds, L);
   fwd_line<NS>(v, L.h);
@@ -122,8 +141,9 @@ __global__ PTYG_SUB_KERNEL void k_sub_inv(PatArgs a) {
 // objective only.  MODE 3: adjoint of a given far field (writes R).
 template <int MODE, DataLayout LAY>
 __global__ __launch_bounds__(256) void k_combine(PatArgs a, int64_t items) {
-  __shared__ double red[8];
+  __shared__ double red[16];
   double acc_phi = 0.0, acc_f = 0.0;
+  double z[4] = {0.0, 0.0, 0.0, 0.0};  // with a.zs_part: MODE 0 direction sums, MODE 1 sum |G psi|^2
   const float inv = 1.0f / NB;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < items; i += (int64_t)gridDim.x * 256) {
     const int ai = (int)(i & 127), bi = (int)((i >> 7) & 127);
@@ -144,10 +164,29 @@ __global__ __launch_bounds__(256) void k_combine(PatArgs a, int64_t items) {
       g[3] = cscale(csub(s1, e1), inv);  // al 1 be 1
     }
     if constexpr (MODE == 0) {
+      // Rows: far [k][A][B]; Transposed: per pattern [B][A] (the order of
+      // the transposed intensities, for the batched line search)
+      if (LAY == DataLayout::Transposed && a.zs_part) {
+        // sums Re(P conj y), Re(Q conj y), |y|^2, loaded before the stores
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int A = ai + 128 * (j >> 1), B = bi + 128 * (j & 1);
+          const size_t e = (size_t)k * NB * NB + (size_t)B * NB + A;
+          const float2 P = a.zs_p[e], y = g[j];
+          z[0] += (double)P.x * y.x + (double)P.y * y.y;
+          if (a.zs_q) {
+            const float2 Q = a.zs_q[e];
+            z[1] += (double)Q.x * y.x + (double)Q.y * y.y;
+          }
+          z[2] += (double)y.x * y.x + (double)y.y * y.y;
+        }
+      }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int A = ai + 128 * (j >> 1), B = bi + 128 * (j & 1);
-        a.far[(size_t)k * NB * NB + (size_t)A * NB + B] = g[j];
+        const size_t e = (size_t)k * NB * NB +
+                         ((LAY == DataLayout::Transposed) ? (size_t)B * NB + A : (size_t)A * NB + B);
+        a.far[e] = g[j];
       }
       continue;
     }
@@ -164,6 +203,12 @@ __global__ __launch_bounds__(256) void k_combine(PatArgs a, int64_t items) {
         const int A = ai + 128 * (j >> 1), B = bi + 128 * (j & 1);
         const float d = (LAY == DataLayout::Transposed) ? a.data[(size_t)k * NB * NB + (size_t)B * NB + A]
                                                         : a.data[(size_t)k * NB * NB + (size_t)A * NB + B];
+        if constexpr (MODE == 1 && LAY == DataLayout::Transposed) {
+          if (a.gstore) {
+            a.gstore[(size_t)k * NB * NB + (size_t)B * NB + A] = g[j];
+            z[0] += (double)g[j].x * g[j].x + (double)g[j].y * g[j].y;
+          }
+        }
         const float x = fmaf(g[j].x, g[j].x, g[j].y * g[j].y);
         float phi, ft, fac;
         pixel_terms<MODE == 1 || LAY == DataLayout::Rows>(x, d, a.eps, phi, ft, fac);
@@ -184,6 +229,24 @@ __global__ __launch_bounds__(256) void k_combine(PatArgs a, int64_t items) {
       y[SUB] = cscale(cmul(w256(bi, +1), r01), inv);
       y[2 * SUB] = cscale(cmul(w256(ai, +1), r10), inv);
       y[3 * SUB] = cscale(cmul(w256(ai + bi, +1), r11), inv);
+    }
+  }
+  if constexpr ((MODE == 0 || MODE == 1) && LAY == DataLayout::Transposed) {
+    if (a.zs_part && (MODE == 0 || a.gstore)) {
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) z[i] += __shfl_xor(z[i], off);
+      if ((threadIdx.x & 63) == 0)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) red[4 * (threadIdx.x >> 6) + i] = z[i];
+      __syncthreads();
+      const double t = (threadIdx.x < 4) ? red[threadIdx.x] + red[4 + threadIdx.x] + red[8 + threadIdx.x] +
+                                                 red[12 + threadIdx.x]
+                                           : 0.0;
+      if (MODE == 0 && threadIdx.x < 4) a.zs_part[4 * blockIdx.x + threadIdx.x] = t;
+      if (MODE == 1 && threadIdx.x == 0) a.zs_part[blockIdx.x] = t;
+      __syncthreads();  // red is reused by the objective reduction below
     }
   }
   if constexpr (MODE == 1 || MODE == 2) {
@@ -269,6 +332,18 @@ hipError_t launch_grad256(const PatArgs& a, DataLayout lay, int* blocks_out, hip
   if (hipError_t e = sub_fwd(b, s)) return e;
   if (hipError_t e = combine<1>(b, lay, blocks_out, s)) return e;
   return sub_inv(b, s);
+}
+
+int fwd_t256_blocks(int K) { return combine_blocks(K); }
+
+hipError_t launch_fwd_t256(const PatArgs& a, bool lin, hipStream_t s) {
+  if (!staged_ok(a) || !a.far || !a.obj || !a.probe) return hipErrorInvalidValue;
+  if (lin && (!a.dobj || !a.dprobe)) return hipErrorInvalidValue;
+  const dim3 g(4 * a.K), b(G::WG);
+  if (lin) hipLaunchKernelGGL((k_sub_fwd<false, false, true>), g, b, 0, s, a);
+  else hipLaunchKernelGGL((k_sub_fwd<false, false>), g, b, 0, s, a);
+  if (hipError_t e = hipGetLastError()) return e;
+  return combine<0>(a, DataLayout::Transposed, nullptr, s);
 }
 
 hipError_t launch_minfunc256(const PatArgs& a, DataLayout lay, int* blocks_out, hipStream_t s) {

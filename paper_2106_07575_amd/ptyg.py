@@ -37,7 +37,10 @@ class CgOpts(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("update_probe", ctypes.c_int32),
                 ("gamma0", ctypes.c_double), ("tau", ctypes.c_double), ("t", ctypes.c_double),
                 ("max_halvings", ctypes.c_int32), ("eps", ctypes.c_double),
-                ("target_phi", ctypes.c_double)]
+                ("target_phi", ctypes.c_double), ("line_search", ctypes.c_int32)]
+
+
+LINE_SEARCH = {"sequential": 0, "batched": 1}
 
 
 class IterStats(ctypes.Structure):
@@ -137,17 +140,18 @@ def dims_of(obj_shape, n: int, k: int) -> Dims:
     return Dims(int(obj_shape[0]), int(obj_shape[1]), int(n), int(k))
 
 
-def workspace_size(dims: Dims, update_probe: bool = False) -> int:
+def workspace_size(dims: Dims, update_probe: bool = False, line_search: str = "sequential") -> int:
     o = CgOpts()
     o.update_probe = int(update_probe)
+    o.line_search = LINE_SEARCH[line_search]
     sz = load().ptyg_workspace_size(ctypes.byref(dims), ctypes.byref(o))
     if sz == 0:
         raise PtygError(-1, load().ptyg_last_error().decode())
     return sz
 
 
-def workspace(dims: Dims, device, update_probe: bool = False) -> torch.Tensor:
-    return torch.empty(workspace_size(dims, update_probe), dtype=torch.uint8, device=device)
+def workspace(dims: Dims, device, update_probe: bool = False, line_search: str = "sequential") -> torch.Tensor:
+    return torch.empty(workspace_size(dims, update_probe, line_search), dtype=torch.uint8, device=device)
 
 
 def _common(obj, probe, pos):
@@ -232,15 +236,18 @@ class CgResult:
 
 def cg_solve(obj0, probe, pos, data, iters: int, update_probe: bool = False, gamma0: float = 1.0,
              tau: float = 0.5, t: float = 0.0, max_halvings: int = 40, eps: float = 1e-32,
-             target_phi: float | None = None, ws=None) -> CgResult:
-    """ML-CG (Algorithm 1).  Works on copies of obj0 / probe."""
+             target_phi: float | None = None, ws=None, line_search: str = "sequential") -> CgResult:
+    """ML-CG (Algorithm 1).  Works on copies of obj0 / probe.  line_search:
+    "sequential" (one MINFUNC pass per trial) or "batched" (trials evaluated
+    from stored far fields, up to 16 per pass; the workspace must then be
+    sized with the same line_search)."""
     obj, probe_c, pos, d = _common(obj0, probe, pos)
     data = _dev(data, "data", torch.float32)
     obj = obj.clone()
     probe_c = probe_c.clone()
     o = CgOpts(int(iters), int(update_probe), float(gamma0), float(tau), float(t), int(max_halvings),
-               float(eps), -1.0 if target_phi is None else float(target_phi))
-    ws = workspace(d, obj.device, update_probe) if ws is None else ws
+               float(eps), -1.0 if target_phi is None else float(target_phi), LINE_SEARCH[line_search])
+    ws = workspace(d, obj.device, update_probe, line_search) if ws is None else ws
     trace = (IterStats * max(1, iters))()
     done = ctypes.c_int32(0)
     _check(load().ptyg_cg_solve(ctypes.byref(d), _ptr(obj), _ptr(probe_c), _ptr(pos), _ptr(data),
@@ -283,7 +290,7 @@ def debug_lane_swap(a, b):
     _check(load().ptyg_debug_lane_swap(_ptr(a), _ptr(b), _stream()))
 
 
-KERNEL_KINDS = ("grad", "minfunc")
+KERNEL_KINDS = ("grad", "minfunc", "dir_forward", "tile_sum")
 
 
 def timing_enable(on: bool = True):
@@ -295,8 +302,11 @@ def timing_reset():
 
 
 def timing_read() -> dict:
-    """{kind: (total ms, launches)} for the fused GRAD and MINFUNC kernels."""
-    ms = (ctypes.c_double * 2)()
-    cnt = (ctypes.c_int32 * 2)()
-    _check(load().ptyg_timing_read(ms, cnt, 2))
+    """{kind: (total ms, launches)} for the fused GRAD kernel, the line-search
+    kernel, the direction forward transform of the batched line search and
+    the ordered overlap sum of the object gradient."""
+    n = len(KERNEL_KINDS)
+    ms = (ctypes.c_double * n)()
+    cnt = (ctypes.c_int32 * n)()
+    _check(load().ptyg_timing_read(ms, cnt, n))
     return {k: (ms[i], cnt[i]) for i, k in enumerate(KERNEL_KINDS)}
