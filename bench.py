@@ -55,8 +55,15 @@ KERNEL_NAMES = {"grad": "k_grad (fused GRAD)", "minfunc": "k_minfunc (line-searc
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch (FETCH_SIZE x 2 + WRITE_SIZE x 1, the factors from a
 # 512 MiB device copy measured by the same counters) of the current kernels,
-# from the rocprofv3 --pmc runs summarised in profiles/; absent = not measured
-TRAFFIC_BYTES = {}
+# from the rocprofv3 --pmc runs summarised in
+# profiles/cg_c2_batched_ls_hbm_bytes.md; keyed (kind, workload, line search);
+# absent = not measured for that kernel build
+TRAFFIC_BYTES = {
+    ("grad", "c2", "batched"): 1539236164,
+    ("dir_forward", "c2", "batched"): 1195023212,
+    ("tile_sum", "c2", "batched"): 707885457,
+    ("ls_batched", "c2", "batched"): 402561581,
+}
 FP32_PEAK_TFLOPS = 157.3
 
 
@@ -191,7 +198,7 @@ def main():
     d = kinds[dom]
     bpl = d["bytes_per_launch"]
     roofline = {"bound": "hbm", "achieved": round(d["alg_GBs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(d["alg_GBs"] / HBM_PEAK_GBS, 4), "traffic": TRAFFIC_BYTES.get((dom, args.config)),
+                "frac": round(d["alg_GBs"] / HBM_PEAK_GBS, 4), "traffic": TRAFFIC_BYTES.get((dom, args.config, ls)),
                 "kernel": KERNEL_NAMES[dom], "bytes_per_launch": bpl, "avg_launch_us": round(d["avg_us"], 2),
                 "fft_tflops": round(d["fft_TFLOPs"], 2), "fft_frac_of_fp32_peak":
                     round(d["fft_TFLOPs"] / FP32_PEAK_TFLOPS, 4)}

@@ -320,17 +320,17 @@ def finetune(net: Net, objects, probe, steps: int = 20, lr: float = 2e-4, batch_
 
 
 def time_to_objective(net: Net, probe, pos, data, obj_shape, obj_true=None, plain_iters: int = 100,
-                      max_iters: int = 100, sync_iters: int = 100):
+                      max_iters: int = 100, sync_iters: int = 100, line_search: str = "batched"):
     """Plain CG (psi_0 = 1, `plain_iters` iterations) against the warm start
     (inference + stitch + CG until its objective reaches plain CG's final
     one).  Wall times are synchronised host timings."""
     H, W = int(obj_shape[0]), int(obj_shape[1])
     K = pos.shape[0]
-    ws = ptyg.workspace(ptyg.dims_of((H, W), probe.shape[0], K), probe.device)
+    ws = ptyg.workspace(ptyg.dims_of((H, W), probe.shape[0], K), probe.device, line_search=line_search)
     ones = torch.ones((H, W), dtype=torch.complex64, device=probe.device)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    plain = ptyg.cg_solve(ones, probe, pos, data, plain_iters, ws=ws)
+    plain = ptyg.cg_solve(ones, probe, pos, data, plain_iters, ws=ws, line_search=line_search)
     torch.cuda.synchronize()
     t_plain = time.perf_counter() - t0
     phi_plain = plain.trace[-1]["phi"] if plain.trace else float("nan")
@@ -348,7 +348,8 @@ def time_to_objective(net: Net, probe, pos, data, obj_shape, obj_true=None, plai
     t_stitch = time.perf_counter() - t2
     phi0_warm = float(ptyg.minfunc(psi0, probe, pos, data, ws=ws)[0])
     t3 = time.perf_counter()
-    warm = ptyg.cg_solve(psi0, probe, pos, data, max_iters, target_phi=phi_plain_final, ws=ws)
+    warm = ptyg.cg_solve(psi0, probe, pos, data, max_iters, target_phi=phi_plain_final, ws=ws,
+                         line_search=line_search)
     torch.cuda.synchronize()
     t_cg = time.perf_counter() - t3
     phi_warm_final = float(ptyg.minfunc(warm.obj, probe, pos, data, ws=ws)[0])
@@ -411,6 +412,7 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=5e-4)
     ap.add_argument("--finetune", type=int, default=0, help="fine-tuning steps through the operator")
     ap.add_argument("--sync-iters", type=int, default=100)
+    ap.add_argument("--line-search", default="batched", choices=["batched", "sequential"])
     args = ap.parse_args(argv)
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -441,7 +443,8 @@ def main(argv=None):
             objs.append({"pos": p, "data": torch.poisson((far.real ** 2 + far.imag ** 2).float()).contiguous(),
                          "shape": (1024, 1024)})
         ft = finetune(net, objs, probe, steps=args.finetune, log=log)
-    res = time_to_objective(net, probe, pos, data, tuple(obj_true.shape), obj_true, sync_iters=args.sync_iters)
+    res = time_to_objective(net, probe, pos, data, tuple(obj_true.shape), obj_true, sync_iters=args.sync_iters,
+                            line_search=args.line_search)
     res.update({"train_patterns": args.objects * args.per_side ** 2, "train_epochs": args.epochs,
                 "t_data_s": round(t_data, 2), "t_train_s": round(t_train, 2), "loss_history": hist[-5:],
                 "finetune_phi": ft[-3:] if ft else None,
