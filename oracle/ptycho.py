@@ -9,8 +9,8 @@ holds none of the method's arithmetic.
 
 Every function below follows one passage of the paper (arXiv 2106.07575,
 section "Background", subsections "Forward problem of ptychography" and
-"Inverse problem for ptychography", Eqs. fwd_model, ML, gradient, update,
-DaiYuan, linesearch; the CG coefficient eq. cg_ch1_1 of section "Challenges
+"Inverse problem for ptychography", Eqs. fwd_model, ML, gradient, update2
+(gradient descent), update, DaiYuan, linesearch; the CG coefficient eq. cg_ch1_1 of section "Challenges
 of CG solver parallelization"; and Algorithm 1, "Complete workflow of
 PtyGer").  Precision is complex128 / float64 throughout.
 
@@ -293,6 +293,28 @@ def cg_solve(obj0, probe0, pos, d, iters: int, gamma0: float = 1.0,
         g_old = g_new
         restart = not accepted
     o, p = unpack(x)
+    return o, p, trace
+
+
+# ------------------------------------------------------ GD (Eq. update2)
+def gd_solve(obj0, probe0, pos, d, iters: int, gamma: float, eps: float = EPS,
+             update_probe: bool = False):
+    """Gradient-descent solver of Eq. update2: psi_{m+1} = psi_m - gamma
+    grad F(psi_m) with a constant step gamma (the paper's slower baseline).
+    Joint mode also steps the probe with the same gamma along its gradient.
+    Returns (obj, probe, trace) with one row per iteration: phi, f (at
+    psi_m) and step_norm = gamma ||grad F(psi_m)||."""
+    o = np.array(obj0, dtype=np.complex128)
+    p = np.array(probe0, dtype=np.complex128)
+    trace = []
+    for _ in range(iters):
+        res = grad(o, p, pos, d, eps, want_probe=update_probe)
+        g2 = inner(res["grad_obj"], res["grad_obj"]).real
+        o = o - gamma * res["grad_obj"]
+        if update_probe:
+            g2 += inner(res["grad_probe"], res["grad_probe"]).real
+            p = p - gamma * res["grad_probe"]
+        trace.append({"phi": res["phi"], "f": res["f"], "step_norm": gamma * math.sqrt(g2)})
     return o, p, trace
 
 
