@@ -129,6 +129,57 @@ def cpu_baseline(cfg_name: str, halvings_per_iter: float, budget_s: float = 12.0
                       f"float64, scipy.fft with {os.cpu_count()} workers"}
 
 
+def run_gd(args, cfg, probe, pos, data, obj0, joint):
+    """Gradient descent (Eq. update2) timed like the CG run; CG's objective
+    after the same number of iterations (untimed) shows the convergence gap."""
+    import torch
+
+    from paper_2106_07575_amd import ptyg
+
+    K = cfg.k
+    gamma = args.gd_gamma
+    if gamma <= 0.0:
+        pa = probe.abs().to(torch.complex64)
+        illum, _ = ptyg.adjoint(ptyg.forward(torch.ones_like(obj0), pa, pos), pa, pos, tuple(obj0.shape))
+        gamma = 0.1 / float(illum.real.max())
+        del illum
+    ws = ptyg.workspace(ptyg.dims_of(obj0.shape, cfg.n, K), obj0.device, update_probe=joint)
+    est = args.estimator
+    if args.warmup > 0:
+        ptyg.gd_solve(obj0, probe, pos, data, args.warmup, gamma, update_probe=joint, ws=ws, estimator=est)
+    torch.cuda.synchronize()
+    ptyg.timing_reset()
+    ptyg.timing_enable(True)
+    t0 = time.perf_counter()
+    _, _, phis = ptyg.gd_solve(obj0, probe, pos, data, args.steps, gamma, update_probe=joint, ws=ws, estimator=est)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    ptyg.timing_enable(False)
+    kt = ptyg.timing_read()
+    wsc = ptyg.workspace(ptyg.dims_of(obj0.shape, cfg.n, K), obj0.device, update_probe=joint, line_search="batched")
+    cg = ptyg.cg_solve(obj0, probe, pos, data, args.steps, update_probe=joint, ws=wsc, line_search="batched",
+                       estimator=est)
+    kinds = {k: {"launches": c, "avg_us": round(ms / c * 1e3, 2)} for k, (ms, c) in kt.items() if c}
+    g = kt["grad"]
+    avg_s = g[0] / g[1] / 1e3
+    alg = kernel_bytes("grad", cfg, False, 0)
+    print(json.dumps({
+        "metric": "diffraction patterns/s through grad (gradient descent, constant step)",
+        "value": round(K * args.steps / dt, 1), "unit": "patterns/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": round(dt / args.steps * 1e3, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "fp32 transforms, fp64 reductions", "data": "synthetic",
+        "config": {"workload": f"{args.config}: {cfg.obj_h}x{cfg.obj_w} object, {cfg.n}x{cfg.n} probe, {K} "
+                               f"positions, Poisson at {cfg.photons:g} photons, gradient descent gamma {gamma:.4g}",
+                   "estimator": est},
+        "phi_first": phis[0], "phi_last": phis[-1],
+        "cg_phi_after_same_iterations": cg.trace[-1]["phi"] if cg.trace else None,
+        "kernels": kinds,
+        "roofline": {"bound": "hbm", "achieved": round(alg / avg_s / 1e9, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": round(alg / avg_s / 1e9 / HBM_PEAK_GBS, 4), "traffic": None,
+                     "kernel": KERNEL_NAMES["grad"], "bytes_per_launch": alg, "avg_launch_us": round(avg_s * 1e6, 2)},
+    }))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -140,6 +191,13 @@ def main():
     ap.add_argument("--line-search", default="batched", choices=["batched", "sequential"],
                     help="batched: trials from stored far fields, up to 16 per streaming pass (default); "
                          "sequential: one forward pass per trial")
+    ap.add_argument("--estimator", default="ml", choices=["ml", "ls"],
+                    help="ml: Poisson maximum likelihood (Eq. ML, the headline); ls: least squares on amplitudes")
+    ap.add_argument("--solver", default="cg", choices=["cg", "gd"],
+                    help="cg: ML-CG (the headline); gd: gradient descent with a constant step (Eq. update2), "
+                         "reported with the objective CG reaches in the same number of iterations")
+    ap.add_argument("--gd-gamma", type=float, default=0.0,
+                    help="GD step (default 0.1 / peak illumination)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the timed run, copy a MIB-MiB device buffer 3 times (a reference kernel of known "
@@ -162,17 +220,22 @@ def main():
     if joint:
         probe = probe.abs().to(torch.complex64)   # amplitude known, phase unknown
     obj0 = torch.ones((cfg.obj_h, cfg.obj_w), dtype=torch.complex64, device=device)
+    if args.solver == "gd":
+        run_gd(args, cfg, probe, pos, data, obj0, joint)
+        return
     ls = args.line_search
     ws = ptyg.workspace(ptyg.dims_of(obj0.shape, cfg.n, K), device, update_probe=joint, line_search=ls)
 
+    est = args.estimator
     if args.warmup > 0:
-        ptyg.cg_solve(obj0, probe, pos, data, args.warmup, update_probe=joint, ws=ws, line_search=ls)
+        ptyg.cg_solve(obj0, probe, pos, data, args.warmup, update_probe=joint, ws=ws, line_search=ls, estimator=est)
     torch.cuda.synchronize()
     ptyg.timing_reset()
     ptyg.timing_enable(True)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    res = ptyg.cg_solve(obj0, probe, pos, data, args.steps, update_probe=joint, ws=ws, line_search=ls)
+    res = ptyg.cg_solve(obj0, probe, pos, data, args.steps, update_probe=joint, ws=ws, line_search=ls,
+                        estimator=est)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ptyg.timing_enable(False)
@@ -215,7 +278,7 @@ def main():
         "vs_baseline": None,
         "dtype": "fp32 transforms, fp64 reductions",
         "data": "synthetic",
-        "config": {"line_search": ls,
+        "config": {"line_search": ls, "estimator": est,
                    "workload": f"{args.config}: {cfg.obj_h}x{cfg.obj_w} complex64 object, {cfg.n}x{cfg.n} probe, "
                                f"{K} positions ({cfg.grid[0]}x{cfg.grid[1]} raster, step {cfg.step}, "
                                f"+-{cfg.jitter} px), Poisson at {cfg.photons:g} photons, "
@@ -238,7 +301,7 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = src.numel()
-    if not args.no_cpu_baseline and not joint:
+    if not args.no_cpu_baseline and not joint and est == "ml":
         out["cpu_baseline"] = cpu_baseline(args.config, halvings / max(iters, 1))
     print(json.dumps(out))
 

@@ -63,6 +63,15 @@ enum {
 /* hipStream_t, passed as an opaque pointer so this header needs no HIP headers. */
 typedef void* ptyg_stream_t;
 
+/* Estimators.  PTYG_EST_ML: the Poisson maximum likelihood of Eq. ML (the
+ * paper's worked formulation).  PTYG_EST_LS: least squares on the amplitudes,
+ * which the paper names (section Background) without a formula; taken as
+ * F = sum_j (|G psi|_j - sqrt(d_j))^2 with gradient
+ * G^H (G psi - sqrt(d) G psi / |G psi|) in the same Wirtinger convention as
+ * Eq. gradient (no factor 2); d <= 0 pixels contribute |G psi|^2.  Its Phi
+ * and F are the same number. */
+enum { PTYG_EST_ML = 0, PTYG_EST_LS = 1 };
+
 typedef struct {
   int32_t obj_h, obj_w; /* object rows, columns */
   int32_t n;            /* probe side = detector side, in {16, 32, 64, 128, 256} */
@@ -88,6 +97,7 @@ typedef struct {
                            over the stored far fields (no transforms); the accepted
                            trial is the first that passes, as in the sequential order.
                            Needs 2 (joint: 3) extra k*n*n complex64 of workspace. */
+  int32_t estimator;    /* PTYG_EST_ML or PTYG_EST_LS */
 } ptyg_cg_opts;
 
 enum { PTYG_LS_SEQUENTIAL = 0, PTYG_LS_BATCHED = 1 };
@@ -144,19 +154,21 @@ ptyg_status ptyg_adjoint(const ptyg_dims* dims, const ptyg_c64* far, const ptyg_
  * by g where |g|^2 < eps.  data: float32 intensities [k][n][n].
  * grad_probe (nullable): sum_k conj(obj[pos_k]) * F^H r_k.
  * objective (nullable, device double[2]): {deviance Phi, Eq. ML value F},
- * accumulated in FP64 with a fixed reduction order. */
+ * accumulated in FP64 with a fixed reduction order.  estimator: PTYG_EST_ML
+ * (as above) or PTYG_EST_LS (residual g - sqrt(d) g / |g|, objective
+ * sum (|g| - sqrt d)^2 in both slots). */
 ptyg_status ptyg_grad(const ptyg_dims* dims, const ptyg_c64* obj, const ptyg_c64* probe,
-                      const int32_t* pos, const float* data, float eps, ptyg_c64* grad_obj,
-                      ptyg_c64* grad_probe, double* objective, void* ws, size_t ws_bytes,
-                      ptyg_stream_t stream);
+                      const int32_t* pos, const float* data, float eps, int32_t estimator,
+                      ptyg_c64* grad_obj, ptyg_c64* grad_probe, double* objective, void* ws,
+                      size_t ws_bytes, ptyg_stream_t stream);
 
 /* MINFUNC of Algorithm 1 (one line-search trial): objective (device
  * double[2], {Phi, F}) at obj + gamma*dir_obj and probe + gamma*dir_probe.
  * dir_obj / dir_probe may be NULL (no step in that block). */
 ptyg_status ptyg_minfunc(const ptyg_dims* dims, const ptyg_c64* obj, const ptyg_c64* dir_obj,
                          const ptyg_c64* probe, const ptyg_c64* dir_probe, double gamma, const int32_t* pos,
-                         const float* data, float eps, double* objective, void* ws, size_t ws_bytes,
-                         ptyg_stream_t stream);
+                         const float* data, float eps, int32_t estimator, double* objective, void* ws,
+                         size_t ws_bytes, ptyg_stream_t stream);
 
 /* ML-CG reconstruction (Algorithm 1 on one GPU; Eqs. update, DaiYuan,
  * linesearch).  obj: in psi_0, out psi_iters.  probe: read, and updated when
@@ -169,6 +181,20 @@ ptyg_status ptyg_minfunc(const ptyg_dims* dims, const ptyg_c64* obj, const ptyg_
 ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj, ptyg_c64* probe, const int32_t* pos,
                           const float* data, const ptyg_cg_opts* opts, void* ws, size_t ws_bytes,
                           ptyg_cg_iter_stats* trace, int32_t* iters_done, ptyg_stream_t stream);
+
+/* Gradient descent (Eq. update2): obj_{m+1} = obj_m - gamma * grad F(obj_m)
+ * with a constant step gamma >= 0 (the paper's slower baseline solver);
+ * with update_probe the probe takes the same step along its gradient.
+ * obj (and probe) are updated in place; phi_trace: HOST array of `iters`
+ * doubles (nullable), the deviance Phi at obj_m from each GRAD pass.  Needs
+ * the workspace of ptyg_cg_solve with the same update_probe and the
+ * sequential line search.  The objectives are read back every 1024
+ * iterations and at the end; a non-finite one returns PTYG_E_NONFINITE (the
+ * iterates after it are then not meaningful). */
+ptyg_status ptyg_gd_solve(const ptyg_dims* dims, ptyg_c64* obj, ptyg_c64* probe, const int32_t* pos,
+                          const float* data, int32_t iters, double gamma, int32_t update_probe, float eps,
+                          int32_t estimator, void* ws, size_t ws_bytes, double* phi_trace,
+                          ptyg_stream_t stream);
 
 /* Opt-in kernel timing for benchmarks: when enabled, the fused GRAD kernel
  * (kind 0), the line-search kernel (kind 1: a MINFUNC pass, or a batched

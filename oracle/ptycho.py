@@ -31,6 +31,9 @@ reason in the design notes):
   * Scan positions are integer (row, col) top-left corners inside the object.
   * Joint object+probe mode (not in the paper) runs the same CG on the pair
     (psi, p) with inner products summed over both blocks.
+  * The least-squares estimator, which the paper says its techniques also
+    apply to but gives no formula for, is taken as F = sum (|g| - sqrt d)^2
+    with the Wirtinger gradient convention of Eq. gradient.
 
 Parity status: every function here is pinned by the not-gpu tests (brute
 force DFT, closed forms, adjoint identity, zero gradient at the truth, finite
@@ -142,14 +145,23 @@ def adjoint(far: np.ndarray, probe: np.ndarray, pos: np.ndarray, shape,
 
 
 # ------------------------------------------------------- objective (Eq. 2)
-def objective_terms(x: np.ndarray, d: np.ndarray, eps: float = EPS):
-    """Per-pixel terms of the ML objective for intensities x = |g|^2.
+def objective_terms(x: np.ndarray, d: np.ndarray, eps: float = EPS, estimator: str = "ml"):
+    """Per-pixel terms of the objective for intensities x = |g|^2.
 
-    paper: x - d log max(x, eps)            (Eq. ML; 2 d log|g| = d log|g|^2)
-    dev:   x - d - d log(max(x, eps) / d)   for d > 0;  x for d = 0
-    Both drop d log(.) where d = 0.  dev = paper - (d - d log d)."""
+    estimator "ml" (Eq. ML):
+      paper: x - d log max(x, eps)            (2 d log|g| = d log|g|^2)
+      dev:   x - d - d log(max(x, eps) / d)   for d > 0;  x for d = 0
+      Both drop d log(.) where d = 0.  dev = paper - (d - d log d).
+    estimator "ls" (least squares on amplitudes; the paper names the LS
+    estimate without a formula, the usual one is taken):
+      paper = dev = (sqrt(x) - sqrt(d))^2 for d > 0; x for d <= 0."""
     x = np.asarray(x, dtype=np.float64)
     d = np.asarray(d, dtype=np.float64)
+    if estimator == "ls":
+        t = np.where(d > 0, (np.sqrt(x) - np.sqrt(np.maximum(d, 0.0))) ** 2, x)
+        return t, t
+    if estimator != "ml":
+        raise ValueError(f"unknown estimator {estimator!r}")
     xg = np.maximum(x, eps)
     pos = d > 0
     dsafe = np.where(pos, d, 1.0)
@@ -158,15 +170,21 @@ def objective_terms(x: np.ndarray, d: np.ndarray, eps: float = EPS):
     return paper, dev
 
 
-def residual(g: np.ndarray, d: np.ndarray, eps: float = EPS) -> np.ndarray:
+def residual(g: np.ndarray, d: np.ndarray, eps: float = EPS, estimator: str = "ml") -> np.ndarray:
     """Inner term of Eq. gradient: g - d / conj(g) = g (1 - d / |g|^2),
-    and g where |g|^2 < eps."""
+    and g where |g|^2 < eps.  Least squares: the Wirtinger derivative of
+    (|g| - sqrt d)^2 with respect to conj(g), g (1 - sqrt(d) / |g|) (g where
+    |g|^2 < eps or d <= 0)."""
     x = np.abs(g) ** 2
+    if estimator == "ls":
+        sd = np.sqrt(np.maximum(np.asarray(d, dtype=np.float64), 0.0))
+        w = np.where(x >= eps, sd / np.sqrt(np.maximum(x, eps)), 0.0)
+        return g * (1.0 - w)
     w = np.where(x >= eps, np.asarray(d, dtype=np.float64) / np.maximum(x, eps), 0.0)
     return g * (1.0 - w)
 
 
-def minfunc(obj, probe, pos, d, eps: float = EPS):
+def minfunc(obj, probe, pos, d, eps: float = EPS, estimator: str = "ml"):
     """MINFUNC of Algorithm 1: (Phi deviance, F of Eq. ML) at psi."""
     n = probe.shape[0]
     phi = 0.0
@@ -174,13 +192,13 @@ def minfunc(obj, probe, pos, d, eps: float = EPS):
     for lo in range(0, len(pos), CHUNK):
         sl = slice(lo, lo + CHUNK)
         g = fft2u(probe[None] * gather(obj, pos[sl], n))
-        paper, dev = objective_terms(np.abs(g) ** 2, d[sl], eps)
+        paper, dev = objective_terms(np.abs(g) ** 2, d[sl], eps, estimator)
         phi += float(np.sum(dev))
         f += float(np.sum(paper))
     return phi, f
 
 
-def grad(obj, probe, pos, d, eps: float = EPS, want_probe: bool = False):
+def grad(obj, probe, pos, d, eps: float = EPS, want_probe: bool = False, estimator: str = "ml"):
     """GRAD stage (Eq. gradient): FORWARD then GRAD_COMP.
 
     grad_obj = G^H (g - d / conj(g)) is the Wirtinger derivative dF/d conj(psi)
@@ -196,10 +214,10 @@ def grad(obj, probe, pos, d, eps: float = EPS, want_probe: bool = False):
         sl = slice(lo, lo + CHUNK)
         patch = gather(obj, pos[sl], n)
         g = fft2u(probe[None] * patch)
-        paper, dev = objective_terms(np.abs(g) ** 2, d[sl], eps)
+        paper, dev = objective_terms(np.abs(g) ** 2, d[sl], eps, estimator)
         phi += float(np.sum(dev))
         f += float(np.sum(paper))
-        u = ifft2u(residual(g, d[sl], eps))
+        u = ifft2u(residual(g, d[sl], eps, estimator))
         gobj += scatter_add(np.conj(probe)[None] * u, pos[sl], obj.shape)
         if want_probe:
             gprb += np.sum(np.conj(patch) * u, axis=0)
@@ -243,7 +261,7 @@ def line_search(phi_of_gamma, phi_m: float, gamma0: float = 1.0,
 def cg_solve(obj0, probe0, pos, d, iters: int, gamma0: float = 1.0,
              tau: float = 0.5, t: float = 0.0, lmax: int = 40,
              eps: float = EPS, update_probe: bool = False,
-             target_phi: float | None = None):
+             target_phi: float | None = None, estimator: str = "ml"):
     """ML-CG reconstruction of Algorithm 1 on one device.
 
     Each iteration: GRAD (Eq. gradient) -> DIR (Eq. DaiYuan, eta_0 = -grad_0)
@@ -265,7 +283,7 @@ def cg_solve(obj0, probe0, pos, d, iters: int, gamma0: float = 1.0,
     restart = True
     for m in range(iters):
         o, p = unpack(x)
-        res = grad(o, p, pos, d, eps, want_probe=update_probe)
+        res = grad(o, p, pos, d, eps, want_probe=update_probe, estimator=estimator)
         g_new = [res["grad_obj"]] + ([res["grad_probe"]] if update_probe else [])
         phi_m = res["phi"]
         if target_phi is not None and phi_m <= target_phi:
@@ -281,7 +299,7 @@ def cg_solve(obj0, probe0, pos, d, iters: int, gamma0: float = 1.0,
         # LS stage
         def phi_of_gamma(gamma):
             oo, pp = unpack([b + gamma * e for b, e in zip(x, eta)])
-            return minfunc(oo, pp, pos, d, eps)[0]
+            return minfunc(oo, pp, pos, d, eps, estimator)[0]
 
         gamma, trials, accepted = line_search(phi_of_gamma, phi_m, gamma0, tau, t, lmax)
         # Update stage
@@ -298,7 +316,7 @@ def cg_solve(obj0, probe0, pos, d, iters: int, gamma0: float = 1.0,
 
 # ------------------------------------------------------ GD (Eq. update2)
 def gd_solve(obj0, probe0, pos, d, iters: int, gamma: float, eps: float = EPS,
-             update_probe: bool = False):
+             update_probe: bool = False, estimator: str = "ml"):
     """Gradient-descent solver of Eq. update2: psi_{m+1} = psi_m - gamma
     grad F(psi_m) with a constant step gamma (the paper's slower baseline).
     Joint mode also steps the probe with the same gamma along its gradient.
@@ -308,7 +326,7 @@ def gd_solve(obj0, probe0, pos, d, iters: int, gamma: float, eps: float = EPS,
     p = np.array(probe0, dtype=np.complex128)
     trace = []
     for _ in range(iters):
-        res = grad(o, p, pos, d, eps, want_probe=update_probe)
+        res = grad(o, p, pos, d, eps, want_probe=update_probe, estimator=estimator)
         g2 = inner(res["grad_obj"], res["grad_obj"]).real
         o = o - gamma * res["grad_obj"]
         if update_probe:

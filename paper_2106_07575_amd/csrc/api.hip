@@ -42,6 +42,11 @@ size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
 bool n_supported(int n) { return n == 16 || n == 32 || n == 64 || n == 128 || n == 256; }
 
+ptyg_status check_est(int32_t est) {
+  if (est != PTYG_EST_ML && est != PTYG_EST_LS) return fail(PTYG_E_INVAL, "estimator=%d is not a PTYG_EST_* value", est);
+  return PTYG_OK;
+}
+
 ptyg_status check_dims(const ptyg_dims* d) {
   if (!d) return fail(PTYG_E_INVAL, "dims is NULL");
   if (!n_supported(d->n)) return fail(PTYG_E_INVAL, "probe size n=%d not in {16,32,64,128,256}", d->n);
@@ -54,8 +59,10 @@ ptyg_status check_dims(const ptyg_dims* d) {
 }
 
 // Workspace regions (byte offsets, each 256-byte aligned).
+constexpr int kGdTrace = 1024;  // objectives kept on the device between gradient-descent readbacks
+
 struct Layout {
-  size_t partials, scalars, flag, pparts, eta_obj, grad_obj, eta_probe, grad_probe, data_t, ubuf, toff, tlist,
+  size_t partials, scalars, gdtrace, flag, pparts, eta_obj, grad_obj, eta_probe, grad_probe, data_t, ubuf, toff, tlist,
       far_a, far_b, far_c, lsparts, lsphi, nz_counts, nz_offsets, nz_idx, zparts, zsums, total;
   size_t nz_blocks, z_blocks;
   size_t n_partials;
@@ -75,6 +82,8 @@ Layout layout(const ptyg_dims* d, bool joint, bool batched = false) {
   o = align_up(o + L.n_partials * 2 * sizeof(double));
   L.scalars = o;
   o = align_up(o + kScalars * sizeof(double));
+  L.gdtrace = o;  // slot i gets (Phi, F) of iteration i; the next iteration overwrites F
+  o = align_up(o + (kGdTrace + 1) * sizeof(double));
   L.flag = o;
   o = align_up(o + sizeof(int));
   L.pparts = o;
@@ -217,7 +226,7 @@ struct TimedLaunch {
 
 extern "C" {
 
-int32_t ptyg_abi_version(void) { return 2; }
+int32_t ptyg_abi_version(void) { return 3; }
 
 const char* ptyg_status_string(ptyg_status s) {
   switch (s) {
@@ -308,10 +317,11 @@ namespace {
 // One fused GRAD pass; writes {phi, f} to `objective` (device) when given.
 // The tile lists of `pos` must already be in the workspace.
 ptyg_status run_grad(const ptyg_dims* dims, const float2* obj, const float2* probe, const int2* pos,
-                     const float* data, DataLayout lay, float eps, float2* grad_obj, float2* grad_probe,
+                     const float* data, DataLayout lay, float eps, int est, float2* grad_obj, float2* grad_probe,
                      double* objective, void* ws, const Layout& L, hipStream_t s, float2* gstore = nullptr,
                      double* gsum = nullptr) {
   PatArgs a = base_args(dims);
+  a.est = est;
   a.gstore = gstore;
   if (gstore) a.zs_part = at<double>(ws, L.zparts);
   a.obj = obj;
@@ -347,8 +357,9 @@ ptyg_status build_tiles(const ptyg_dims* dims, const int2* pos, void* ws, const 
 
 ptyg_status run_minfunc(const ptyg_dims* dims, const float2* obj, const float2* dobj, const float2* probe,
                         const float2* dprobe, double gamma, const int2* pos, const float* data, DataLayout lay,
-                        float eps, double* objective, void* ws, const Layout& L, hipStream_t s) {
+                        float eps, int est, double* objective, void* ws, const Layout& L, hipStream_t s) {
   PatArgs a = base_args(dims);
+  a.est = est;
   a.obj = obj;
   a.dobj = dobj;
   a.probe = probe;
@@ -370,32 +381,34 @@ ptyg_status run_minfunc(const ptyg_dims* dims, const float2* obj, const float2* 
 }  // namespace
 
 ptyg_status ptyg_grad(const ptyg_dims* dims, const ptyg_c64* obj, const ptyg_c64* probe, const int32_t* pos,
-                      const float* data, float eps, ptyg_c64* grad_obj, ptyg_c64* grad_probe, double* objective,
-                      void* ws, size_t ws_bytes, ptyg_stream_t stream) {
+                      const float* data, float eps, int32_t estimator, ptyg_c64* grad_obj, ptyg_c64* grad_probe,
+                      double* objective, void* ws, size_t ws_bytes, ptyg_stream_t stream) {
   if (ptyg_status st = check_dims(dims)) return st;
   if (!obj || !probe || !pos || !data || !grad_obj) return fail(PTYG_E_INVAL, "NULL array argument");
   if (!(eps >= 0.0f)) return fail(PTYG_E_INVAL, "eps must be >= 0");
+  if (ptyg_status st = check_est(estimator)) return st;
   Layout L;
   if (ptyg_status st = check_ws(dims, ws, ws_bytes, false, &L)) return st;
   if (ptyg_status st = build_tiles(dims, reinterpret_cast<const int2*>(pos), ws, L, S(stream))) return st;
   return run_grad(dims, reinterpret_cast<const float2*>(obj), reinterpret_cast<const float2*>(probe),
-                  reinterpret_cast<const int2*>(pos), data, DataLayout::Rows, eps,
+                  reinterpret_cast<const int2*>(pos), data, DataLayout::Rows, eps, estimator,
                   reinterpret_cast<float2*>(grad_obj), reinterpret_cast<float2*>(grad_probe), objective, ws, L,
                   S(stream));
 }
 
 ptyg_status ptyg_minfunc(const ptyg_dims* dims, const ptyg_c64* obj, const ptyg_c64* dir_obj,
                          const ptyg_c64* probe, const ptyg_c64* dir_probe, double gamma, const int32_t* pos,
-                         const float* data, float eps, double* objective, void* ws, size_t ws_bytes,
-                         ptyg_stream_t stream) {
+                         const float* data, float eps, int32_t estimator, double* objective, void* ws,
+                         size_t ws_bytes, ptyg_stream_t stream) {
   if (ptyg_status st = check_dims(dims)) return st;
   if (!obj || !probe || !pos || !data || !objective) return fail(PTYG_E_INVAL, "NULL array argument");
   if (!std::isfinite(gamma)) return fail(PTYG_E_INVAL, "gamma not finite");
+  if (ptyg_status st = check_est(estimator)) return st;
   Layout L;
   if (ptyg_status st = check_ws(dims, ws, ws_bytes, false, &L)) return st;
   return run_minfunc(dims, reinterpret_cast<const float2*>(obj), reinterpret_cast<const float2*>(dir_obj),
                      reinterpret_cast<const float2*>(probe), reinterpret_cast<const float2*>(dir_probe), gamma,
-                     reinterpret_cast<const int2*>(pos), data, DataLayout::Rows, eps, objective, ws, L,
+                     reinterpret_cast<const int2*>(pos), data, DataLayout::Rows, eps, estimator, objective, ws, L,
                      S(stream));
 }
 
@@ -411,6 +424,8 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
   if (!(opts->eps >= 0.0)) return fail(PTYG_E_INVAL, "eps must be >= 0");
   if (opts->line_search != PTYG_LS_SEQUENTIAL && opts->line_search != PTYG_LS_BATCHED)
     return fail(PTYG_E_INVAL, "line_search=%d is not a PTYG_LS_* value", opts->line_search);
+  if (ptyg_status st = check_est(opts->estimator)) return st;
+  const int est = opts->estimator;
   const bool joint = opts->update_probe != 0;
   const bool batched = opts->line_search == PTYG_LS_BATCHED;
   Layout L;
@@ -465,7 +480,7 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
 
   for (int m = 0; m < opts->iters; ++m) {
     // GRAD stage
-    if (ptyg_status st = run_grad(dims, obj, probe, pos, dt, DataLayout::Transposed, eps, grad_o, grad_p,
+    if (ptyg_status st = run_grad(dims, obj, probe, pos, dt, DataLayout::Transposed, eps, est, grad_o, grad_p,
                                   sc + PHI, ws, L, s, far_a, batched ? at<double>(ws, L.zsums) : nullptr))
       return st;
     VecArgs v{};
@@ -575,6 +590,7 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
       la.idx = at<int>(ws, L.nz_idx);
       la.n = nnz;
       la.eps = eps;
+      la.est = est;
       // whole-array sums: [0] |a|^2 (GRAD), [4..7] direction pass, [8..11] joint pass
       double zs[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
       double zc[6] = {0, 0, 0, 0, 0, 0};  // d <= 0 parts: aa, ab, bb, ac, bc, cc
@@ -642,7 +658,7 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
       gamma *= opts->tau;
       trials = j;
       if (ptyg_status st = run_minfunc(dims, obj, eta_o, probe, eta_p, gamma, pos, dt, DataLayout::Transposed,
-                                       eps, sc + PHIT, ws, L, s))
+                                       eps, est, sc + PHIT, ws, L, s))
         return st;
       PTYG_HIP(hipMemcpyAsync(h + N3O, sc + N3O, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
       PTYG_HIP(hipStreamSynchronize(s));
@@ -688,6 +704,63 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
     if (iters_done) *iters_done = m + 1;
   }
   PTYG_HIP(hipStreamSynchronize(s));
+  return PTYG_OK;
+}
+
+ptyg_status ptyg_gd_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* probe_c, const int32_t* pos_i,
+                          const float* data, int32_t iters, double gamma, int32_t update_probe, float eps,
+                          int32_t estimator, void* ws, size_t ws_bytes, double* phi_trace,
+                          ptyg_stream_t stream) {
+  if (ptyg_status st = check_dims(dims)) return st;
+  if (ptyg_status st = check_est(estimator)) return st;
+  if (!obj_c || !probe_c || !pos_i || !data) return fail(PTYG_E_INVAL, "NULL argument");
+  if (iters < 0) return fail(PTYG_E_INVAL, "iters < 0");
+  if (!(gamma >= 0.0) || !std::isfinite(gamma)) return fail(PTYG_E_INVAL, "gamma must be finite and >= 0");
+  if (!(eps >= 0.0f)) return fail(PTYG_E_INVAL, "eps must be >= 0");
+  const bool joint = update_probe != 0;
+  Layout L;
+  if (ptyg_status st = check_ws(dims, ws, ws_bytes, joint, &L)) return st;
+  if (ptyg_status st = ptyg_check_positions(dims, pos_i, ws, ws_bytes, stream)) return st;
+  const hipStream_t s = S(stream);
+  float2* obj = reinterpret_cast<float2*>(obj_c);
+  float2* probe = reinterpret_cast<float2*>(probe_c);
+  const int2* pos = reinterpret_cast<const int2*>(pos_i);
+  float2* grad_o = at<float2>(ws, L.grad_obj);
+  float2* grad_p = joint ? at<float2>(ws, L.grad_probe) : nullptr;
+  float* dt = at<float>(ws, L.data_t);
+  double* tr = at<double>(ws, L.gdtrace);
+  PTYG_HIP(launch_transpose_data(data, dt, dims->k, dims->n, s));
+  if (ptyg_status st = build_tiles(dims, pos, ws, L, s)) return st;
+  std::vector<double> h(kGdTrace);
+  for (int m0 = 0; m0 < iters; m0 += kGdTrace) {
+    const int cnt = std::min(kGdTrace, iters - m0);
+    for (int i = 0; i < cnt; ++i) {
+      // GRAD stage; the objective of obj_m lands in the device trace
+      if (ptyg_status st = run_grad(dims, obj, probe, pos, dt, DataLayout::Transposed, eps, estimator, grad_o,
+                                    grad_p, tr + i, ws, L, s))
+        return st;
+      VecArgs u{};
+      u.n = (int64_t)dims->obj_h * dims->obj_w;
+      u.a = obj;
+      u.c = grad_o;
+      u.alpha = -gamma;
+      PTYG_HIP(launch_axpy(u, s));
+      if (joint) {
+        VecArgs up{};
+        up.n = (int64_t)dims->n * dims->n;
+        up.a = probe;
+        up.c = grad_p;
+        up.alpha = -gamma;
+        PTYG_HIP(launch_axpy(up, s));
+      }
+    }
+    PTYG_HIP(hipMemcpyAsync(h.data(), tr, cnt * sizeof(double), hipMemcpyDeviceToHost, s));
+    PTYG_HIP(hipStreamSynchronize(s));
+    for (int i = 0; i < cnt; ++i) {
+      if (phi_trace) phi_trace[m0 + i] = h[i];
+      if (!std::isfinite(h[i])) return fail(PTYG_E_NONFINITE, "objective is %g at iteration %d", h[i], m0 + i);
+    }
+  }
   return PTYG_OK;
 }
 

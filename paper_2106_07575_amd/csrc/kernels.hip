@@ -324,7 +324,7 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_fwd_t(PatArgs a) {
   }
 }
 
-template <int N, DataLayout LAY, bool SG>
+template <int N, DataLayout LAY, bool SG, int EST>
 __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
   using G = Geo<N>;
   __shared__ float2 lds[G::LDS_ELEMS];
@@ -370,7 +370,7 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
     const float2 g = SG ? v[s] : cscale(v[s], invN);
     const float x = fmaf(g.x, g.x, g.y * g.y);
     float phi, ft, fac;
-    pixel_terms<true>(x, d, a.eps, phi, ft, fac);
+    pixel_terms<true, EST>(x, d, a.eps, phi, ft, fac);
     acc_phi += (double)phi;
     acc_f += (double)ft;
     v[s] = cscale(g, fac * invN);
@@ -400,7 +400,7 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
   }
 }
 
-template <int N, DataLayout LAY, bool LINC_O, bool LINC_P>
+template <int N, DataLayout LAY, bool LINC_O, bool LINC_P, int EST>
 __global__ PTYG_PATTERN_KERNEL(N) void k_minfunc(PatArgs a) {
   using G = Geo<N>;
   __shared__ float2 lds[G::LDS_ELEMS];
@@ -430,7 +430,7 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_minfunc(PatArgs a) {
     float phi, ft, fac;
     // the solver's line search (transposed intensities) needs only Phi
     constexpr bool WANT_F = LAY == DataLayout::Rows;
-    pixel_terms<WANT_F>(x, d, a.eps, phi, ft, fac);
+    pixel_terms<WANT_F, EST>(x, d, a.eps, phi, ft, fac);
     acc_phi += (double)phi;
     if constexpr (WANT_F) acc_f += (double)ft;
   }
@@ -799,7 +799,7 @@ __global__ __launch_bounds__(kVecWG) void k_sum_copies(const float2* src, int co
 // A + g_j B (+ g_j^2 C), evaluated with the same per-pixel deviance as a
 // MINFUNC pass for every listed element (d > 0 or NaN), FP64 accumulation
 // per trial, per-workgroup partials in a fixed order.
-template <bool QUAD>
+template <bool QUAD, int EST>
 __global__ __launch_bounds__(256) void k_ls_batch(LsArgs a) {
   __shared__ double red[4][kLsRow];
   double acc[kLsRow];
@@ -831,7 +831,7 @@ __global__ __launch_bounds__(256) void k_ls_batch(LsArgs a) {
           xi = fmaf(g2, cv.y, xi);
         }
         float phi, ft, fac;
-        pixel_terms<false>(fmaf(xr, xr, xi * xi), dv, a.eps, phi, ft, fac);
+        pixel_terms<false, EST>(fmaf(xr, xr, xi * xi), dv, a.eps, phi, ft, fac);
         acc[j] += (double)phi;
       }
     }
@@ -971,13 +971,16 @@ hipError_t launch_grad(const PatArgs& a, DataLayout lay, int* blocks_out, hipStr
     const int nb = pattern_blocks<N>(a.K);
     if (blocks_out) *blocks_out = nb;
     const dim3 g(nb), b(Geo<N>::WG);
-    if (lay == DataLayout::Transposed) {
-      if (a.gstore) hipLaunchKernelGGL((k_grad<N, DataLayout::Transposed, true>), g, b, 0, s, a);
-      else hipLaunchKernelGGL((k_grad<N, DataLayout::Transposed, false>), g, b, 0, s, a);
-    } else {
-      hipLaunchKernelGGL((k_grad<N, DataLayout::Rows, false>), g, b, 0, s, a);
-    }
-    return hipGetLastError();
+    return dispatch_est(a.est, [&](auto ec) {
+      constexpr int E = decltype(ec)::value;
+      if (lay == DataLayout::Transposed) {
+        if (a.gstore) hipLaunchKernelGGL((k_grad<N, DataLayout::Transposed, true, E>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_grad<N, DataLayout::Transposed, false, E>), g, b, 0, s, a);
+      } else {
+        hipLaunchKernelGGL((k_grad<N, DataLayout::Rows, false, E>), g, b, 0, s, a);
+      }
+      return hipGetLastError();
+    });
   });
 }
 
@@ -1030,9 +1033,12 @@ hipError_t launch_ls_batch(const LsArgs& a, int* blocks_out, hipStream_t s) {
   const int64_t want = (a.n + 255) / 256;
   const int nb = (int)(want < 1 ? 1 : (want < kLsBlocks ? want : kLsBlocks));
   if (blocks_out) *blocks_out = nb;
-  if (a.C) hipLaunchKernelGGL(k_ls_batch<true>, dim3(nb), dim3(256), 0, s, a);
-  else hipLaunchKernelGGL(k_ls_batch<false>, dim3(nb), dim3(256), 0, s, a);
-  return hipGetLastError();
+  return dispatch_est(a.est, [&](auto ec) {
+    constexpr int E = decltype(ec)::value;
+    if (a.C) hipLaunchKernelGGL((k_ls_batch<true, E>), dim3(nb), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_ls_batch<false, E>), dim3(nb), dim3(256), 0, s, a);
+    return hipGetLastError();
+  });
 }
 
 hipError_t launch_ls_finalize(const double* partials, int count, double* out, hipStream_t s) {
@@ -1050,18 +1056,22 @@ hipError_t launch_minfunc(const PatArgs& a, DataLayout lay, int* blocks_out, hip
     if (blocks_out) *blocks_out = nb;
     const dim3 g(nb), b(Geo<N>::WG);
     const bool lo = a.dobj != nullptr, lp = a.dprobe != nullptr;
-    if (lay == DataLayout::Transposed) {
-      if (lo && lp) hipLaunchKernelGGL((k_minfunc<N, DataLayout::Transposed, true, true>), g, b, 0, s, a);
-      else if (lo) hipLaunchKernelGGL((k_minfunc<N, DataLayout::Transposed, true, false>), g, b, 0, s, a);
-      else if (lp) hipLaunchKernelGGL((k_minfunc<N, DataLayout::Transposed, false, true>), g, b, 0, s, a);
-      else hipLaunchKernelGGL((k_minfunc<N, DataLayout::Transposed, false, false>), g, b, 0, s, a);
-    } else {
-      if (lo && lp) hipLaunchKernelGGL((k_minfunc<N, DataLayout::Rows, true, true>), g, b, 0, s, a);
-      else if (lo) hipLaunchKernelGGL((k_minfunc<N, DataLayout::Rows, true, false>), g, b, 0, s, a);
-      else if (lp) hipLaunchKernelGGL((k_minfunc<N, DataLayout::Rows, false, true>), g, b, 0, s, a);
-      else hipLaunchKernelGGL((k_minfunc<N, DataLayout::Rows, false, false>), g, b, 0, s, a);
-    }
-    return hipGetLastError();
+    return dispatch_est(a.est, [&](auto ec) {
+      constexpr int E = decltype(ec)::value;
+      constexpr DataLayout T = DataLayout::Transposed, R = DataLayout::Rows;
+      if (lay == T) {
+        if (lo && lp) hipLaunchKernelGGL((k_minfunc<N, T, true, true, E>), g, b, 0, s, a);
+        else if (lo) hipLaunchKernelGGL((k_minfunc<N, T, true, false, E>), g, b, 0, s, a);
+        else if (lp) hipLaunchKernelGGL((k_minfunc<N, T, false, true, E>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_minfunc<N, T, false, false, E>), g, b, 0, s, a);
+      } else {
+        if (lo && lp) hipLaunchKernelGGL((k_minfunc<N, R, true, true, E>), g, b, 0, s, a);
+        else if (lo) hipLaunchKernelGGL((k_minfunc<N, R, true, false, E>), g, b, 0, s, a);
+        else if (lp) hipLaunchKernelGGL((k_minfunc<N, R, false, true, E>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_minfunc<N, R, false, false, E>), g, b, 0, s, a);
+      }
+      return hipGetLastError();
+    });
   });
 }
 

@@ -5,6 +5,7 @@
 
 #include <cstddef>
 #include <cstdint>
+#include <type_traits>
 
 namespace ptyg {
 
@@ -23,6 +24,7 @@ struct PatArgs {
   float2* ubuf;          // per-pattern back-propagated waves u_k = F^H r_k, [K][N][N]
   double* partials;      // per-workgroup (phi, f) pairs
   float eps;
+  int est;               // estimator: kEstML (Eq. ML) or kEstLS (least squares on amplitudes)
   float2* gstore;        // GRAD: far field G psi, per-pattern transposed (batched line search); nullable
   // batched line search: GRAD with gstore writes per-workgroup sums of
   // |G psi|^2 to zs_part; the direction forward writes rows of 4:
@@ -51,6 +53,7 @@ struct LsArgs {
   const int* idx;   // compacted element indices
   int64_t n;        // number of listed elements
   int J;            // trials in this pass, 1..kLsBatch
+  int est;          // estimator (as PatArgs::est)
   float eps;
   float g[kLsBatch];
   double* partials;  // [blocks][kLsRow]
@@ -68,6 +71,17 @@ struct VecArgs {
 };
 
 enum class DataLayout { Rows = 0, Transposed = 1 };
+
+// Calls f with std::integral_constant<int, est> for a supported estimator
+// (0: Poisson ML, 1: least squares), else returns hipErrorInvalidValue.
+template <typename F>
+hipError_t dispatch_est(int est, F&& f) {
+  switch (est) {
+    case 0: return f(std::integral_constant<int, 0>{});
+    case 1: return f(std::integral_constant<int, 1>{});
+    default: return hipErrorInvalidValue;
+  }
+}
 
 // Launchers; each returns hipSuccess or the launch error.  `blocks_out`
 // receives the number of (phi, f) partial pairs written.

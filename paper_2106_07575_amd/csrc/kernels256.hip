@@ -139,7 +139,7 @@ __global__ PTYG_SUB_KERNEL void k_sub_inv(PatArgs a) {
 // k = i >> 14.  MODE 0: forward only (writes far, unitary).  MODE 1: GRAD
 // (objective partials, residual adjoint written back as R).  MODE 2:
 // objective only.  MODE 3: adjoint of a given far field (writes R).
-template <int MODE, DataLayout LAY>
+template <int MODE, DataLayout LAY, int EST = 0>
 __global__ __launch_bounds__(256) void k_combine(PatArgs a, int64_t items) {
   __shared__ double red[16];
   double acc_phi = 0.0, acc_f = 0.0;
@@ -211,7 +211,7 @@ __global__ __launch_bounds__(256) void k_combine(PatArgs a, int64_t items) {
         }
         const float x = fmaf(g[j].x, g[j].x, g[j].y * g[j].y);
         float phi, ft, fac;
-        pixel_terms<MODE == 1 || LAY == DataLayout::Rows>(x, d, a.eps, phi, ft, fac);
+        pixel_terms<MODE == 1 || LAY == DataLayout::Rows, EST>(x, d, a.eps, phi, ft, fac);
         acc_phi += (double)phi;
         if constexpr (MODE == 1 || LAY == DataLayout::Rows) acc_f += (double)ft;
         r[j] = cscale(g[j], fac);
@@ -281,11 +281,16 @@ hipError_t combine(const PatArgs& a, DataLayout lay, int* blocks_out, hipStream_
   const int nb = combine_blocks(a.K);
   const int64_t items = (int64_t)a.K * SUB;
   if (blocks_out) *blocks_out = nb;
-  if (lay == DataLayout::Transposed)
-    hipLaunchKernelGGL((k_combine<MODE, DataLayout::Transposed>), dim3(nb), dim3(256), 0, s, a, items);
-  else
-    hipLaunchKernelGGL((k_combine<MODE, DataLayout::Rows>), dim3(nb), dim3(256), 0, s, a, items);
-  return hipGetLastError();
+  // the estimator only enters the modes with objective terms
+  const int est = (MODE == 1 || MODE == 2) ? a.est : 0;
+  return dispatch_est(est, [&](auto ec) {
+    constexpr int E = (MODE == 1 || MODE == 2) ? decltype(ec)::value : 0;
+    if (lay == DataLayout::Transposed)
+      hipLaunchKernelGGL((k_combine<MODE, DataLayout::Transposed, E>), dim3(nb), dim3(256), 0, s, a, items);
+    else
+      hipLaunchKernelGGL((k_combine<MODE, DataLayout::Rows, E>), dim3(nb), dim3(256), 0, s, a, items);
+    return hipGetLastError();
+  });
 }
 
 hipError_t sub_fwd(const PatArgs& a, hipStream_t s) {

@@ -13,7 +13,7 @@ constexpr float kLn2 = 0.69314718055994530942f;
 static __device__ const float kTwCosDev[kTwM] = PTYG_TW_COS;
 static __device__ const float kTwSinDev[kTwM] = PTYG_TW_SIN;
 
-// Per-pixel objective terms and residual factor (Eqs. ML, gradient).
+// Per-pixel Poisson objective terms and residual factor (Eqs. ML, gradient).
 //   phi   : deviance x - d - d log(max(x,eps)/d)  (x for d = 0)
 //   fterm : x - d log max(x, eps)                  (x for d = 0)
 //   fac   : 1 - d/x for x >= eps, 1 otherwise      (r = g * fac)
@@ -21,9 +21,33 @@ static __device__ const float kTwSinDev[kTwM] = PTYG_TW_SIN;
 // a series for |delta| < 0.1 (no cancellation near a fit), otherwise the
 // log of the ratio x/d itself (1 + delta would round to 0 for x << d).
 // A NaN intensity propagates into every term.
-template <bool WANT_F>
+// Estimators: the Poisson maximum likelihood of Eq. ML, or least squares on
+// the amplitudes (the paper's LS estimate; it gives no formula, the usual one
+// is F = sum (|g| - sqrt d)^2 with the Wirtinger residual g - sqrt(d) g/|g|).
+enum : int { kEstML = 0, kEstLS = 1 };
+
+// Least-squares terms: phi = fterm = (sqrt x - sqrt d)^2, formed as
+// ((x - d) / (sqrt x + sqrt d))^2 (x - d is exact near a fit); x for d <= 0;
+// fac = 1 - sqrt(d / x) for x >= eps, 1 otherwise.  NaN intensities propagate.
+__device__ __forceinline__ void pixel_terms_ls(float x, float d, float eps, float& phi, float& fac) {
+  const bool dpos = !(d <= 0.0f);
+  const bool big = x >= eps;
+  const float sd = __builtin_sqrtf(dpos ? d : 0.0f);
+  const float sx = __builtin_sqrtf(x);
+  const float den = sx + sd;
+  const float diff = (x - d) * __builtin_amdgcn_rcpf(den > 0.0f ? den : 1.0f);
+  phi = dpos ? diff * diff : x;
+  fac = (big && dpos) ? 1.0f - sd * __builtin_amdgcn_rsqf(big ? x : 1.0f) : 1.0f;
+}
+
+template <bool WANT_F, int EST = kEstML>
 __device__ __forceinline__ void pixel_terms(float x, float d, float eps, float& phi, float& fterm,
                                             float& fac) {
+  if constexpr (EST == kEstLS) {
+    pixel_terms_ls(x, d, eps, phi, fac);
+    if constexpr (WANT_F) fterm = phi;
+    return;
+  }
   const bool dpos = !(d <= 0.0f);  // NaN counts as positive so that it propagates
   const bool big = x >= eps;
   const float rd = __builtin_amdgcn_rcpf(dpos ? d : 1.0f);

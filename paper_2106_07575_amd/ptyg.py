@@ -37,10 +37,13 @@ class CgOpts(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int32), ("update_probe", ctypes.c_int32),
                 ("gamma0", ctypes.c_double), ("tau", ctypes.c_double), ("t", ctypes.c_double),
                 ("max_halvings", ctypes.c_int32), ("eps", ctypes.c_double),
-                ("target_phi", ctypes.c_double), ("line_search", ctypes.c_int32)]
+                ("target_phi", ctypes.c_double), ("line_search", ctypes.c_int32),
+                ("estimator", ctypes.c_int32)]
 
 
 LINE_SEARCH = {"sequential": 0, "batched": 1}
+# Poisson maximum likelihood (Eq. ML) or least squares on the amplitudes
+ESTIMATOR = {"ml": 0, "ls": 1}
 
 
 class IterStats(ctypes.Structure):
@@ -58,13 +61,16 @@ _SIGS = {
     "ptyg_check_positions": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, ctypes.c_size_t, _P]),
     "ptyg_forward": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "ptyg_adjoint": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
-    "ptyg_grad": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P, ctypes.c_float, _P, _P, _P, _P,
-                                   ctypes.c_size_t, _P]),
+    "ptyg_grad": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P, ctypes.c_float, ctypes.c_int32, _P, _P,
+                                   _P, _P, ctypes.c_size_t, _P]),
     "ptyg_minfunc": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P, ctypes.c_double, _P, _P,
-                                      ctypes.c_float, _P, _P, ctypes.c_size_t, _P]),
+                                      ctypes.c_float, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P]),
     "ptyg_cg_solve": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P, ctypes.POINTER(CgOpts), _P,
                                        ctypes.c_size_t, ctypes.POINTER(IterStats),
                                        ctypes.POINTER(ctypes.c_int32), _P]),
+    "ptyg_gd_solve": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P, ctypes.c_int32, ctypes.c_double,
+                                       ctypes.c_int32, ctypes.c_float, ctypes.c_int32, _P, ctypes.c_size_t,
+                                       ctypes.POINTER(ctypes.c_double), _P]),
     "ptyg_debug_gather": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P]),
     "ptyg_debug_scatter": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P]),
     "ptyg_debug_lane_swap": (ctypes.c_int32, [_P, _P, _P]),
@@ -194,7 +200,7 @@ def adjoint(far, probe, pos, obj_shape, obj=None, want_probe: bool = False):
     return out, pout
 
 
-def grad(obj, probe, pos, data, want_probe: bool = False, eps: float = 1e-32, ws=None):
+def grad(obj, probe, pos, data, want_probe: bool = False, eps: float = 1e-32, ws=None, estimator: str = "ml"):
     """GRAD stage: returns (objective f64 [2] = (Phi, F), grad_obj, grad_probe or None)."""
     obj, probe, pos, d = _common(obj, probe, pos)
     data = _dev(data, "data", torch.float32)
@@ -205,12 +211,13 @@ def grad(obj, probe, pos, data, want_probe: bool = False, eps: float = 1e-32, ws
     objective = torch.empty(2, dtype=torch.float64, device=obj.device)
     ws = workspace(d, obj.device) if ws is None else ws
     _check(load().ptyg_grad(ctypes.byref(d), _ptr(obj), _ptr(probe), _ptr(pos), _ptr(data), float(eps),
-                            _ptr(g), _ptr(gp), _ptr(objective), _ptr(ws), ws.numel(), _stream()))
+                            ESTIMATOR[estimator], _ptr(g), _ptr(gp), _ptr(objective), _ptr(ws), ws.numel(),
+                            _stream()))
     return objective, g, gp
 
 
 def minfunc(obj, probe, pos, data, dir_obj=None, dir_probe=None, gamma: float = 0.0,
-            eps: float = 1e-32, ws=None) -> torch.Tensor:
+            eps: float = 1e-32, ws=None, estimator: str = "ml") -> torch.Tensor:
     """Objective (Phi, F) at (obj + gamma dir_obj, probe + gamma dir_probe)."""
     obj, probe, pos, d = _common(obj, probe, pos)
     data = _dev(data, "data", torch.float32)
@@ -221,8 +228,8 @@ def minfunc(obj, probe, pos, data, dir_obj=None, dir_probe=None, gamma: float = 
     objective = torch.empty(2, dtype=torch.float64, device=obj.device)
     ws = workspace(d, obj.device) if ws is None else ws
     _check(load().ptyg_minfunc(ctypes.byref(d), _ptr(obj), _ptr(dir_obj), _ptr(probe), _ptr(dir_probe),
-                               float(gamma), _ptr(pos), _ptr(data), float(eps), _ptr(objective), _ptr(ws),
-                               ws.numel(), _stream()))
+                               float(gamma), _ptr(pos), _ptr(data), float(eps), ESTIMATOR[estimator],
+                               _ptr(objective), _ptr(ws), ws.numel(), _stream()))
     return objective
 
 
@@ -236,7 +243,8 @@ class CgResult:
 
 def cg_solve(obj0, probe, pos, data, iters: int, update_probe: bool = False, gamma0: float = 1.0,
              tau: float = 0.5, t: float = 0.0, max_halvings: int = 40, eps: float = 1e-32,
-             target_phi: float | None = None, ws=None, line_search: str = "sequential") -> CgResult:
+             target_phi: float | None = None, ws=None, line_search: str = "sequential",
+             estimator: str = "ml") -> CgResult:
     """ML-CG (Algorithm 1).  Works on copies of obj0 / probe.  line_search:
     "sequential" (one MINFUNC pass per trial) or "batched" (trials evaluated
     from stored far fields, up to 16 per pass; the workspace must then be
@@ -246,7 +254,8 @@ def cg_solve(obj0, probe, pos, data, iters: int, update_probe: bool = False, gam
     obj = obj.clone()
     probe_c = probe_c.clone()
     o = CgOpts(int(iters), int(update_probe), float(gamma0), float(tau), float(t), int(max_halvings),
-               float(eps), -1.0 if target_phi is None else float(target_phi), LINE_SEARCH[line_search])
+               float(eps), -1.0 if target_phi is None else float(target_phi), LINE_SEARCH[line_search],
+               ESTIMATOR[estimator])
     ws = workspace(d, obj.device, update_probe, line_search) if ws is None else ws
     trace = (IterStats * max(1, iters))()
     done = ctypes.c_int32(0)
@@ -255,6 +264,22 @@ def cg_solve(obj0, probe, pos, data, iters: int, update_probe: bool = False, gam
     rows = [{"phi": r.phi, "f": r.f_eq2, "gamma": r.gamma, "beta": r.beta, "step_norm": r.step_norm,
              "halvings": r.halvings, "restarted": bool(r.restarted)} for r in trace[:done.value]]
     return CgResult(obj, probe_c, rows, done.value)
+
+
+def gd_solve(obj0, probe, pos, data, iters: int, gamma: float, update_probe: bool = False,
+             eps: float = 1e-32, ws=None, estimator: str = "ml"):
+    """Gradient descent (Eq. update2) with a constant step.  Works on copies;
+    returns (obj, probe, [Phi at obj_m for every iteration])."""
+    obj, probe_c, pos, d = _common(obj0, probe, pos)
+    data = _dev(data, "data", torch.float32)
+    obj = obj.clone()
+    probe_c = probe_c.clone()
+    ws = workspace(d, obj.device, update_probe) if ws is None else ws
+    phis = (ctypes.c_double * max(1, iters))()
+    _check(load().ptyg_gd_solve(ctypes.byref(d), _ptr(obj), _ptr(probe_c), _ptr(pos), _ptr(data), int(iters),
+                                float(gamma), int(update_probe), float(eps), ESTIMATOR[estimator], _ptr(ws),
+                                ws.numel(), phis, _stream()))
+    return obj, probe_c, list(phis[:iters])
 
 
 def check_positions(pos, obj_shape, n: int):

@@ -40,7 +40,7 @@ def rel(a, b):
     return float(np.linalg.norm((a - b).ravel()) / max(np.linalg.norm(b.ravel()), 1e-300))
 
 
-def grad_with_floor(psi, probe, pos, data, want_probe=False):
+def grad_with_floor(psi, probe, pos, data, want_probe=False, estimator="ml"):
     """Oracle gradient plus its FP32 conditioning floor.
 
     The Poisson residual g - d g/|g|^2 amplifies far-field errors by d/|g|^2,
@@ -50,9 +50,9 @@ def grad_with_floor(psi, probe, pos, data, want_probe=False):
     its forward and inverse transforms are rounded to single precision
     (fp32_transforms).  Returns (ref, floor_obj, floor_probe)."""
     args = (psi.astype(np.complex128), probe.astype(np.complex128), pos, data.astype(np.float64))
-    ref = O.grad(*args, want_probe=want_probe)
+    ref = O.grad(*args, want_probe=want_probe, estimator=estimator)
     with fp32_transforms():
-        pert = O.grad(*args, want_probe=want_probe)
+        pert = O.grad(*args, want_probe=want_probe, estimator=estimator)
     fo = rel(pert["grad_obj"], ref["grad_obj"])
     fp = rel(pert["grad_probe"], ref["grad_probe"]) if want_probe else None
     return ref, fo, fp
@@ -99,6 +99,15 @@ def cg_with_floor(obj0, probe, pos, data, iters, **kw):
     ref = O.cg_solve(*args, **kw)
     with fp32_transforms():
         pert = O.cg_solve(*args, **kw)
+    return ref, pert
+
+
+def gd_with_floor(obj0, probe, pos, data, iters, gamma, **kw):
+    """(oracle FP64 gradient descent, the same with FP32-rounded transforms)."""
+    args = (obj0.astype(np.complex128), probe.astype(np.complex128), pos, data.astype(np.float64), iters, gamma)
+    ref = O.gd_solve(*args, **kw)
+    with fp32_transforms():
+        pert = O.gd_solve(*args, **kw)
     return ref, pert
 
 

@@ -1,0 +1,93 @@
+"""Gradient descent (Eq. update2) on the GPU (ptyg_gd_solve) against the
+oracle's.  GD with a stable step is not chaotic: the GPU iterate must stay
+within max(1e-4, 5x) the divergence of the oracle's own GD when its
+transforms are rounded to FP32, its objectives within max(1e-5, 5x that
+oracle's largest relative objective departure)."""
+import numpy as np
+import pytest
+
+from oracle import ptycho as O
+
+from _cases import FLOOR_FACTOR, gd_with_floor, rel, workload
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_07575_amd import ptyg
+    ptyg.load()
+    return ptyg
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+def stable_gamma(probe, pos, shape):
+    return 0.1 / O.illumination(probe.astype(np.complex128), pos, shape).max()
+
+
+@pytest.mark.parametrize("case,iters", [("c1", 16), ("m32", 10), ("m128", 6), ("m256", 3)])
+def test_gd_parity(P, case, iters):
+    cfg, inp, probe, obj, data = workload(case)
+    obj0 = np.ones(obj.shape, np.complex64)
+    gamma = stable_gamma(probe, inp.pos, obj.shape)
+    print(f"gd {case} {iters} it gamma {gamma:.3e}", flush=True)
+    o, _, phis = P.gd_solve(dev(obj0), dev(probe), dev(inp.pos), dev(data), iters, gamma)
+    (ro, rp, rtr), (po, pp, ptr) = gd_with_floor(obj0, probe, inp.pos, data, iters, gamma)
+    err = rel(o.cpu().numpy(), ro)
+    floor = rel(po, ro)
+    print(f"   object rel {err:.2e} (fp32 floor {floor:.2e}); phi {phis[-1]:.6e} oracle {rtr[-1]['phi']:.6e}")
+    assert err <= max(1e-4, FLOOR_FACTOR * floor)
+    # objectives: 1e-5 relative, or 5x the largest relative departure of the
+    # FP32-rounded oracle's objectives over the run (the iterates part at the
+    # floor level; a single iteration's departure can be accidentally small)
+    pfloor = max(abs(c["phi"] - b["phi"]) / abs(b["phi"]) for b, c in zip(rtr, ptr))
+    for a, b in zip(phis, rtr):
+        assert abs(a - b["phi"]) <= max(1e-5, FLOOR_FACTOR * pfloor) * abs(b["phi"])
+
+
+def test_gd_zero_data_closed_form(P):
+    cfg, inp, probe, obj, data = workload("m32")
+    rng = np.random.default_rng(9)
+    psi0 = (rng.standard_normal(obj.shape) + 1j * rng.standard_normal(obj.shape)).astype(np.complex64)
+    illum = O.illumination(probe.astype(np.complex128), inp.pos, obj.shape)
+    gamma = 0.3 / illum.max()
+    o, _, phis = P.gd_solve(dev(psi0), dev(probe), dev(inp.pos), dev(np.zeros_like(data)), 4, gamma)
+    want = (1.0 - gamma * illum) ** 4 * psi0
+    assert rel(o.cpu().numpy(), want) <= 1e-5
+    assert abs(phis[0] - np.sum(illum * np.abs(psi0.astype(np.complex128)) ** 2)) <= 1e-5 * phis[0]
+
+
+def test_gd_joint_probe(P):
+    cfg, inp, probe, obj, data = workload("m16r")
+    p0 = (np.abs(probe) * np.exp(0.2j)).astype(np.complex64)
+    obj0 = np.ones(obj.shape, np.complex64)
+    gamma = stable_gamma(probe, inp.pos, obj.shape)
+    o, p, phis = P.gd_solve(dev(obj0), dev(p0), dev(inp.pos), dev(data), 4, gamma, update_probe=True)
+    (ro, rp, rtr), (po, pp, ptr) = gd_with_floor(obj0, p0, inp.pos, data, 4, gamma, update_probe=True)
+    eo, ep = rel(o.cpu().numpy(), ro), rel(p.cpu().numpy(), rp)
+    fo, fp = rel(po, ro), rel(pp, rp)
+    print(f"joint gd: object rel {eo:.2e} (floor {fo:.2e}) probe rel {ep:.2e} (floor {fp:.2e})")
+    assert eo <= max(1e-4, FLOOR_FACTOR * fo) and ep <= max(1e-4, FLOOR_FACTOR * fp)
+
+
+def test_gd_zero_step_is_identity(P):
+    cfg, inp, probe, obj, data = workload("c1")
+    o0 = dev(np.ones(obj.shape, np.complex64))
+    o, _, phis = P.gd_solve(o0, dev(probe), dev(inp.pos), dev(data), 3, 0.0)
+    assert torch.equal(o, o0)
+    assert phis[0] == phis[1] == phis[2]
+
+
+def test_gd_nonfinite_data_is_reported(P):
+    cfg, inp, probe, obj, data = workload("c1")
+    bad = data.copy()
+    bad[1, 1, 1] = np.inf
+    with pytest.raises(P.PtygError) as e:
+        P.gd_solve(dev(np.ones(obj.shape, np.complex64)), dev(probe), dev(inp.pos), dev(bad), 2, 1e-3)
+    assert e.value.status == -4
