@@ -196,6 +196,29 @@ ptyg_status ptyg_gd_solve(const ptyg_dims* dims, ptyg_c64* obj, ptyg_c64* probe,
                           int32_t estimator, void* ws, size_t ws_bytes, double* phi_trace,
                           ptyg_stream_t stream);
 
+/* Multi-view batch (3-D ptychography: many independent projections, which
+ * the paper's introduction and outlook name as the larger use case; the
+ * paper solves one projection at a time): `views` independent ML-CG solves
+ * of equal shape run as one set of launches -- the views are stacked into
+ * one object of views * obj_h rows, so the pattern kernels see views * k
+ * patterns, and every reduction, direction, step and line-search decision
+ * is per view.  Each view's iterates are those ptyg_cg_solve gives for it
+ * alone, up to the order of floating-point sums.
+ * dims: ONE view (obj_h, obj_w, n, k); n <= 128; k a multiple of the
+ * patterns per workgroup (16 for n = 16, 8 for n = 32, 2 for n = 64);
+ * k*n*n a multiple of 4096.
+ * obj: [views][obj_h][obj_w] (in: psi_0, out: iterates); probe: [n][n],
+ * shared and fixed (object-only); pos: [views][k][2], each inside its own
+ * view's object; data: [views][k][n][n].  opts as for ptyg_cg_solve, with
+ * update_probe = 0 and target_phi < 0.  trace: HOST [views][opts->iters]
+ * rows (nullable); iters_done: HOST (nullable).  Workspace:
+ * ptyg_views_workspace_size bytes (0 means invalid arguments). */
+size_t ptyg_views_workspace_size(const ptyg_dims* dims, int32_t views, const ptyg_cg_opts* opts);
+ptyg_status ptyg_cg_solve_views(const ptyg_dims* dims, int32_t views, ptyg_c64* obj, const ptyg_c64* probe,
+                                const int32_t* pos, const float* data, const ptyg_cg_opts* opts, void* ws,
+                                size_t ws_bytes, ptyg_cg_iter_stats* trace, int32_t* iters_done,
+                                ptyg_stream_t stream);
+
 /* Opt-in kernel timing for benchmarks: when enabled, the fused GRAD kernel
  * (kind 0), the line-search kernel (kind 1: a MINFUNC pass, or a batched
  * pass over stored far fields), the forward transform of the search

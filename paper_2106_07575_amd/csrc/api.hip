@@ -764,6 +764,304 @@ ptyg_status ptyg_gd_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
   return PTYG_OK;
 }
 
+namespace {
+// Multi-view batch: the views are stacked along the rows into one object of
+// views * obj_h rows; their patterns follow each other.
+struct ViewsLayout {
+  ptyg_dims stacked;
+  Layout L;  // of the stacked problem
+  size_t pos2, vparts, vout, vbeta, valpha, total;
+};
+
+ptyg_status views_layout(const ptyg_dims* d, int32_t views, const ptyg_cg_opts* opts, ViewsLayout* out) {
+  if (ptyg_status st = check_dims(d)) return st;
+  if (views < 1) return fail(PTYG_E_INVAL, "views=%d must be >= 1", views);
+  if (d->n > 128) return fail(PTYG_E_INVAL, "the multi-view batch supports n <= 128 (n=%d)", d->n);
+  const int ppw = patterns_per_block(d->n);
+  if (d->k % ppw) return fail(PTYG_E_INVAL, "k=%d per view must be a multiple of %d for n=%d", d->k, ppw, d->n);
+  const int64_t elems = (int64_t)d->k * d->n * d->n;
+  if (elems % kNzChunk)
+    return fail(PTYG_E_INVAL, "k*n*n=%lld per view must be a multiple of %d", (long long)elems, kNzChunk);
+  if ((int64_t)views * d->obj_h * d->obj_w >= (int64_t(1) << 31) || (int64_t)views * elems >= (int64_t(1) << 31))
+    return fail(PTYG_E_INVAL, "%d views of this size are too large", views);
+  if (opts && opts->update_probe) return fail(PTYG_E_INVAL, "the multi-view batch is object-only");
+  ViewsLayout V{};
+  V.stacked = *d;
+  V.stacked.obj_h = d->obj_h * views;
+  V.stacked.k = d->k * views;
+  V.L = layout(&V.stacked, false, opts && opts->line_search == PTYG_LS_BATCHED);
+  size_t o = V.L.total;
+  V.pos2 = o;
+  o = align_up(o + (size_t)V.stacked.k * sizeof(int2));
+  V.vparts = o;
+  o = align_up(o + (size_t)views * kSegBlocks * kLsRow * sizeof(double));
+  V.vout = o;
+  o = align_up(o + (size_t)views * 32 * sizeof(double));
+  V.vbeta = o;
+  o = align_up(o + (size_t)views * sizeof(double));
+  V.valpha = o;
+  o = align_up(o + (size_t)views * sizeof(double));
+  V.total = o;
+  *out = V;
+  return PTYG_OK;
+}
+}  // namespace
+
+size_t ptyg_views_workspace_size(const ptyg_dims* dims, int32_t views, const ptyg_cg_opts* opts) {
+  ViewsLayout V;
+  if (views_layout(dims, views, opts, &V) != PTYG_OK) return 0;
+  return V.total;
+}
+
+ptyg_status ptyg_cg_solve_views(const ptyg_dims* dims, int32_t views, ptyg_c64* obj_c, const ptyg_c64* probe_c,
+                                const int32_t* pos_i, const float* data, const ptyg_cg_opts* opts, void* ws,
+                                size_t ws_bytes, ptyg_cg_iter_stats* trace, int32_t* iters_done,
+                                ptyg_stream_t stream) {
+  if (!obj_c || !probe_c || !pos_i || !data || !opts) return fail(PTYG_E_INVAL, "NULL argument");
+  ViewsLayout VL;
+  if (ptyg_status st = views_layout(dims, views, opts, &VL)) return st;
+  if (opts->iters < 0) return fail(PTYG_E_INVAL, "iters < 0");
+  if (!(opts->tau > 0.0 && opts->tau < 1.0)) return fail(PTYG_E_INVAL, "tau must be in (0, 1)");
+  if (!(opts->gamma0 > 0.0) || !std::isfinite(opts->gamma0)) return fail(PTYG_E_INVAL, "gamma0 must be > 0");
+  if (opts->max_halvings < 1) return fail(PTYG_E_INVAL, "max_halvings must be >= 1");
+  if (!(opts->eps >= 0.0)) return fail(PTYG_E_INVAL, "eps must be >= 0");
+  if (opts->target_phi >= 0.0) return fail(PTYG_E_INVAL, "target_phi is not supported by the multi-view batch");
+  if (opts->line_search != PTYG_LS_SEQUENTIAL && opts->line_search != PTYG_LS_BATCHED)
+    return fail(PTYG_E_INVAL, "line_search=%d is not a PTYG_LS_* value", opts->line_search);
+  if (ptyg_status st = check_est(opts->estimator)) return st;
+  if (!ws || ((uintptr_t)ws) % kAlign) return fail(PTYG_E_INVAL, "workspace NULL or not 256-byte aligned");
+  if (ws_bytes < VL.total) return fail(PTYG_E_WORKSPACE, "workspace %zu bytes < required %zu", ws_bytes, VL.total);
+  if (iters_done) *iters_done = 0;
+  const int V = views;
+  const bool batched = opts->line_search == PTYG_LS_BATCHED;
+  const int est = opts->estimator;
+  const float eps = (float)opts->eps;
+  const ptyg_dims* D = &VL.stacked;
+  const Layout& L = VL.L;
+  const hipStream_t s = S(stream);
+  // every position inside its own view's object
+  {
+    ptyg_dims d1 = *dims;
+    d1.k = dims->k * V;
+    if (ptyg_status st = ptyg_check_positions(&d1, pos_i, ws, ws_bytes, stream)) return st;
+  }
+  float2* obj = reinterpret_cast<float2*>(obj_c);
+  const float2* probe = reinterpret_cast<const float2*>(probe_c);
+  int2* pos = at<int2>(ws, VL.pos2);
+  PTYG_HIP(launch_shift_views(reinterpret_cast<const int2*>(pos_i), dims->k, V, dims->obj_h, pos, s));
+  const int64_t on = (int64_t)dims->obj_h * dims->obj_w;  // per view
+  const int64_t pe = (int64_t)dims->k * dims->n * dims->n;  // pattern elements per view
+  float2* eta_o = at<float2>(ws, L.eta_obj);
+  float2* grad_o = at<float2>(ws, L.grad_obj);
+  float* dt = at<float>(ws, L.data_t);
+  double* partials = at<double>(ws, L.partials);
+  double* vparts = at<double>(ws, VL.vparts);
+  double* vout = at<double>(ws, VL.vout);  // [V][32]: per-view results
+  double* dbeta = at<double>(ws, VL.vbeta);
+  double* dalpha = at<double>(ws, VL.valpha);
+  float2* far_a = batched ? at<float2>(ws, L.far_a) : nullptr;
+  float2* far_b = batched ? at<float2>(ws, L.far_b) : nullptr;
+  PTYG_HIP(launch_transpose_data(data, dt, D->k, D->n, s));
+  PTYG_HIP(launch_zero(eta_o, on * V, s));
+  if (ptyg_status st = build_tiles(D, pos, ws, L, s)) return st;
+  const int cpv = (int)(pe / kNzChunk);  // compaction chunks per view
+  if (batched)
+    PTYG_HIP(launch_nz_compact(dt, pe * V, at<int>(ws, L.nz_counts), at<int>(ws, L.nz_offsets), at<int>(ws, L.nz_idx),
+                               s));
+
+  // per-view state
+  std::vector<double> h((size_t)V * 32), hbeta(V, 0.0), halpha(V, 0.0), phi_m(V), f_m(V), n3_prev(V, 0.0);
+  std::vector<double> lsrow((size_t)V * kLsRow), zc((size_t)V * 3);
+  std::vector<int> restart(V, 1), accepted(V), trials(V), last_trials(V, kLsBatch), restarted(V);
+  std::vector<double> gamma_v(V), beta_v(V), n3(V), eta2(V);
+  // vout slots: 0 phi, 1 f, 2 n1, 3 n2, 4 n3, 5 eta2, 6 |a|^2, 8..11 direction sums
+  for (int m = 0; m < opts->iters; ++m) {
+    // GRAD over every view in one launch; objectives and sums per view
+    if (ptyg_status st = run_grad(D, obj, probe, pos, dt, DataLayout::Transposed, eps, est, grad_o, nullptr,
+                                  nullptr, ws, L, s, far_a, nullptr))
+      return st;
+    PTYG_HIP(launch_finalize_views(partials, D->n, D->k, dims->k, V, 2, vparts, s));
+    PTYG_HIP(launch_dot2_views(grad_o, eta_o, on, V, vparts + 2 * V, s));
+    PTYG_HIP(launch_finalize_seg(vparts + 2 * V, kSegBlocks, 2, V, vparts + (size_t)V * kSegBlocks * 2 + 2 * V,
+                                 s));
+    if (batched) PTYG_HIP(launch_finalize_views(at<double>(ws, L.zparts), D->n, D->k, dims->k, V, 1, dalpha, s));
+    // gather [V][2] (phi, f), [V][2] (n1, n2), [V] |a|^2 to the host
+    std::vector<double> pf(2 * V), nn(2 * V), aa(V, 0.0);
+    PTYG_HIP(hipMemcpyAsync(pf.data(), vparts, 2 * V * sizeof(double), hipMemcpyDeviceToHost, s));
+    PTYG_HIP(hipMemcpyAsync(nn.data(), vparts + (size_t)V * kSegBlocks * 2 + 2 * V, 2 * V * sizeof(double),
+                            hipMemcpyDeviceToHost, s));
+    if (batched) PTYG_HIP(hipMemcpyAsync(aa.data(), dalpha, V * sizeof(double), hipMemcpyDeviceToHost, s));
+    PTYG_HIP(hipStreamSynchronize(s));
+    for (int v = 0; v < V; ++v) {
+      phi_m[v] = pf[2 * v];
+      f_m[v] = pf[2 * v + 1];
+      if (!std::isfinite(phi_m[v]))
+        return fail(PTYG_E_NONFINITE, "objective is %g at iteration %d of view %d", phi_m[v], m, v);
+      double beta = 0.0;
+      restarted[v] = restart[v];
+      if (!restart[v]) {
+        const double den = nn[2 * v + 1] - n3_prev[v];
+        if (std::isfinite(den) && den > 0.0 && std::isfinite(nn[2 * v])) beta = nn[2 * v] / den;
+        else restarted[v] = 1;
+      }
+      beta_v[v] = restarted[v] ? 0.0 : beta;
+      hbeta[v] = beta_v[v];
+    }
+    // DIR: eta_v = -grad_v + beta_v eta_v (beta 0 restarts; eta stays finite)
+    PTYG_HIP(hipMemcpyAsync(dbeta, hbeta.data(), V * sizeof(double), hipMemcpyHostToDevice, s));
+    PTYG_HIP(launch_dir_views(grad_o, eta_o, dbeta, on, V, vparts, s));
+    PTYG_HIP(launch_finalize_seg(vparts, kSegBlocks, 2, V, vout, s));
+    std::vector<double> de(2 * V);
+    PTYG_HIP(hipMemcpyAsync(de.data(), vout, 2 * V * sizeof(double), hipMemcpyDeviceToHost, s));
+
+    // LS: the same trial sequence for every view, per-view decisions
+    for (int v = 0; v < V; ++v) {
+      accepted[v] = 0;
+      trials[v] = 0;
+      gamma_v[v] = 0.0;
+    }
+    int pending = V;
+    if (batched) {
+      PatArgs fa = base_args(D);
+      fa.pos = pos;
+      fa.ubuf = at<float2>(ws, L.ubuf);
+      fa.far = far_b;
+      fa.obj = eta_o;
+      fa.probe = probe;
+      fa.zs_p = far_a;
+      fa.zs_part = at<double>(ws, L.zparts) + L.n_partials;
+      {
+        TimedLaunch tl_fwd(2, s);
+        PTYG_HIP(launch_fwd_t(fa, false, s));
+      }
+      PTYG_HIP(launch_finalize_views(fa.zs_part, D->n, D->k, dims->k, V, 4, vout + 2 * V, s));
+      std::vector<double> zs4(4 * V);
+      PTYG_HIP(hipMemcpyAsync(zs4.data(), vout + 2 * V, 4 * V * sizeof(double), hipMemcpyDeviceToHost, s));
+      LsArgs la{};
+      la.A = far_a;
+      la.B = far_b;
+      la.d = dt;
+      la.idx = at<int>(ws, L.nz_idx);
+      la.eps = eps;
+      la.est = est;
+      la.partials = vparts;
+      int j0 = 1;
+      bool first = true;
+      double g_run = opts->gamma0;
+      while (j0 <= opts->max_halvings && pending > 0) {
+        int J = std::min(kLsBatch, opts->max_halvings - j0 + 1);
+        if (first) {
+          int want = 4;
+          for (int v = 0; v < V; ++v) want = std::max(want, last_trials[v] + 2);
+          J = std::min(J, want);
+        }
+        double gam[kLsBatch];
+        for (int i = 0; i < J; ++i) {
+          g_run *= opts->tau;
+          gam[i] = g_run;
+          la.g[i] = (float)g_run;
+        }
+        la.J = J;
+        {
+          TimedLaunch tl(1, s);
+          PTYG_HIP(launch_ls_batch_views(la, at<int>(ws, L.nz_offsets), cpv, V, s));
+        }
+        PTYG_HIP(launch_ls_finalize_views(vparts, V, vout + 8 * V, s));
+        PTYG_HIP(hipMemcpyAsync(lsrow.data(), vout + 8 * V, (size_t)V * kLsRow * sizeof(double),
+                                hipMemcpyDeviceToHost, s));
+        PTYG_HIP(hipStreamSynchronize(s));
+        for (int v = 0; v < V; ++v) {
+          const double* row = lsrow.data() + (size_t)v * kLsRow;
+          if (first) {
+            n3[v] = de[2 * v];
+            eta2[v] = de[2 * v + 1];
+            zc[3 * v + 0] = aa[v] - row[kLsBatch + 0];
+            zc[3 * v + 1] = zs4[4 * v + 0] - row[kLsBatch + 1];
+            zc[3 * v + 2] = zs4[4 * v + 2] - row[kLsBatch + 2];
+          }
+          if (accepted[v]) continue;
+          for (int i = 0; i < J; ++i) {
+            trials[v] = j0 + i;
+            const double g = (double)la.g[i];
+            const double zero = zc[3 * v] + 2.0 * g * zc[3 * v + 1] + g * g * zc[3 * v + 2];
+            if (row[i] + zero <= phi_m[v] + gam[i] * opts->t) {
+              accepted[v] = 1;
+              gamma_v[v] = gam[i];
+              --pending;
+              break;
+            }
+          }
+        }
+        j0 += J;
+        first = false;
+      }
+      for (int v = 0; v < V; ++v)
+        if (accepted[v]) last_trials[v] = trials[v];
+    } else {
+      PTYG_HIP(hipStreamSynchronize(s));
+      for (int v = 0; v < V; ++v) {
+        n3[v] = de[2 * v];
+        eta2[v] = de[2 * v + 1];
+      }
+      double gamma = opts->gamma0;
+      for (int j = 1; j <= opts->max_halvings && pending > 0; ++j) {
+        gamma *= opts->tau;
+        PatArgs a = base_args(D);
+        a.obj = obj;
+        a.dobj = eta_o;
+        a.probe = probe;
+        a.gamma = (float)gamma;
+        a.pos = pos;
+        a.data = dt;
+        a.eps = eps;
+        a.est = est;
+        a.partials = partials;
+        a.ubuf = at<float2>(ws, L.ubuf);
+        {
+          TimedLaunch tl(1, s);
+          PTYG_HIP(launch_minfunc(a, DataLayout::Transposed, nullptr, s));
+        }
+        PTYG_HIP(launch_finalize_views(partials, D->n, D->k, dims->k, V, 2, vout + 8 * V, s));
+        std::vector<double> pt(2 * V);
+        PTYG_HIP(hipMemcpyAsync(pt.data(), vout + 8 * V, 2 * V * sizeof(double), hipMemcpyDeviceToHost, s));
+        PTYG_HIP(hipStreamSynchronize(s));
+        for (int v = 0; v < V; ++v) {
+          if (accepted[v]) continue;
+          trials[v] = j;
+          if (pt[2 * v] <= phi_m[v] + gamma * opts->t) {
+            accepted[v] = 1;
+            gamma_v[v] = gamma;
+            --pending;
+          }
+        }
+      }
+    }
+    // Update: psi_v += gamma_v eta_v (0 for a failed search)
+    for (int v = 0; v < V; ++v) halpha[v] = accepted[v] ? gamma_v[v] : 0.0;
+    PTYG_HIP(hipMemcpyAsync(dalpha, halpha.data(), V * sizeof(double), hipMemcpyHostToDevice, s));
+    PTYG_HIP(launch_axpy_views(obj, eta_o, dalpha, on, V, s));
+    for (int v = 0; v < V; ++v) {
+      if (trace) {
+        ptyg_cg_iter_stats& t = trace[(size_t)v * opts->iters + m];
+        t.phi = phi_m[v];
+        t.f_eq2 = f_m[v];
+        t.gamma = halpha[v];
+        t.beta = beta_v[v];
+        t.step_norm = halpha[v] * std::sqrt(eta2[v] > 0.0 ? eta2[v] : 0.0);
+        t.halvings = accepted[v] ? trials[v] : opts->max_halvings;
+        t.restarted = restarted[v];
+      }
+      n3_prev[v] = n3[v];
+      restart[v] = !accepted[v];
+    }
+    // the host vectors copied to the device above must outlive the copies
+    PTYG_HIP(hipStreamSynchronize(s));
+    if (iters_done) *iters_done = m + 1;
+  }
+  PTYG_HIP(hipStreamSynchronize(s));
+  return PTYG_OK;
+}
+
 void ptyg_timing_enable(int32_t on) { g_timing.on = on != 0; }
 
 void ptyg_timing_reset(void) {

@@ -905,6 +905,182 @@ __global__ __launch_bounds__(256) void k_ls_finalize(const double* partials, int
   if (threadIdx.x == 0) out[j] = red[0];
 }
 
+// ------------------------------------------------------ multi-view batch
+// Per-view ordered sums of pattern-kernel partials: workgroup v walks every
+// block, keeps those whose pattern group lies in view v (each thread a
+// contiguous range of blocks, then a fixed tree).
+__global__ __launch_bounds__(256) void k_finalize_views(const double* partials, int nblocks, int groups, int ppw,
+                                                        int k_per_view, int width, double* out) {
+  __shared__ double red[256 * 4];
+  const int v = blockIdx.x;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int per = (nblocks + 255) / 256;
+  const int lo = threadIdx.x * per, hi = min(nblocks, lo + per);
+  for (int b = lo; b < hi; ++b) {
+    const int g = group_of_block(b, groups);
+    if (g < 0 || (g * ppw) / k_per_view != v) continue;
+    for (int j = 0; j < width; ++j) acc[j] += partials[(size_t)b * width + j];
+  }
+  for (int j = 0; j < 4; ++j) red[threadIdx.x * 4 + j] = acc[j];
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off)
+      for (int j = 0; j < 4; ++j) red[threadIdx.x * 4 + j] += red[(threadIdx.x + off) * 4 + j];
+    __syncthreads();
+  }
+  if (threadIdx.x < width) out[(size_t)v * width + threadIdx.x] = red[threadIdx.x];
+}
+
+// grid (kSegBlocks, views): block (i, v) covers view v's elements with stride
+__global__ __launch_bounds__(kVecWG) void k_dot2_views(const float2* a, const float2* b, int64_t n,
+                                                       double* partials) {
+  __shared__ double red[2 * (kVecWG / 64)];
+  const int v = blockIdx.y;
+  const float2* av = a + (size_t)v * n;
+  const float2* bv = b ? b + (size_t)v * n : nullptr;
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kVecWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVecWG) {
+    const float2 g = av[i];
+    s1 += (double)g.x * g.x + (double)g.y * g.y;
+    if (bv) {
+      const float2 e = bv[i];
+      s2 += (double)e.x * g.x + (double)e.y * g.y;
+    }
+  }
+  block_sum2<kVecWG>(s1, s2, red);
+  if (threadIdx.x == 0) {
+    double* p = partials + ((size_t)v * gridDim.x + blockIdx.x) * 2;
+    p[0] = s1;
+    p[1] = s2;
+  }
+}
+
+__global__ __launch_bounds__(kVecWG) void k_dir_views(const float2* a, float2* b, const double* beta, int64_t n,
+                                                      double* partials) {
+  __shared__ double red[2 * (kVecWG / 64)];
+  const int v = blockIdx.y;
+  const float2* av = a + (size_t)v * n;
+  float2* bv = b + (size_t)v * n;
+  const float bt = (float)beta[v];
+  double s1 = 0.0, s2 = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kVecWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVecWG) {
+    const float2 g = av[i];
+    const float2 e = bv[i];
+    const float2 en = make_float2(fmaf(bt, e.x, -g.x), fmaf(bt, e.y, -g.y));
+    bv[i] = en;
+    s1 += (double)en.x * g.x + (double)en.y * g.y;
+    s2 += (double)en.x * en.x + (double)en.y * en.y;
+  }
+  block_sum2<kVecWG>(s1, s2, red);
+  if (threadIdx.x == 0) {
+    double* p = partials + ((size_t)v * gridDim.x + blockIdx.x) * 2;
+    p[0] = s1;
+    p[1] = s2;
+  }
+}
+
+__global__ __launch_bounds__(kVecWG) void k_axpy_views(float2* a, const float2* c, const double* alpha, int64_t n) {
+  const int v = blockIdx.y;
+  const float al = (float)alpha[v];
+  float2* av = a + (size_t)v * n;
+  const float2* cv = c + (size_t)v * n;
+  for (int64_t i = (int64_t)blockIdx.x * kVecWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVecWG) {
+    const float2 x = av[i], y = cv[i];
+    av[i] = make_float2(fmaf(al, y.x, x.x), fmaf(al, y.y, x.y));
+  }
+}
+
+// one workgroup per view: ordered sum of its `rows` rows
+__global__ __launch_bounds__(256) void k_finalize_seg(const double* partials, int rows, int width, double* out) {
+  __shared__ double red[256 * 4];
+  const int v = blockIdx.x;
+  const double* base = partials + (size_t)v * rows * width;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int per = (rows + 255) / 256;
+  const int lo = threadIdx.x * per, hi = min(rows, lo + per);
+  for (int i = lo; i < hi; ++i)
+    for (int j = 0; j < width; ++j) acc[j] += base[(size_t)i * width + j];
+  for (int j = 0; j < 4; ++j) red[threadIdx.x * 4 + j] = acc[j];
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off)
+      for (int j = 0; j < 4; ++j) red[threadIdx.x * 4 + j] += red[(threadIdx.x + off) * 4 + j];
+    __syncthreads();
+  }
+  if (threadIdx.x < width) out[(size_t)v * width + threadIdx.x] = red[threadIdx.x];
+}
+
+// Batched line-search pass, one row of kSegBlocks workgroups per view.
+template <bool QUAD, int EST>
+__global__ __launch_bounds__(256) void k_ls_batch_views(LsArgs a, const int* offsets, int chunks_per_view) {
+  __shared__ double red[4][kLsRow];
+  const int v = blockIdx.y;
+  const int64_t beg = offsets[(size_t)v * chunks_per_view], end = offsets[(size_t)(v + 1) * chunks_per_view];
+  double acc[kLsRow];
+#pragma unroll
+  for (int j = 0; j < kLsRow; ++j) acc[j] = 0.0;
+  for (int64_t i = beg + (int64_t)blockIdx.x * 256 + threadIdx.x; i < end; i += (int64_t)gridDim.x * 256) {
+    const int e = a.idx[i];
+    const float2 av = a.A[e], bv = a.B[e];
+    float2 cv = make_float2(0.f, 0.f);
+    if constexpr (QUAD) cv = a.C[e];
+    const float dv = a.d[e];
+    acc[kLsBatch + 0] += (double)av.x * av.x + (double)av.y * av.y;
+    acc[kLsBatch + 1] += (double)av.x * bv.x + (double)av.y * bv.y;
+    acc[kLsBatch + 2] += (double)bv.x * bv.x + (double)bv.y * bv.y;
+#pragma unroll
+    for (int j = 0; j < kLsBatch; ++j) {
+      if (j < a.J) {
+        const float gm = a.g[j];
+        float xr = fmaf(gm, bv.x, av.x), xi = fmaf(gm, bv.y, av.y);
+        if constexpr (QUAD) {
+          const float g2 = gm * gm;
+          xr = fmaf(g2, cv.x, xr);
+          xi = fmaf(g2, cv.y, xi);
+        }
+        float phi, ft, fac;
+        pixel_terms<false, EST>(fmaf(xr, xr, xi * xi), dv, a.eps, phi, ft, fac);
+        acc[j] += (double)phi;
+      }
+    }
+  }
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+#pragma unroll
+  for (int j = 0; j < kLsRow; ++j) {
+    double x = acc[j];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) x += __shfl_xor(x, off);
+    if (l == 0) red[w][j] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < kLsRow)
+    a.partials[((size_t)v * gridDim.x + blockIdx.x) * kLsRow + threadIdx.x] =
+        red[0][threadIdx.x] + red[1][threadIdx.x] + red[2][threadIdx.x] + red[3][threadIdx.x];
+}
+
+// grid (kLsRow, views): ordered sum of a view's kSegBlocks rows, one column
+__global__ __launch_bounds__(256) void k_ls_finalize_views(const double* partials, double* out) {
+  __shared__ double red[256];
+  const int j = blockIdx.x, v = blockIdx.y;
+  const double* base = partials + (size_t)v * kSegBlocks * kLsRow;
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < kSegBlocks; i += 256) acc += base[(size_t)i * kLsRow + j];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[(size_t)v * kLsRow + j] = red[0];
+}
+
+__global__ void k_shift_views(const int2* pos, int k, int views, int rows_per_view, int2* out) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= k * views) return;
+  const int2 p = pos[i];
+  out[i] = make_int2(p.x + (i / k) * rows_per_view, p.y);
+}
+
 // In-order reduction of `count` rows of `width` (<= 4) doubles, one workgroup.
 __global__ __launch_bounds__(256) void k_finalize(const double* partials, int count, int width, double* out) {
   __shared__ double red[256 * 4];
@@ -1153,6 +1329,88 @@ hipError_t launch_probe_grad(const float2* ubuf, const float2* obj, const int2* 
     hipLaunchKernelGGL(k_probe_partial<false>, dim3((nn + 255) / 256, kProbeChunks), dim3(256), 0, s, ubuf, obj, pos,
                        K, W, N, partial);
   hipLaunchKernelGGL(k_probe_reduce, dim3((nn + 255) / 256), dim3(256), 0, s, partial, nn, out);
+  return hipGetLastError();
+}
+
+int patterns_per_block(int N) {
+  int ppw = 0;
+  dispatch_n(N, [&](auto nc) {
+    ppw = Geo<decltype(nc)::value>::PPW;
+    return hipSuccess;
+  });
+  return ppw;
+}
+
+hipError_t launch_finalize_views(const double* partials, int N, int K, int k_per_view, int views, int width,
+                                 double* out, hipStream_t s) {
+  if (!partials || !out || N > 128 || views < 1 || k_per_view < 1 || width < 1 || width > 4)
+    return hipErrorInvalidValue;
+  int nb = 0, groups = 0, ppw = 0;
+  hipError_t e = dispatch_n(N, [&](auto nc) {
+    constexpr int NN = decltype(nc)::value;
+    ppw = Geo<NN>::PPW;
+    groups = (K + ppw - 1) / ppw;
+    nb = pattern_blocks<NN>(K);
+    return hipSuccess;
+  });
+  if (e != hipSuccess) return e;
+  if (k_per_view % ppw) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_finalize_views, dim3(views), dim3(256), 0, s, partials, nb, groups, ppw, k_per_view, width,
+                     out);
+  return hipGetLastError();
+}
+
+hipError_t launch_dot2_views(const float2* a, const float2* b, int64_t n, int views, double* partials,
+                             hipStream_t s) {
+  if (!a || !partials || n < 1 || views < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dot2_views, dim3(kSegBlocks, views), dim3(kVecWG), 0, s, a, b, n, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_dir_views(const float2* a, float2* b, const double* beta, int64_t n, int views,
+                            double* partials, hipStream_t s) {
+  if (!a || !b || !beta || !partials || n < 1 || views < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dir_views, dim3(kSegBlocks, views), dim3(kVecWG), 0, s, a, b, beta, n, partials);
+  return hipGetLastError();
+}
+
+hipError_t launch_axpy_views(float2* a, const float2* c, const double* alpha, int64_t n, int views,
+                             hipStream_t s) {
+  if (!a || !c || !alpha || n < 1 || views < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_axpy_views, dim3(kSegBlocks, views), dim3(kVecWG), 0, s, a, c, alpha, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_finalize_seg(const double* partials, int rows, int width, int views, double* out,
+                               hipStream_t s) {
+  if (!partials || !out || rows < 1 || width < 1 || width > 4 || views < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_finalize_seg, dim3(views), dim3(256), 0, s, partials, rows, width, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_ls_batch_views(const LsArgs& a, const int* offsets, int chunks_per_view, int views,
+                                 hipStream_t s) {
+  if (!a.A || !a.B || !a.d || !a.idx || !a.partials || !offsets || a.J < 1 || a.J > kLsBatch || views < 1)
+    return hipErrorInvalidValue;
+  return dispatch_est(a.est, [&](auto ec) {
+    constexpr int E = decltype(ec)::value;
+    const dim3 g(kSegBlocks, views), b(256);
+    if (a.C) hipLaunchKernelGGL((k_ls_batch_views<true, E>), g, b, 0, s, a, offsets, chunks_per_view);
+    else hipLaunchKernelGGL((k_ls_batch_views<false, E>), g, b, 0, s, a, offsets, chunks_per_view);
+    return hipGetLastError();
+  });
+}
+
+hipError_t launch_ls_finalize_views(const double* partials, int views, double* out, hipStream_t s) {
+  if (!partials || !out || views < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_ls_finalize_views, dim3(kLsRow, views), dim3(256), 0, s, partials, out);
+  return hipGetLastError();
+}
+
+hipError_t launch_shift_views(const int2* pos, int k, int views, int rows_per_view, int2* out, hipStream_t s) {
+  if (!pos || !out || k < 1 || views < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_shift_views, dim3((k * views + 255) / 256), dim3(256), 0, s, pos, k, views, rows_per_view,
+                     out);
   return hipGetLastError();
 }
 

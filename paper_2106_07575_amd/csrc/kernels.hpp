@@ -133,6 +133,36 @@ hipError_t launch_ls_batch(const LsArgs& a, int* blocks_out, hipStream_t s);
 hipError_t launch_nz_compact(const float* d, int64_t n, int* counts, int* offsets, int* idx, hipStream_t s);
 // Zero-pixel sums of the direction forward: rows of 4 doubles per block.
 int fwd_t_blocks(int N, int K);
+
+// ---- multi-view batch: V views of equal shape stacked into one launch.
+// Patterns per workgroup of the n x n pattern kernels (n <= 128).
+int patterns_per_block(int N);
+// out[v][0..width) = ordered sums over the workgroups of a pattern kernel
+// launch (blocks of `width` doubles) whose patterns belong to view v
+// (k patterns per view, every workgroup inside one view).
+hipError_t launch_finalize_views(const double* partials, int N, int K, int k_per_view, int views, int width,
+                                 double* out, hipStream_t s);
+// Segmented object-sized kernels: view v owns elements [v n, (v + 1) n);
+// partial rows [v][kSegBlocks][2]; alpha (beta or gamma) per view from a
+// device array.
+constexpr int kSegBlocks = 256;
+hipError_t launch_dot2_views(const float2* a, const float2* b, int64_t n, int views, double* partials,
+                             hipStream_t s);
+hipError_t launch_dir_views(const float2* a, float2* b, const double* beta, int64_t n, int views,
+                            double* partials, hipStream_t s);
+hipError_t launch_axpy_views(float2* a, const float2* c, const double* alpha, int64_t n, int views,
+                             hipStream_t s);
+// out[v][0..width) = ordered sums of rows [v][0..rows) of `width` doubles.
+hipError_t launch_finalize_seg(const double* partials, int rows, int width, int views, double* out,
+                               hipStream_t s);
+// Batched line-search pass per view: view v's listed elements are
+// idx[offsets[v * chunks_per_view] .. offsets[(v + 1) * chunks_per_view]);
+// partial rows [v][kSegBlocks][kLsRow].
+hipError_t launch_ls_batch_views(const LsArgs& a, const int* offsets, int chunks_per_view, int views,
+                                 hipStream_t s);
+hipError_t launch_shift_views(const int2* pos, int k, int views, int rows_per_view, int2* out, hipStream_t s);
+// out[v][j] = ordered sum of rows [v][0..kSegBlocks) column j, j < kLsRow.
+hipError_t launch_ls_finalize_views(const double* partials, int views, double* out, hipStream_t s);
 // out[j] = in-order sum over `count` rows of partials[row][j], j < kLsRow.
 hipError_t launch_ls_finalize(const double* partials, int count, double* out, hipStream_t s);
 hipError_t launch_transpose_data(const float* d, float* dt, int K, int N, hipStream_t s);

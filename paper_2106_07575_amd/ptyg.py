@@ -71,6 +71,10 @@ _SIGS = {
     "ptyg_gd_solve": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P, ctypes.c_int32, ctypes.c_double,
                                        ctypes.c_int32, ctypes.c_float, ctypes.c_int32, _P, ctypes.c_size_t,
                                        ctypes.POINTER(ctypes.c_double), _P]),
+    "ptyg_views_workspace_size": (ctypes.c_size_t, [ctypes.POINTER(Dims), ctypes.c_int32, ctypes.POINTER(CgOpts)]),
+    "ptyg_cg_solve_views": (ctypes.c_int32, [ctypes.POINTER(Dims), ctypes.c_int32, _P, _P, _P, _P,
+                                             ctypes.POINTER(CgOpts), _P, ctypes.c_size_t, ctypes.POINTER(IterStats),
+                                             ctypes.POINTER(ctypes.c_int32), _P]),
     "ptyg_debug_gather": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P]),
     "ptyg_debug_scatter": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P]),
     "ptyg_debug_lane_swap": (ctypes.c_int32, [_P, _P, _P]),
@@ -280,6 +284,38 @@ def gd_solve(obj0, probe, pos, data, iters: int, gamma: float, update_probe: boo
                                 float(gamma), int(update_probe), float(eps), ESTIMATOR[estimator], _ptr(ws),
                                 ws.numel(), phis, _stream()))
     return obj, probe_c, list(phis[:iters])
+
+
+def cg_solve_views(obj0, probe, pos, data, iters: int, gamma0: float = 1.0, tau: float = 0.5, t: float = 0.0,
+                   max_halvings: int = 40, eps: float = 1e-32, line_search: str = "batched",
+                   estimator: str = "ml", ws=None):
+    """Multi-view batch: obj0 [V, H, W], pos [V, k, 2], data [V, k, n, n],
+    shared probe [n, n]; V independent ML-CG solves in one set of launches.
+    Returns (obj [V, H, W], traces: V lists of row dicts, iters_done)."""
+    obj = _dev(obj0, "obj", torch.complex64).clone()
+    probe = _dev(probe, "probe", torch.complex64)
+    pos = _dev(positions(pos.reshape(-1, 2)), "pos", torch.int32)
+    data = _dev(data, "data", torch.float32)
+    if obj.dim() != 3 or data.dim() != 4:
+        raise ValueError("obj must be [V, H, W] and data [V, k, n, n]")
+    V, H, W = obj.shape
+    k = data.shape[1]
+    d = dims_of((H, W), probe.shape[0], k)
+    o = CgOpts(int(iters), 0, float(gamma0), float(tau), float(t), int(max_halvings), float(eps), -1.0,
+               LINE_SEARCH[line_search], ESTIMATOR[estimator])
+    if ws is None:
+        sz = load().ptyg_views_workspace_size(ctypes.byref(d), V, ctypes.byref(o))
+        if sz == 0:
+            raise PtygError(-1, load().ptyg_last_error().decode())
+        ws = torch.empty(sz, dtype=torch.uint8, device=obj.device)
+    trace = (IterStats * max(1, V * iters))()
+    done = ctypes.c_int32(0)
+    _check(load().ptyg_cg_solve_views(ctypes.byref(d), V, _ptr(obj), _ptr(probe), _ptr(pos), _ptr(data),
+                                      ctypes.byref(o), _ptr(ws), ws.numel(), trace, ctypes.byref(done), _stream()))
+    rows = [[{"phi": r.phi, "f": r.f_eq2, "gamma": r.gamma, "beta": r.beta, "step_norm": r.step_norm,
+              "halvings": r.halvings, "restarted": bool(r.restarted)}
+             for r in trace[v * iters: v * iters + done.value]] for v in range(V)]
+    return obj, rows, done.value
 
 
 def check_positions(pos, obj_shape, n: int):

@@ -142,3 +142,31 @@ def c5_workload():
         phi0 += float(np.sum(O.objective_terms(np.broadcast_to(x0, data[sl].shape), data[sl].astype(np.float64))[1]))
     _C5["w"] = (cfg, inp, probe32, obj32, data, phi0)
     return _C5["w"]
+
+
+@functools.lru_cache(maxsize=4)
+def views_workload(n: int, views: int):
+    """`views` independent projections sharing one probe: objects and scans
+    from the generator (one seed set per view), intensities from the
+    oracle's forward model.  Returns (probe32, objs32 [V,H,W], pos [V,k,2],
+    data [V,k,n,n] float32)."""
+    if n == 32:
+        geo = dict(obj=120, grid=8, step=12, jitter=1, photons=1e3)
+    elif n == 128:
+        geo = dict(obj=320, grid=7, step=24, jitter=2, photons=1e5)
+    else:
+        raise KeyError(n)
+    probe32 = objs = None
+    objs, poss, datas = [], [], []
+    for v in range(views):
+        cfg = synth.small_config(f"view{v}", geo["obj"], n, geo["grid"], geo["step"], geo["jitter"],
+                                 photons=geo["photons"], cid=100 + v)
+        inp = synth.make_inputs(cfg)
+        if probe32 is None:
+            probe32 = inp.probe.astype(np.complex64)
+        obj32 = inp.obj_true.astype(np.complex64)
+        inten = np.abs(O.forward(obj32.astype(np.complex128), probe32.astype(np.complex128), inp.pos)) ** 2
+        objs.append(obj32)
+        poss.append(inp.pos)
+        datas.append(synth.make_data(cfg, inten).astype(np.float32))
+    return probe32, np.stack(objs), np.stack(poss), np.stack(datas)

@@ -1,8 +1,8 @@
 """Gradient descent (Eq. update2) on the GPU (ptyg_gd_solve) against the
 oracle's.  GD with a stable step is not chaotic: the GPU iterate must stay
 within max(1e-4, 5x) the divergence of the oracle's own GD when its
-transforms are rounded to FP32, its objectives within max(1e-5, 5x that
-oracle's largest relative objective departure)."""
+transforms are rounded to FP32, its objectives within max(1e-5 relative,
+the first-order objective change that iterate error allows)."""
 import numpy as np
 import pytest
 
@@ -43,12 +43,12 @@ def test_gd_parity(P, case, iters):
     floor = rel(po, ro)
     print(f"   object rel {err:.2e} (fp32 floor {floor:.2e}); phi {phis[-1]:.6e} oracle {rtr[-1]['phi']:.6e}")
     assert err <= max(1e-4, FLOOR_FACTOR * floor)
-    # objectives: 1e-5 relative, or 5x the largest relative departure of the
-    # FP32-rounded oracle's objectives over the run (the iterates part at the
-    # floor level; a single iteration's departure can be accidentally small)
-    pfloor = max(abs(c["phi"] - b["phi"]) / abs(b["phi"]) for b, c in zip(rtr, ptr))
+    # objectives: 1e-5 relative, or the first-order effect of the iterate
+    # error the object bound allows, |dPhi| <= 2 ||grad Phi|| ||d psi||
+    # (||grad Phi(psi_m)|| = step_norm / gamma from the oracle's trace)
+    dpsi = max(1e-4, FLOOR_FACTOR * floor) * np.linalg.norm(ro)
     for a, b in zip(phis, rtr):
-        assert abs(a - b["phi"]) <= max(1e-5, FLOOR_FACTOR * pfloor) * abs(b["phi"])
+        assert abs(a - b["phi"]) <= max(1e-5 * abs(b["phi"]), 2.0 * b["step_norm"] / gamma * dpsi)
 
 
 def test_gd_zero_data_closed_form(P):

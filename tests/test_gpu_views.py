@@ -1,0 +1,83 @@
+"""Multi-view batch (ptyg_cg_solve_views): V independent projections in one
+set of launches must give, view by view, what the oracle's CG gives for each
+view alone -- identical line-search decisions on the well-conditioned
+32^2 workload, the FP32-floor bound on the 128^2 one."""
+import numpy as np
+import pytest
+
+from oracle import ptycho as O
+
+from _cases import FLOOR_FACTOR, cg_with_floor, rel, views_workload
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def P():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2106_07575_amd import ptyg
+    ptyg.load()
+    return ptyg
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x)).cuda()
+
+
+@pytest.mark.parametrize("ls", ["batched", "sequential"])
+def test_views_exact_decisions_32(P, ls):
+    probe, objs, pos, data = views_workload(32, 3)
+    V = objs.shape[0]
+    obj0 = np.ones(objs.shape, np.complex64)
+    print(f"views 32 x{V} {ls}", flush=True)
+    out, traces, done = P.cg_solve_views(dev(obj0), dev(probe), dev(pos), dev(data), 8, line_search=ls)
+    assert done == 8
+    for v in range(V):
+        (ro, rp, rtr), _ = cg_with_floor(obj0[v], probe, pos[v], data[v], 8)
+        err = rel(out[v].cpu().numpy(), ro)
+        print(f"   view {v}: object rel {err:.2e}", [r["gamma"] for r in traces[v]])
+        assert [r["gamma"] for r in traces[v]] == [r["gamma"] for r in rtr]
+        assert [r["halvings"] for r in traces[v]] == [r["halvings"] for r in rtr]
+        for a, b in zip(traces[v], rtr):
+            assert abs(a["phi"] - b["phi"]) <= 1e-5 * abs(b["phi"])
+        assert err <= 1e-3
+
+
+def test_views_within_fp32_floor_128(P):
+    probe, objs, pos, data = views_workload(128, 2)
+    V = objs.shape[0]
+    obj0 = np.ones(objs.shape, np.complex64)
+    out, traces, done = P.cg_solve_views(dev(obj0), dev(probe), dev(pos), dev(data), 4)
+    for v in range(V):
+        (ro, rp, rtr), (po, pp, ptr) = cg_with_floor(obj0[v], probe, pos[v], data[v], 4)
+        illum = O.illumination(probe.astype(np.complex128), pos[v], objs.shape[1:])
+        mask = illum >= 1e-3 * illum.max()
+        err, floor = rel(out[v].cpu().numpy()[mask], ro[mask]), rel(po[mask], ro[mask])
+        print(f"views 128 view {v}: object rel {err:.2e} (floor {floor:.2e})")
+        assert err <= max(1e-3, FLOOR_FACTOR * floor)
+        assert traces[v][0]["gamma"] == rtr[0]["gamma"]
+
+
+def test_single_view_matches_cg_solve(P):
+    probe, objs, pos, data = views_workload(32, 3)
+    o0 = np.ones(objs.shape[1:], np.complex64)
+    a = P.cg_solve(dev(o0), dev(probe), dev(pos[1]), dev(data[1]), 6, line_search="batched")
+    out, traces, _ = P.cg_solve_views(dev(o0[None]), dev(probe), dev(pos[1:2]), dev(data[1:2]), 6)
+    assert [r["gamma"] for r in a.trace] == [r["gamma"] for r in traces[0]]
+    assert rel(out[0].cpu().numpy(), a.obj.cpu().numpy()) <= 1e-6
+
+
+def test_views_argument_errors(P):
+    probe, objs, pos, data = views_workload(32, 3)
+    o0 = np.ones(objs.shape, np.complex64)
+    # k = 63 is not a multiple of the 8 patterns per workgroup at n = 32
+    with pytest.raises(P.PtygError) as e:
+        P.cg_solve_views(dev(o0), dev(probe), dev(pos[:, :63]), dev(data[:, :63]), 2)
+    assert e.value.status == -1
+    bad = pos.copy()
+    bad[2, 5] = (objs.shape[1] - 31, 0)
+    with pytest.raises(P.PtygError) as e:
+        P.cg_solve_views(dev(o0), dev(probe), dev(bad), dev(data), 2)
+    assert e.value.status == -2
