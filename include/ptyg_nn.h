@@ -49,7 +49,7 @@ int64_t ptyg_nn_wgrad_scratch(int32_t B, int32_t H, int32_t W, int32_t cin, int3
 int32_t ptyg_nn_conv3x3_bwd_weight(const void* x, const void* dz, float* dw32, float* db, int32_t B, int32_t H,
                                    int32_t W, int32_t cin, int32_t cout, void* scratch, int64_t scratch_bytes,
                                    void* stream);
-/* dz = dy * (y > 0), n elements (bf16). */
+/* dz = dy * (y > 0), n elements (bf16, n a multiple of 8). */
 int32_t ptyg_nn_relu_bwd(const void* dy, const void* y, int64_t n, void* dz, void* stream);
 /* 2x2 average pooling of x [B][H][W][Cp(c)] (backward: x is dy [B][H/2][W/2], y is dx [B][H][W]). */
 int32_t ptyg_nn_pool2(const void* x, void* y, int32_t B, int32_t H, int32_t W, int32_t c, int32_t backward,

@@ -12,7 +12,8 @@
 // F is the unitary 2-D DFT (1/N per transform), DC at [0][0].  Transform
 // arithmetic is FP32; objective terms are accumulated per thread in FP64 and
 // reduced deterministically (fixed workgroup -> pattern mapping, fixed
-// reduction trees).  The object-gradient scatter uses FP32 atomics.
+// reduction trees).  The object gradient is an ordered overlap sum of the
+// per-pattern back-propagated waves (no atomics): results are bit-reproducible.
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"

@@ -10,13 +10,15 @@
 //   backward x   dx[p][ci] = sum_{t, co} wT[ci][t Cp_out + co] dz[p - o(t)][co]
 //   backward w   dw[co][t Cp_in + ci] = sum_p dz[p][co] x[p + o(t)][ci]
 // with o(t) = (t / 3 - 1, t % 3 - 1).  The GEMM core runs
-// v_mfma_f32_16x16x32_bf16: a 256-thread workgroup computes a 64 x 64 output
-// tile, each wave 32 x 32 as 2 x 2 MFMA blocks, K in steps of 32; every
-// operand fragment is 8 consecutive-K bf16 values per lane.
+// v_mfma_f32_16x16x32_bf16 from LDS-staged tiles: a 256-thread workgroup
+// computes a BM x BN output tile (shape chosen by the problem), each wave a
+// quarter of it, K in steps of 32; every operand fragment is 8
+// consecutive-K bf16 values per lane.
 #include <hip/hip_runtime.h>
 #include <hip/hip_bf16.h>
 
 #include <cstdint>
+#include <type_traits>
 
 #include "../../include/ptyg_nn.h"
 #include "fft.hpp"
@@ -101,19 +103,27 @@ struct WgtB {  // B[n = t Cpi + ci][k = p] = x[p + o(t)][ci]  (8 gathered pixels
   int cpi;
   __device__ bf16x8 operator()(int nn, int k) const {
     bf16x8 r = zero8();
-    if (nn >= 9 * cpi) return r;
+    if (nn >= 9 * cpi || k >= g.P) return r;
     const int t = nn / cpi, ci = nn - t * cpi;
     const int dy = t / 3 - 1, dx = t % 3 - 1;
+    // the 8 pixels k..k+7 lie in one image row when W is a multiple of 8;
+    // otherwise each is decomposed on its own
+    int n, y, x0;
+    pix(g, k, n, y, x0);
+    y += dy;
+    const bool row = (g.W & 7) == 0;
+    if (row && (y < 0 || y >= g.H)) return r;
 #pragma unroll
     for (int j = 0; j < 8; ++j) {
-      const int p = k + j;
-      if (p < g.P) {
-        int n, y, xx;
-        pix(g, p, n, y, xx);
-        y += dy;
-        xx += dx;
-        if (y >= 0 && y < g.H && xx >= 0 && xx < g.W) r[j] = x[(((size_t)n * g.H + y) * g.W + xx) * cpi + ci];
+      int nj = n, yj = y, xj = x0 + j + dx;
+      if (!row) {
+        if (k + j >= g.P) continue;
+        pix(g, k + j, nj, yj, xj);
+        yj += dy;
+        xj += dx;
+        if (yj < 0 || yj >= g.H) continue;
       }
+      if (xj >= 0 && xj < g.W) r[j] = x[(((size_t)nj * g.H + yj) * g.W + xj) * cpi + ci];
     }
     return r;
   }
@@ -153,41 +163,91 @@ struct PartStore {  // partial[ks][m][n] (FP32, split-K)
 };
 
 // ------------------------------------------------------------- GEMM core
-template <class LA, class LB, class ST>
+// LDS-tiled MFMA GEMM: a 256-thread workgroup computes a BM x BN tile, each
+// wave a (BM/2) x (BN/2) quarter as 16 x 16 MFMA blocks; K advances in steps
+// of 32.  The A and B chunks of step k+1 (8 consecutive-K bf16 each, from
+// the loaders) are fetched into registers while step k's fragments are read
+// from LDS and multiplied.
+template <int BM, int BN, class LA, class LB, class ST>
 __global__ __launch_bounds__(256) void k_gemm(LA la, LB lb, ST st, int K, int kchunk) {
-  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  const int m0 = blockIdx.x * 64 + (w >> 1) * 32, n0 = blockIdx.y * 64 + (w & 1) * 32;
+  constexpr int BK = 32, LDK = BK + 8;  // LDS row: 32 bf16 + 16 B of padding
+  constexpr int WM = BM / 2, WN = BN / 2, FM = WM / 16, FN = WN / 16;
+  constexpr int CA = (BM * 4 + 255) / 256, CB = (BN * 4 + 255) / 256;  // 16-byte chunks per thread
+  __shared__ __attribute__((aligned(16))) __bf16 sa[BM * LDK];
+  __shared__ __attribute__((aligned(16))) __bf16 sb[BN * LDK];
+  const int tid = threadIdx.x, w = tid >> 6, l = tid & 63;
+  const int bm0 = blockIdx.x * BM, bn0 = blockIdx.y * BN;
+  const int wm0 = (w >> 1) * WM, wn0 = (w & 1) * WN;
   const int r = l & 15, kq = (l >> 4) * 8;
-  f4 acc[2][2];
+  f4 acc[FM][FN];
 #pragma unroll
-  for (int i = 0; i < 2; ++i)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int j = 0; j < 2; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < FN; ++j) acc[i][j] = f4{0.f, 0.f, 0.f, 0.f};
   const int kbeg = blockIdx.z * kchunk;
   const int kend = min(K, kbeg + kchunk);
-  for (int k0 = kbeg; k0 < kend; k0 += 32) {
-    const bf16x8 a0 = la(m0 + r, k0 + kq), a1 = la(m0 + 16 + r, k0 + kq);
-    const bf16x8 b0 = lb(n0 + r, k0 + kq), b1 = lb(n0 + 16 + r, k0 + kq);
-    acc[0][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b0, acc[0][0], 0, 0, 0);
-    acc[0][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a0, b1, acc[0][1], 0, 0, 0);
-    acc[1][0] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b0, acc[1][0], 0, 0, 0);
-    acc[1][1] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a1, b1, acc[1][1], 0, 0, 0);
+  bf16x8 ra[CA], rb[CB];
+  // chunk c: tile row c / 4, K offset (c % 4) * 8
+  auto fetch = [&](int k0) {
+#pragma unroll
+    for (int i = 0; i < CA; ++i) {
+      const int c = tid + 256 * i;
+      if (c < BM * 4) ra[i] = la(bm0 + (c >> 2), k0 + (c & 3) * 8);
+    }
+#pragma unroll
+    for (int i = 0; i < CB; ++i) {
+      const int c = tid + 256 * i;
+      if (c < BN * 4) rb[i] = lb(bn0 + (c >> 2), k0 + (c & 3) * 8);
+    }
+  };
+  if (kbeg < kend) fetch(kbeg);
+  for (int k0 = kbeg; k0 < kend; k0 += BK) {
+    __syncthreads();  // the previous step's fragments have been read
+#pragma unroll
+    for (int i = 0; i < CA; ++i) {
+      const int c = tid + 256 * i;
+      if (c < BM * 4) *reinterpret_cast<bf16x8*>(&sa[(c >> 2) * LDK + (c & 3) * 8]) = ra[i];
+    }
+#pragma unroll
+    for (int i = 0; i < CB; ++i) {
+      const int c = tid + 256 * i;
+      if (c < BN * 4) *reinterpret_cast<bf16x8*>(&sb[(c >> 2) * LDK + (c & 3) * 8]) = rb[i];
+    }
+    __syncthreads();
+    if (k0 + BK < kend) fetch(k0 + BK);
+    bf16x8 fa[FM], fb[FN];
+#pragma unroll
+    for (int i = 0; i < FM; ++i) fa[i] = *reinterpret_cast<const bf16x8*>(&sa[(wm0 + 16 * i + r) * LDK + kq]);
+#pragma unroll
+    for (int j = 0; j < FN; ++j) fb[j] = *reinterpret_cast<const bf16x8*>(&sb[(wn0 + 16 * j + r) * LDK + kq]);
+#pragma unroll
+    for (int i = 0; i < FM; ++i)
+#pragma unroll
+      for (int j = 0; j < FN; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(fa[i], fb[j], acc[i][j], 0, 0, 0);
   }
-  // C fragment: lane l holds rows 4 (l >> 4) + i, column l & 15
+  // C fragment: lane l holds rows 4 (l >> 4) + e, column l & 15
 #pragma unroll
-  for (int bi = 0; bi < 2; ++bi)
+  for (int i = 0; i < FM; ++i)
 #pragma unroll
-    for (int bj = 0; bj < 2; ++bj)
+    for (int j = 0; j < FN; ++j)
 #pragma unroll
-      for (int i = 0; i < 4; ++i) st(m0 + 16 * bi + 4 * (l >> 4) + i, n0 + 16 * bj + r, acc[bi][bj][i]);
+      for (int e = 0; e < 4; ++e) st(bm0 + wm0 + 16 * i + 4 * (l >> 4) + e, bn0 + wn0 + 16 * j + r, acc[i][j][e]);
 }
 
+// Tile shape by problem shape: narrow outputs (N <= 32) take tall tiles.
 template <class LA, class LB, class ST>
 hipError_t gemm(const LA& la, const LB& lb, const ST& st, int M, int N, int K, int splits, hipStream_t s) {
   const int kpad = (K + 31) / 32 * 32;
   const int kchunk = ((kpad + splits - 1) / splits + 31) / 32 * 32;
-  const dim3 grid((M + 63) / 64, (N + 63) / 64, splits);
-  hipLaunchKernelGGL((k_gemm<LA, LB, ST>), grid, dim3(256), 0, s, la, lb, st, kpad, kchunk);
+  auto launch = [&](auto bm, auto bn) {
+    constexpr int BM = decltype(bm)::value, BN = decltype(bn)::value;
+    const dim3 grid((M + BM - 1) / BM, (N + BN - 1) / BN, splits);
+    hipLaunchKernelGGL((k_gemm<BM, BN, LA, LB, ST>), grid, dim3(256), 0, s, la, lb, st, kpad, kchunk);
+  };
+  if (M <= 64) launch(std::integral_constant<int, 64>{}, std::integral_constant<int, 128>{});
+  else if (N <= 32) launch(std::integral_constant<int, 256>{}, std::integral_constant<int, 32>{});
+  else if (N <= 64) launch(std::integral_constant<int, 128>{}, std::integral_constant<int, 64>{});
+  else launch(std::integral_constant<int, 128>{}, std::integral_constant<int, 128>{});
   return hipGetLastError();
 }
 
@@ -200,20 +260,33 @@ __global__ void k_reduce_parts(const float* part, int splits, int64_t n, float* 
   out[i] = s;
 }
 
-// db[co] = sum_p dz[p][co] (fixed order: per-thread contiguous pixel ranges,
-// then a fixed tree)
-__global__ __launch_bounds__(256) void k_bias_grad(const __bf16* dz, int P, int cpo, int cout, float* db) {
+// db[co] = sum_p dzT[co][p] from the channel-major copy (contiguous rows):
+// grid (kBiasChunks, cout), workgroup (c, co) sums its fixed pixel range
+// (strided per thread, then a fixed tree) into part[co][c]; k_bias_reduce
+// adds the chunks in order.
+constexpr int kBiasChunks = 64;
+__global__ __launch_bounds__(256) void k_bias_grad(const __bf16* dzt, int P, float* part) {
   __shared__ float red[256];
-  const int co = blockIdx.x;
+  const int c = blockIdx.x, co = blockIdx.y;
+  const int per = (P + kBiasChunks - 1) / kBiasChunks;
+  const int lo = c * per, hi = min(P, lo + per);
+  const __bf16* row = dzt + (size_t)co * P;
   float s = 0.0f;
-  for (int p = threadIdx.x; p < P; p += 256) s += (float)dz[(size_t)p * cpo + co];
+  for (int p = lo + threadIdx.x; p < hi; p += 256) s += (float)row[p];
   red[threadIdx.x] = s;
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
     if (threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
     __syncthreads();
   }
-  if (threadIdx.x == 0 && co < cout) db[co] = red[0];
+  if (threadIdx.x == 0) part[co * kBiasChunks + c] = red[0];
+}
+__global__ void k_bias_reduce(const float* part, int cout, float* db) {
+  const int co = blockIdx.x * blockDim.x + threadIdx.x;
+  if (co >= cout) return;
+  float s = 0.0f;
+  for (int c = 0; c < kBiasChunks; ++c) s += part[co * kBiasChunks + c];
+  db[co] = s;
 }
 
 // dzT[c][p] = dz[p][c]
@@ -263,64 +336,69 @@ __global__ void k_unpack_wgrad(const float* dwp, int cout, int cin, int cpi, flo
   dw32[i] = dwp[(size_t)co * 9 * cpi + t * cpi + ci];
 }
 
-__global__ void k_relu_bwd(const __bf16* dy, const __bf16* y, int64_t n, __bf16* dz) {
+// Elementwise layers on 8-channel (16-byte) groups: element i of the
+// group index space is (pixel, channel group); all counts are multiples of 8.
+__global__ void k_relu_bwd(const bf16x8* dy, const bf16x8* y, int64_t n8, bf16x8* dz) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n) return;
-  dz[i] = ((float)y[i] > 0.0f) ? dy[i] : (__bf16)0.0f;
+  if (i >= n8) return;
+  const bf16x8 a = dy[i], b = y[i];
+  bf16x8 r;
+#pragma unroll
+  for (int c = 0; c < 8; ++c) r[c] = ((float)b[c] > 0.0f) ? a[c] : (__bf16)0.0f;
+  dz[i] = r;
 }
 
 // 2x2 average pooling (NHWC): out [B][H/2][W/2][cp]
-__global__ void k_pool_fwd(const __bf16* x, int B, int H, int W, int cp, __bf16* y) {
+__global__ void k_pool_fwd(const bf16x8* x, int B, int H, int W, int g8, bf16x8* y) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int Ho = H / 2, Wo = W / 2;
-  if (i >= (int64_t)B * Ho * Wo * cp) return;
-  const int c = (int)(i % cp);
-  int64_t q = i / cp;
-  const int xo = (int)(q % Wo);
-  q /= Wo;
-  const int yo = (int)(q % Ho);
-  const int n = (int)(q / Ho);
-  const size_t b = (((size_t)n * H + 2 * yo) * W + 2 * xo) * cp + c;
-  const float s = (float)x[b] + (float)x[b + cp] + (float)x[b + (size_t)W * cp] + (float)x[b + (size_t)W * cp + cp];
-  y[i] = (__bf16)(0.25f * s);
+  if (i >= (int64_t)B * Ho * Wo * g8) return;
+  const int c = (int)(i % g8);
+  const int64_t q = i / g8;
+  const int xo = (int)(q % Wo), yo = (int)((q / Wo) % Ho), n = (int)(q / ((int64_t)Wo * Ho));
+  const size_t b = (((size_t)n * H + 2 * yo) * W + 2 * xo) * g8 + c;
+  const size_t rs = (size_t)W * g8;
+  const bf16x8 p0 = x[b], p1 = x[b + g8], p2 = x[b + rs], p3 = x[b + rs + g8];
+  bf16x8 r;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) r[e] = (__bf16)(0.25f * ((float)p0[e] + (float)p1[e] + (float)p2[e] + (float)p3[e]));
+  y[i] = r;
 }
-__global__ void k_pool_bwd(const __bf16* dy, int B, int H, int W, int cp, __bf16* dx) {
+__global__ void k_pool_bwd(const bf16x8* dy, int B, int H, int W, int g8, bf16x8* dx) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)B * H * W * cp) return;
-  const int c = (int)(i % cp);
-  int64_t q = i / cp;
-  const int x = (int)(q % W);
-  q /= W;
-  const int y = (int)(q % H);
-  const int n = (int)(q / H);
-  dx[i] = (__bf16)(0.25f * (float)dy[(((size_t)n * (H / 2) + y / 2) * (W / 2) + x / 2) * cp + c]);
+  if (i >= (int64_t)B * H * W * g8) return;
+  const int c = (int)(i % g8);
+  const int64_t q = i / g8;
+  const int x = (int)(q % W), y = (int)((q / W) % H), n = (int)(q / ((int64_t)W * H));
+  const bf16x8 a = dy[(((size_t)n * (H / 2) + y / 2) * (W / 2) + x / 2) * g8 + c];
+  bf16x8 r;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) r[e] = (__bf16)(0.25f * (float)a[e]);
+  dx[i] = r;
 }
 // nearest 2x upsampling: out [B][2H][2W][cp]
-__global__ void k_up_fwd(const __bf16* x, int B, int H, int W, int cp, __bf16* y) {
+__global__ void k_up_fwd(const bf16x8* x, int B, int H, int W, int g8, bf16x8* y) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int Ho = 2 * H, Wo = 2 * W;
-  if (i >= (int64_t)B * Ho * Wo * cp) return;
-  const int c = (int)(i % cp);
-  int64_t q = i / cp;
-  const int xo = (int)(q % Wo);
-  q /= Wo;
-  const int yo = (int)(q % Ho);
-  const int n = (int)(q / Ho);
-  y[i] = x[(((size_t)n * H + yo / 2) * W + xo / 2) * cp + c];
+  if (i >= (int64_t)B * Ho * Wo * g8) return;
+  const int c = (int)(i % g8);
+  const int64_t q = i / g8;
+  const int xo = (int)(q % Wo), yo = (int)((q / Wo) % Ho), n = (int)(q / ((int64_t)Wo * Ho));
+  y[i] = x[(((size_t)n * H + yo / 2) * W + xo / 2) * g8 + c];
 }
-__global__ void k_up_bwd(const __bf16* dy, int B, int H, int W, int cp, __bf16* dx) {
+__global__ void k_up_bwd(const bf16x8* dy, int B, int H, int W, int g8, bf16x8* dx) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= (int64_t)B * H * W * cp) return;
-  const int c = (int)(i % cp);
-  int64_t q = i / cp;
-  const int x = (int)(q % W);
-  q /= W;
-  const int y = (int)(q % H);
-  const int n = (int)(q / H);
+  if (i >= (int64_t)B * H * W * g8) return;
+  const int c = (int)(i % g8);
+  const int64_t q = i / g8;
+  const int x = (int)(q % W), y = (int)((q / W) % H), n = (int)(q / ((int64_t)W * H));
   const size_t Wo = 2 * (size_t)W;
-  const size_t b = (((size_t)n * 2 * H + 2 * y) * Wo + 2 * x) * cp + c;
-  const float s = (float)dy[b] + (float)dy[b + cp] + (float)dy[b + Wo * cp] + (float)dy[b + Wo * cp + cp];
-  dx[i] = (__bf16)s;
+  const size_t b = (((size_t)n * 2 * H + 2 * y) * Wo + 2 * x) * g8 + c;
+  const bf16x8 p0 = dy[b], p1 = dy[b + g8], p2 = dy[b + Wo * g8], p3 = dy[b + Wo * g8 + g8];
+  bf16x8 r;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) r[e] = (__bf16)((float)p0[e] + (float)p1[e] + (float)p2[e] + (float)p3[e]);
+  dx[i] = r;
 }
 
 // Network input: x[b][u][v][0] = scale * log(1 + d[b][(u + n/2) % n][(v + n/2) % n])
@@ -630,9 +708,9 @@ int32_t ptyg_nn_conv3x3_bwd_data(const void* dz, const void* wt, void* dx, int32
 int64_t ptyg_nn_wgrad_scratch(int32_t B, int32_t H, int32_t W, int32_t cin, int32_t cout) {
   const int64_t P = (int64_t)B * H * W;
   const int splits = (int)((P + 2047) / 2048);
-  // dzT (bf16) + split-K partials + reduced packed gradient (fp32), in bytes
+  // dzT (bf16) + split-K partials + reduced packed gradient + bias chunk sums (fp32), in bytes
   return (int64_t)cpad(cout) * P * 2 + (int64_t)splits * cout * 9 * cpad(cin) * 4 +
-         (int64_t)cout * 9 * cpad(cin) * 4 + 1024;
+         (int64_t)cout * 9 * cpad(cin) * 4 + (int64_t)kBiasChunks * cout * 4 + 1024;
 }
 
 int32_t ptyg_nn_conv3x3_bwd_weight(const void* x, const void* dz, float* dw32, float* db, int32_t B, int32_t H,
@@ -663,15 +741,18 @@ int32_t ptyg_nn_conv3x3_bwd_weight(const void* x, const void* dz, float* dw32, f
   hipLaunchKernelGGL(k_reduce_parts, dim3(nblk(n)), dim3(256), 0, s, part, splits, n, dwp);
   hipLaunchKernelGGL(k_unpack_wgrad, dim3(nblk((int64_t)cout * 9 * cin)), dim3(256), 0, s, dwp, cout, cin, cpi,
                      dw32);
-  hipLaunchKernelGGL(k_bias_grad, dim3(cout), dim3(256), 0, s, static_cast<const __bf16*>(dz), g.P, cpo, cout, db);
+  float* bpart = dwp + (size_t)cout * 9 * cpi;  // kBiasChunks * cout floats after the packed gradient
+  hipLaunchKernelGGL(k_bias_grad, dim3(kBiasChunks, cout), dim3(256), 0, s, dzt, g.P, bpart);
+  hipLaunchKernelGGL(k_bias_reduce, dim3((cout + 255) / 256), dim3(256), 0, s, bpart, cout, db);
   NN_HIP(hipGetLastError());
   return 0;
 }
 
 int32_t ptyg_nn_relu_bwd(const void* dy, const void* y, int64_t n, void* dz, void* stream) {
   if (!dy || !y || !dz) return nn_fail("NULL argument");
-  hipLaunchKernelGGL(k_relu_bwd, dim3(nblk(n)), dim3(256), 0, SS(stream), static_cast<const __bf16*>(dy),
-                     static_cast<const __bf16*>(y), n, static_cast<__bf16*>(dz));
+  if (n % 8) return nn_fail("element count must be a multiple of 8");
+  hipLaunchKernelGGL(k_relu_bwd, dim3(nblk(n / 8)), dim3(256), 0, SS(stream), static_cast<const bf16x8*>(dy),
+                     static_cast<const bf16x8*>(y), n / 8, static_cast<bf16x8*>(dz));
   NN_HIP(hipGetLastError());
   return 0;
 }
@@ -679,13 +760,13 @@ int32_t ptyg_nn_relu_bwd(const void* dy, const void* y, int64_t n, void* dz, voi
 int32_t ptyg_nn_pool2(const void* x, void* y, int32_t B, int32_t H, int32_t W, int32_t c, int32_t backward,
                       void* stream) {
   if (!x || !y || (H & 1) || (W & 1)) return nn_fail("bad arguments");
-  const int cp = cpad(c);
+  const int g8 = cpad(c) / 8;
   if (!backward)
-    hipLaunchKernelGGL(k_pool_fwd, dim3(nblk((int64_t)B * (H / 2) * (W / 2) * cp)), dim3(256), 0, SS(stream),
-                       static_cast<const __bf16*>(x), B, H, W, cp, static_cast<__bf16*>(y));
+    hipLaunchKernelGGL(k_pool_fwd, dim3(nblk((int64_t)B * (H / 2) * (W / 2) * g8)), dim3(256), 0, SS(stream),
+                       static_cast<const bf16x8*>(x), B, H, W, g8, static_cast<bf16x8*>(y));
   else
-    hipLaunchKernelGGL(k_pool_bwd, dim3(nblk((int64_t)B * H * W * cp)), dim3(256), 0, SS(stream),
-                       static_cast<const __bf16*>(x), B, H, W, cp, static_cast<__bf16*>(y));
+    hipLaunchKernelGGL(k_pool_bwd, dim3(nblk((int64_t)B * H * W * g8)), dim3(256), 0, SS(stream),
+                       static_cast<const bf16x8*>(x), B, H, W, g8, static_cast<bf16x8*>(y));
   NN_HIP(hipGetLastError());
   return 0;
 }
@@ -693,13 +774,13 @@ int32_t ptyg_nn_pool2(const void* x, void* y, int32_t B, int32_t H, int32_t W, i
 int32_t ptyg_nn_up2(const void* x, void* y, int32_t B, int32_t H, int32_t W, int32_t c, int32_t backward,
                     void* stream) {
   if (!x || !y) return nn_fail("bad arguments");
-  const int cp = cpad(c);
+  const int g8 = cpad(c) / 8;
   if (!backward)
-    hipLaunchKernelGGL(k_up_fwd, dim3(nblk((int64_t)B * 4 * H * W * cp)), dim3(256), 0, SS(stream),
-                       static_cast<const __bf16*>(x), B, H, W, cp, static_cast<__bf16*>(y));
+    hipLaunchKernelGGL(k_up_fwd, dim3(nblk((int64_t)B * 4 * H * W * g8)), dim3(256), 0, SS(stream),
+                       static_cast<const bf16x8*>(x), B, H, W, g8, static_cast<bf16x8*>(y));
   else
-    hipLaunchKernelGGL(k_up_bwd, dim3(nblk((int64_t)B * H * W * cp)), dim3(256), 0, SS(stream),
-                       static_cast<const __bf16*>(x), B, H, W, cp, static_cast<__bf16*>(y));
+    hipLaunchKernelGGL(k_up_bwd, dim3(nblk((int64_t)B * H * W * g8)), dim3(256), 0, SS(stream),
+                       static_cast<const bf16x8*>(x), B, H, W, g8, static_cast<bf16x8*>(y));
   NN_HIP(hipGetLastError());
   return 0;
 }

@@ -320,7 +320,7 @@ def finetune(net: Net, objects, probe, steps: int = 20, lr: float = 2e-4, batch_
 
 
 def time_to_objective(net: Net, probe, pos, data, obj_shape, obj_true=None, plain_iters: int = 100,
-                      max_iters: int = 100, sync_iters: int = 100, line_search: str = "batched"):
+                      max_iters: int = 200, sync_iters: int = 100, line_search: str = "batched"):
     """Plain CG (psi_0 = 1, `plain_iters` iterations) against the warm start
     (inference + stitch + CG until its objective reaches plain CG's final
     one).  Wall times are synchronised host timings."""
@@ -354,12 +354,15 @@ def time_to_objective(net: Net, probe, pos, data, obj_shape, obj_true=None, plai
     t_cg = time.perf_counter() - t3
     phi_warm_final = float(ptyg.minfunc(warm.obj, probe, pos, data, ws=ws)[0])
     reached = warm.iters_done < max_iters or phi_warm_final <= phi_plain_final
+    t_plain_per_iter = t_plain / max(plain.iters_done, 1)
     marks = [0, 5, 10, 25, 50, 75, 99]
     res = {"phi_plain_final": phi_plain_final, "phi_plain_last_trace": phi_plain, "t_plain_s": t_plain,
            "plain_iters": plain.iters_done, "phi0_ones": plain.trace[0]["phi"] if plain.trace else None,
            "phi0_warm": phi0_warm, "t_infer_s": t_infer, "t_stitch_s": t_stitch, "t_cg_warm_s": t_cg,
            "warm_iters": warm.iters_done, "warm_reached_target": bool(reached),
            "t_warm_total_s": t_infer + t_stitch + t_cg, "phi_warm_final": phi_warm_final,
+           "warm_faster": bool(reached) and t_infer + t_stitch + t_cg < t_plain,
+           "break_even_iters": (t_plain - t_infer - t_stitch) / t_plain_per_iter,
            "phi_trace_plain": {m: plain.trace[m]["phi"] for m in marks if m < len(plain.trace)},
            "phi_trace_warm": {m: warm.trace[m]["phi"] for m in marks if m < len(warm.trace)}}
     if obj_true is not None:
