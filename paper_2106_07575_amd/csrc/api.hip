@@ -472,11 +472,18 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
   }
 
   // scalar slots
-  enum { PHI = 0, FEQ = 1, N1O = 2, N2O = 3, N1P = 4, N2P = 5, N3O = 6, EEO = 7, N3P = 8, EEP = 9, PHIT = 10 };
+  enum {
+    PHI = 0, FEQ = 1, N1O = 2, N2O = 3, N1P = 4, N2P = 5, N3O = 6, EEO = 7, N3P = 8, EEP = 9,
+    PHIT = 10,  // a trial's (Phi, F): two slots
+    BETA = 12, RST = 13, NSC = 14
+  };
   double h[16];
-  double n3_prev = 0.0;  // Re<eta_{m-1}, grad_{m-1}>
   bool restart = true;
   const int nvb_o = vec_blocks(on), nvb_p = vec_blocks(pn);
+  // the direction update reads its coefficient from the device: start from a
+  // finite (zero) direction
+  PTYG_HIP(launch_zero(eta_o, on, s));
+  if (joint) PTYG_HIP(launch_zero(eta_p, pn, s));
 
   for (int m = 0; m < opts->iters; ++m) {
     // GRAD stage
@@ -499,35 +506,18 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
       PTYG_HIP(launch_dot2(vp, s));
       PTYG_HIP(launch_finalize(partials, nvb_p, 2, sc + N1P, s));
     }
-    PTYG_HIP(hipMemcpyAsync(h, sc, 6 * sizeof(double), hipMemcpyDeviceToHost, s));
-    PTYG_HIP(hipStreamSynchronize(s));
-    const double phi_m = h[PHI], f_m = h[FEQ];
-    if (!std::isfinite(phi_m))
-      return fail(PTYG_E_NONFINITE, "objective is %g at iteration %d", phi_m, m);
-    if (opts->target_phi >= 0.0 && phi_m <= opts->target_phi) break;
 
-    // DIR stage (Eq. DaiYuan): beta = ||g_m||^2 / Re<eta_{m-1}, g_m - g_{m-1}>
-    double beta = 0.0;
-    bool restarted = restart;
-    if (!restart) {
-      const double n1 = h[N1O] + (joint ? h[N1P] : 0.0);
-      const double n2 = h[N2O] + (joint ? h[N2P] : 0.0);
-      const double den = n2 - n3_prev;
-      if (std::isfinite(den) && den > 0.0 && std::isfinite(n1)) beta = n1 / den;
-      else restarted = true;
-    }
+    // DIR stage (Eq. DaiYuan) on the device: beta = ||g_m||^2 /
+    // Re<eta_{m-1}, g_m - g_{m-1}> (sc[N3O] still holds Re<eta_{m-1}, g_{m-1}>),
+    // restart on a failed search or a bad denominator; no host round trip
+    PTYG_HIP(launch_dy_beta(sc, N1O, N2O, N3O, joint ? 2 : 0, BETA, RST, restart ? 1 : 0, s));
     v = VecArgs{};
     v.n = on;
     v.a = grad_o;
     v.b = eta_o;
-    v.alpha = beta;
+    v.alpha_dev = sc + BETA;
+    v.restart_dev = sc + RST;
     v.partials = partials;
-    if (restarted) {
-      // eta = -grad: run the same kernel on a zeroed direction
-      PTYG_HIP(launch_zero(eta_o, on, s));
-      if (joint) PTYG_HIP(launch_zero(eta_p, pn, s));
-      v.alpha = 0.0;
-    }
     PTYG_HIP(launch_dir(v, s));
     PTYG_HIP(launch_finalize(partials, nvb_o, 2, sc + N3O, s));
     if (joint) {
@@ -535,11 +525,24 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
       vp.n = pn;
       vp.a = grad_p;
       vp.b = eta_p;
-      vp.alpha = restarted ? 0.0 : beta;
+      vp.alpha_dev = sc + BETA;
+      vp.restart_dev = sc + RST;
       vp.partials = partials;
       PTYG_HIP(launch_dir(vp, s));
       PTYG_HIP(launch_finalize(partials, nvb_p, 2, sc + N3P, s));
     }
+    // scalars of this iteration, read back with the first line-search result
+    double phi_m = 0.0, f_m = 0.0, beta = 0.0;
+    bool restarted = true, stop = false;
+    auto take_scalars = [&]() -> ptyg_status {
+      phi_m = h[PHI];
+      f_m = h[FEQ];
+      beta = h[BETA];
+      restarted = h[RST] != 0.0;
+      if (!std::isfinite(phi_m)) return fail(PTYG_E_NONFINITE, "objective is %g at iteration %d", phi_m, m);
+      if (opts->target_phi >= 0.0 && phi_m <= opts->target_phi) stop = true;
+      return PTYG_OK;
+    };
 
     // LS stage (Eq. linesearch, Algorithm 1 order: shrink, then evaluate)
     double gamma = opts->gamma0;
@@ -618,11 +621,13 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
         double phis[kLsRow];
         PTYG_HIP(hipMemcpyAsync(phis, lsphi, kLsRow * sizeof(double), hipMemcpyDeviceToHost, s));
         if (first) {
-          PTYG_HIP(hipMemcpyAsync(h + N3O, sc + N3O, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
+          PTYG_HIP(hipMemcpyAsync(h, sc, NSC * sizeof(double), hipMemcpyDeviceToHost, s));
           PTYG_HIP(hipMemcpyAsync(zs, zsums, 12 * sizeof(double), hipMemcpyDeviceToHost, s));
         }
         PTYG_HIP(hipStreamSynchronize(s));
         if (first) {
+          if (ptyg_status st = take_scalars()) return st;
+          if (stop) break;
           n3 = h[N3O] + (joint ? h[N3P] : 0.0);
           eta2 = h[EEO] + (joint ? h[EEP] : 0.0);
           // whole-array sums minus the listed elements' shares (the same FP32
@@ -660,8 +665,12 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
       if (ptyg_status st = run_minfunc(dims, obj, eta_o, probe, eta_p, gamma, pos, dt, DataLayout::Transposed,
                                        eps, est, sc + PHIT, ws, L, s))
         return st;
-      PTYG_HIP(hipMemcpyAsync(h + N3O, sc + N3O, 5 * sizeof(double), hipMemcpyDeviceToHost, s));
+      PTYG_HIP(hipMemcpyAsync(h, sc, NSC * sizeof(double), hipMemcpyDeviceToHost, s));
       PTYG_HIP(hipStreamSynchronize(s));
+      if (j == 1) {
+        if (ptyg_status st = take_scalars()) return st;
+        if (stop) break;
+      }
       n3 = h[N3O] + (joint ? h[N3P] : 0.0);
       eta2 = h[EEO] + (joint ? h[EEP] : 0.0);
       const double phi_t = h[PHIT];
@@ -670,6 +679,7 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
         break;
       }
     }
+    if (stop) break;  // target objective reached at psi_m: no update
     if (!accepted) gamma = 0.0;
 
     // Update stage (Eq. update)
@@ -694,12 +704,11 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
       t.phi = phi_m;
       t.f_eq2 = f_m;
       t.gamma = gamma;
-      t.beta = restarted ? 0.0 : beta;
+      t.beta = beta;
       t.step_norm = gamma * std::sqrt(eta2 > 0.0 ? eta2 : 0.0);
       t.halvings = trials;
       t.restarted = restarted ? 1 : 0;
     }
-    n3_prev = n3;
     restart = !accepted;
     if (iters_done) *iters_done = m + 1;
   }

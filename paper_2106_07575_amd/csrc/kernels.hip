@@ -760,11 +760,12 @@ __global__ __launch_bounds__(kVecWG) void k_dot2(VecArgs v) {
 __global__ __launch_bounds__(kVecWG) void k_dir(VecArgs v) {
   __shared__ double red[2 * (kVecWG / 64)];
   double s1 = 0.0, s2 = 0.0;
-  const float beta = (float)v.alpha;
+  const float beta = (float)(v.alpha_dev ? *v.alpha_dev : v.alpha);
+  const bool rst = v.restart_dev && *v.restart_dev != 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kVecWG + threadIdx.x; i < v.n; i += (int64_t)gridDim.x * kVecWG) {
     const float2 g = v.a[i];
     const float2 e = v.b[i];
-    const float2 en = make_float2(fmaf(beta, e.x, -g.x), fmaf(beta, e.y, -g.y));
+    const float2 en = rst ? make_float2(-g.x, -g.y) : make_float2(fmaf(beta, e.x, -g.x), fmaf(beta, e.y, -g.y));
     v.b[i] = en;
     s1 += (double)en.x * g.x + (double)en.y * g.y;
     s2 += (double)en.x * en.x + (double)en.y * en.y;
@@ -774,6 +775,20 @@ __global__ __launch_bounds__(kVecWG) void k_dir(VecArgs v) {
     v.partials[2 * blockIdx.x] = s1;
     v.partials[2 * blockIdx.x + 1] = s2;
   }
+}
+
+__global__ void k_dy_beta(double* sc, int n1, int n2, int n3, int joint_off, int beta, int rst, int restart) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  double num = sc[n1], a = sc[n2], b = sc[n3];
+  if (joint_off > 0) {
+    num += sc[n1 + joint_off];
+    a += sc[n2 + joint_off];
+    b += sc[n3 + joint_off];
+  }
+  const double den = a - b;
+  const bool ok = !restart && isfinite(den) && den > 0.0 && isfinite(num);
+  sc[beta] = ok ? num / den : 0.0;
+  sc[rst] = ok ? 0.0 : 1.0;
 }
 
 __global__ __launch_bounds__(kVecWG) void k_axpy(VecArgs v) {
@@ -1448,6 +1463,13 @@ hipError_t launch_sum_copies(const float2* src, int copies, int64_t n, float2* o
   hipLaunchKernelGGL(k_sum_copies, dim3(vec_blocks(n)), dim3(kVecWG), 0, s, src, copies, n, out);
   return hipGetLastError();
 }
+hipError_t launch_dy_beta(double* sc, int n1, int n2, int n3, int joint_off, int beta, int rst, int restart,
+                          hipStream_t s) {
+  if (!sc) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_dy_beta, dim3(1), dim3(64), 0, s, sc, n1, n2, n3, joint_off, beta, rst, restart);
+  return hipGetLastError();
+}
+
 hipError_t launch_finalize(const double* partials, int count, int width, double* out, hipStream_t s) {
   hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partials, count, width, out);
   return hipGetLastError();

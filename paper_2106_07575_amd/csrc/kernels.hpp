@@ -68,6 +68,8 @@ struct VecArgs {
   const float2* c;
   double alpha;
   double* partials;
+  const double* alpha_dev;    // k_dir: coefficient read on the device (overrides alpha) ...
+  const double* restart_dev;  // ... and a restart flag (nonzero: b <- -a, the old b ignored)
 };
 
 enum class DataLayout { Rows = 0, Transposed = 1 };
@@ -182,6 +184,13 @@ hipError_t launch_dot2(const VecArgs& v, hipStream_t s);
 hipError_t launch_dir(const VecArgs& v, hipStream_t s);
 // a <- a + alpha c
 hipError_t launch_axpy(const VecArgs& v, hipStream_t s);
+// Dai-Yuan coefficient on the device (Eq. DaiYuan): from sc[n1], sc[n2]
+// (||g_m||^2, Re<eta_{m-1}, g_m>) and sc[n3] (Re<eta_{m-1}, g_{m-1}>), each
+// plus its joint-mode probe term at +joint_off when joint_off > 0, writes
+// sc[beta] and sc[rst] (1 if restarted: `restart`, or a denominator that is
+// not positive and finite, or a non-finite numerator; beta is then 0).
+hipError_t launch_dy_beta(double* sc, int n1, int n2, int n3, int joint_off, int beta, int rst, int restart,
+                          hipStream_t s);
 // out[j] (+)= sum over copies of probe-gradient copies (out[j] = sum_c src[c][j])
 hipError_t launch_sum_copies(const float2* src, int copies, int64_t n, float2* out, hipStream_t s);
 // out[0..width) = in-order sums of `count` rows of `width` doubles
