@@ -396,3 +396,26 @@ def test_net_train_steps(NN):
         net.adam_step(1e-4)
     print("losses", [round(v, 2) for v in losses[::5]])
     assert min(losses[-5:]) < 0.5 * losses[0], losses
+
+
+def test_finetune_through_operator_reduces_objective(NN):
+    """A few fine-tuning steps (deviance of the stitched start, its gradient
+    pulled back through the stitch) lower the objective of the stitched
+    start on the training object."""
+    from paper_2106_07575_amd import ptyg, synth
+    from paper_2106_07575_amd import warmstart as WS
+    dev = torch.device("cuda")
+    cfg = synth.CONFIGS["c2"]
+    probe = torch.from_numpy(synth.make_probe(cfg.n, cfg.probe_kind, cfg.photons, cfg.seed("probe"))
+                             .astype(np.complex64)).to(dev)
+    rng = np.random.default_rng(4)
+    obj = torch.from_numpy(WS._object(77, 256)).to(dev)
+    pos = torch.from_numpy(WS.raster(256, 5, 24, 2, rng)).to(dev)
+    far = ptyg.forward(obj, probe, pos)
+    g = torch.Generator(device=dev).manual_seed(5)
+    data = torch.poisson((far.real ** 2 + far.imag ** 2).float(), generator=g).contiguous()
+    net = WS.Net(dev, seed=6)
+    hist = WS.finetune(net, [{"pos": pos, "data": data, "shape": (256, 256)}], probe, steps=12, lr=1e-3)
+    print("finetune Phi", [round(h) for h in hist])
+    assert all(np.isfinite(hist))
+    assert min(hist[-3:]) < hist[0]
