@@ -302,11 +302,13 @@ ptyg_status ptyg_adjoint(const ptyg_dims* dims, const ptyg_c64* far, const ptyg_
   a.pos = reinterpret_cast<const int2*>(pos);
   a.obj = reinterpret_cast<const float2*>(obj);
   a.ubuf = at<float2>(ws, L.ubuf);
+  // conj(p) folded into the stored waves unless the probe adjoint needs them plain
+  a.premul = !probe_out && dims->n <= 128;
   PTYG_HIP(launch_tile_lists(a.pos, dims->k, dims->obj_h, dims->obj_w, dims->n, at<int>(ws, L.toff),
                              at<int>(ws, L.tlist), s));
   PTYG_HIP(launch_adjoint(a, s));
-  PTYG_HIP(launch_tile_sum(a.ubuf, a.probe, a.pos, at<int>(ws, L.toff), at<int>(ws, L.tlist), dims->k, dims->obj_h,
-                           dims->obj_w, dims->n, reinterpret_cast<float2*>(obj_out), s));
+  PTYG_HIP(launch_tile_sum(a.ubuf, a.premul ? nullptr : a.probe, a.pos, at<int>(ws, L.toff), at<int>(ws, L.tlist),
+                           dims->k, dims->obj_h, dims->obj_w, dims->n, reinterpret_cast<float2*>(obj_out), s));
   if (probe_out)
     PTYG_HIP(launch_probe_grad(a.ubuf, a.obj, a.pos, dims->k, dims->obj_w, dims->n, at<float2>(ws, L.pparts),
                                reinterpret_cast<float2*>(probe_out), s));
@@ -331,6 +333,8 @@ ptyg_status run_grad(const ptyg_dims* dims, const float2* obj, const float2* pro
   a.eps = eps;
   a.ubuf = at<float2>(ws, L.ubuf);
   a.partials = at<double>(ws, L.partials);
+  // conj(p) folded into the stored waves unless the probe gradient needs them plain
+  a.premul = !grad_probe && dims->n <= 128;
   int nb = 0;
   {
     TimedLaunch tl(0, s);
@@ -340,8 +344,8 @@ ptyg_status run_grad(const ptyg_dims* dims, const float2* obj, const float2* pro
   if (gstore && gsum) PTYG_HIP(launch_finalize(a.zs_part, nb, 1, gsum, s));
   {
     TimedLaunch tl(3, s);
-    PTYG_HIP(launch_tile_sum(a.ubuf, probe, pos, at<int>(ws, L.toff), at<int>(ws, L.tlist), dims->k,
-                             dims->obj_h, dims->obj_w, dims->n, grad_obj, s));
+    PTYG_HIP(launch_tile_sum(a.ubuf, a.premul ? nullptr : probe, pos, at<int>(ws, L.toff), at<int>(ws, L.tlist),
+                             dims->k, dims->obj_h, dims->obj_w, dims->n, grad_obj, s));
   }
   if (grad_probe)
     PTYG_HIP(launch_probe_grad(a.ubuf, obj, pos, dims->k, dims->obj_w, dims->n, at<float2>(ws, L.pparts),

@@ -147,17 +147,35 @@ __device__ __forceinline__ void gather_exit_wave(float2* v, const PatArgs& a, co
 }
 
 // Store the back-propagated wave u_k (column layout, spatial slots) of
-// every pattern; the conj(p) multiply and the overlap sum follow in
-// k_tile_sum, the probe adjoint in k_probe_partial.
+// every pattern, or conj(p) u_k when only the object adjoint is wanted; the
+// overlap sum follows in k_tile_sum (which then needs no probe), the probe
+// adjoint in k_probe_partial (from the plain u_k).  A load issued after a
+// store waits for it, so the probe comes in a few large chunks.
+constexpr int kStoreChunk = 32;
+
 template <int N>
 __device__ __forceinline__ void store_u(const float2* v, const PatArgs& a, const Lane& L, int k, bool valid) {
   using G = Geo<N>;
   constexpr int T = G::TPC;
+  constexpr int C = G::E < kStoreChunk ? G::E : kStoreChunk;
   if (!valid) return;
   const uint32_t plo = lane_off<N>(L, N);
   float2* uk = a.ubuf + (size_t)k * N * N;
+  if (a.premul) {
 #pragma unroll
-  for (int m = 0; m < G::E; ++m) (uk + m * T * N)[plo] = v[m];
+    for (int c = 0; c < G::E; c += C) {
+      __builtin_amdgcn_sched_barrier(0);
+      float2 p[C];
+#pragma unroll
+      for (int m = c; m < c + C; ++m) p[m - c] = (a.probe + m * T * N)[plo];
+#pragma unroll
+      for (int m = c; m < c + C; ++m) (uk + m * T * N)[plo] = cmulc(p[m - c], v[m]);
+    }
+    __builtin_amdgcn_sched_barrier(0);
+  } else {
+#pragma unroll
+    for (int m = 0; m < G::E; ++m) (uk + m * T * N)[plo] = v[m];
+  }
 }
 
 // Pattern handled by this lane.  Lanes past the last pattern (only possible
@@ -621,7 +639,8 @@ __global__ __launch_bounds__(1024) void k_scan(const int* __restrict__ counts, i
   if (threadIdx.x == 1023) offsets[T] = part[1023];
 }
 
-// grad[y][x] = sum over the tile's patterns (ascending k) of conj(p) * u_k.
+// grad[y][x] = sum over the tile's patterns (ascending k) of conj(p) * u_k,
+// or of the stored values themselves when they already carry conj(p).
 // 256 threads: lane column x = x0 + (t & 63), rows y0 + (t >> 6) + 4 i.
 // The tile's pattern list and positions are staged in LDS (kTileStage at a
 // time) so the loop issues its loads without waiting on scalar loads.
@@ -635,22 +654,16 @@ __device__ __forceinline__ int u_off(int yy, int xx, int N) {
   else return yy * N + xx;
 }
 
-template <int R, bool POLY>
-__device__ __forceinline__ void tile_accumulate(float2 (&acc)[R], const float2* __restrict__ U,
-                                                const float2* __restrict__ probe, int k, int2 rc, int x, int yb,
-                                                int N) {
-  const int xx = x - rc.y;
-  if ((unsigned)xx >= (unsigned)N) return;
-  const float2* uk = U + (size_t)k * N * N;
-  const float2* pk = probe + xx;
-#pragma unroll
-  for (int i = 0; i < R; ++i) {
-    const int yy = yb + 4 * i - rc.x;
-    if ((unsigned)yy < (unsigned)N) acc[i] = cadd(acc[i], cmulc(pk[yy * N], uk[u_off<POLY>(yy, xx, N)]));
-  }
-}
+// The loads of kTileDepth patterns are issued before their adds: every lane
+// loads from a clamped in-patch address (valid memory) and an out-of-patch
+// value is dropped by a select, so no load sits behind a branch and the adds
+// still run in ascending pattern order.
+#ifndef PTYG_TILE_DEPTH
+#define PTYG_TILE_DEPTH 4
+#endif
+constexpr int kTileDepth = PTYG_TILE_DEPTH;
 
-template <bool POLY>
+template <bool POLY, bool PROBE>
 __global__ __launch_bounds__(256) void k_tile_sum(const float2* __restrict__ U, const float2* __restrict__ probe,
                                                    const int2* __restrict__ pos, const int* __restrict__ offsets,
                                                    const int* __restrict__ list, int H, int W, int N,
@@ -662,6 +675,7 @@ __global__ __launch_bounds__(256) void k_tile_sum(const float2* __restrict__ U, 
   const int x = (t % ntx) * kTileW + (threadIdx.x & 63);
   const int yb = (t / ntx) * kTileH + (threadIdx.x >> 6);
   constexpr int R = kTileH / 4;
+  constexpr int D = kTileDepth;
   float2 acc[R];
 #pragma unroll
   for (int i = 0; i < R; ++i) acc[i] = make_float2(0.f, 0.f);
@@ -675,12 +689,38 @@ __global__ __launch_bounds__(256) void k_tile_sum(const float2* __restrict__ U, 
       sp[j] = pos[k];
     }
     __syncthreads();
-    int j = 0;
-    for (; j + 1 < n; j += 2) {
-      tile_accumulate<R, POLY>(acc, U, probe, sk[j], sp[j], x, yb, N);
-      tile_accumulate<R, POLY>(acc, U, probe, sk[j + 1], sp[j + 1], x, yb, N);
+    for (int j = 0; j < n; j += D) {
+      float2 uv[D][R], pv[D][R];
+      bool ok[D][R];
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+        const bool live = j + q < n;
+        const int jj = live ? j + q : j;
+        const int2 rc = sp[jj];
+        const int xx = x - rc.y;
+        const bool cv = live && (unsigned)xx < (unsigned)N;
+        const int xc = min(max(xx, 0), N - 1);
+        const float2* uk = U + (size_t)sk[jj] * N * N;
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const int yy = yb + 4 * i - rc.x;
+          ok[q][i] = cv && (unsigned)yy < (unsigned)N;
+          const int yc = min(max(yy, 0), N - 1);
+          uv[q][i] = uk[u_off<POLY>(yc, xc, N)];
+          if constexpr (PROBE) pv[q][i] = probe[yc * N + xc];
+        }
+      }
+      // keep every load of the group ahead of the first add
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int q = 0; q < D; ++q) {
+#pragma unroll
+        for (int i = 0; i < R; ++i) {
+          const float2 v = cadd(acc[i], PROBE ? cmulc(pv[q][i], uv[q][i]) : uv[q][i]);
+          acc[i] = ok[q][i] ? v : acc[i];
+        }
+      }
     }
-    if (j < n) tile_accumulate<R, POLY>(acc, U, probe, sk[j], sp[j], x, yb, N);
   }
   if (x < W) {
 #pragma unroll
@@ -1328,10 +1368,17 @@ hipError_t launch_tile_sum(const float2* ubuf, const float2* probe, const int2* 
                            const int* list, int K, int H, int W, int N, float2* out, hipStream_t s) {
   (void)K;
   const int T = tiles_x(W) * tiles_y(H);
-  if (N == 256)
-    hipLaunchKernelGGL(k_tile_sum<true>, dim3(T), dim3(256), 0, s, ubuf, probe, pos, offsets, list, H, W, N, out);
-  else
-    hipLaunchKernelGGL(k_tile_sum<false>, dim3(T), dim3(256), 0, s, ubuf, probe, pos, offsets, list, H, W, N, out);
+  if (N == 256) {
+    if (!probe) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_tile_sum<true, true>), dim3(T), dim3(256), 0, s, ubuf, probe, pos, offsets, list, H, W, N,
+                       out);
+  } else if (probe) {
+    hipLaunchKernelGGL((k_tile_sum<false, true>), dim3(T), dim3(256), 0, s, ubuf, probe, pos, offsets, list, H, W,
+                       N, out);
+  } else {
+    hipLaunchKernelGGL((k_tile_sum<false, false>), dim3(T), dim3(256), 0, s, ubuf, probe, pos, offsets, list, H, W,
+                       N, out);
+  }
   return hipGetLastError();
 }
 

@@ -22,6 +22,7 @@ struct PatArgs {
   float2* far;           // far field [K][N][N] (forward out / adjoint in)
   float2* gobj;          // accumulator of the atomic debug scatter [H][W]
   float2* ubuf;          // per-pattern back-propagated waves u_k = F^H r_k, [K][N][N]
+  int premul;            // GRAD / adjoint, n <= 128: store conj(p) u_k (object adjoint only)
   double* partials;      // per-workgroup (phi, f) pairs
   float eps;
   int est;               // estimator: kEstML (Eq. ML) or kEstLS (least squares on amplitudes)
@@ -111,7 +112,8 @@ inline int tiles_per_patch(int n) { return ((n - 1) / kTileH + 2) * ((n - 1) / k
 // offsets [T + 1], list [sum of counts] (at most K * tiles_per_patch(N)).
 hipError_t launch_tile_lists(const int2* pos, int K, int H, int W, int N, int* offsets, int* list, hipStream_t s);
 // out[y][x] = sum over the tile's patterns k (ascending) of conj(p) * u_k at
-// (y - r_k, x - c_k); every object pixel is written.
+// (y - r_k, x - c_k); every object pixel is written.  probe = NULL: ubuf
+// already holds conj(p) * u_k (PatArgs::premul, n <= 128 only).
 hipError_t launch_tile_sum(const float2* ubuf, const float2* probe, const int2* pos, const int* offsets,
                            const int* list, int K, int H, int W, int N, float2* out, hipStream_t s);
 // out[u][v] = sum_k conj(obj[r_k + u][c_k + v]) u_k[u][v], in fixed order
