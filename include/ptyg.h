@@ -219,16 +219,19 @@ ptyg_status ptyg_cg_solve_views(const ptyg_dims* dims, int32_t views, ptyg_c64* 
                                 size_t ws_bytes, ptyg_cg_iter_stats* trace, int32_t* iters_done,
                                 ptyg_stream_t stream);
 
-/* Opt-in kernel timing for benchmarks: when enabled, the fused GRAD kernel
- * (kind 0), the line-search kernel (kind 1: a MINFUNC pass, or a batched
- * pass over stored far fields), the forward transform of the search
- * direction of the batched line search (kind 2) and the ordered overlap sum
- * of the object gradient (kind 3) launched by the solver and the GRAD call
- * are bracketed by HIP events on their stream.  ptyg_timing_read waits for
- * the recorded events and returns, per kind, the total elapsed milliseconds
- * and the number of launches since the last reset (arrays of `kinds`
- * entries, kinds <= 4).  Timing is per process and not thread-safe. */
-void ptyg_timing_enable(int32_t on);
+/* Opt-in kernel timing for benchmarks: the fused GRAD kernel (kind 0), the
+ * line-search kernel (kind 1: a MINFUNC pass, or a batched pass over stored
+ * far fields), the forward transform of the search direction of the batched
+ * line search (kind 2) and the ordered overlap sum of the object gradient
+ * (kind 3) launched by the solver and the GRAD call can be bracketed by HIP
+ * events on their stream.  `kinds_mask`: bit k times kind k (0 turns timing
+ * off, -1 times every kind); each recorded event pair adds a few
+ * microseconds between launches, so a timed run should time only the kinds
+ * it reports.  ptyg_timing_read waits for the recorded events and returns,
+ * per kind, the total elapsed milliseconds and the number of launches since
+ * the last reset (arrays of `kinds` entries, kinds <= 4).  Timing is per
+ * process and not thread-safe. */
+void ptyg_timing_enable(int32_t kinds_mask);
 void ptyg_timing_reset(void);
 ptyg_status ptyg_timing_read(double* ms, int32_t* count, int32_t kinds);
 

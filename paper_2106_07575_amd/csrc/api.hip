@@ -36,7 +36,11 @@ ptyg_status fail(ptyg_status st, const char* fmt, ...) {
   } while (0)
 
 constexpr size_t kAlign = 256;
-constexpr size_t kScalars = 32;
+constexpr size_t kScalars = 64;
+// Slots of the scalar region read back together once per line-search pass:
+// solver scalars [0, 16), zero-pixel sums [16, 32), line-search row [32, 56).
+constexpr int kZsSlot = 16, kLsSlot = 32;
+static_assert(kLsSlot + kLsRow <= (int)kScalars, "scalar region too small");
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -63,7 +67,7 @@ constexpr int kGdTrace = 1024;  // objectives kept on the device between gradien
 
 struct Layout {
   size_t partials, scalars, gdtrace, flag, pparts, eta_obj, grad_obj, eta_probe, grad_probe, data_t, ubuf, toff, tlist,
-      far_a, far_b, far_c, lsparts, lsphi, nz_counts, nz_offsets, nz_idx, zparts, zsums, total;
+      far_a, far_b, far_c, lsparts, lsphi, nz_counts, nz_offsets, nz_idx, zparts, zsums, illum, total;
   size_t nz_blocks, z_blocks;
   size_t n_partials;
 };
@@ -107,6 +111,7 @@ Layout layout(const ptyg_dims* d, bool joint, bool batched = false) {
   const size_t nl = std::max(T, (size_t)d->k * tiles_per_patch(d->n));
   o = align_up(o + nl * sizeof(int));
   L.far_a = L.far_b = L.far_c = L.lsparts = L.lsphi = L.nz_counts = L.nz_offsets = L.nz_idx = L.zparts = L.zsums = 0;
+  L.illum = 0;
   L.nz_blocks = L.z_blocks = 0;
   if (batched) {
     const size_t elems = (size_t)d->k * probe_n;
@@ -118,11 +123,12 @@ Layout layout(const ptyg_dims* d, bool joint, bool batched = false) {
     o = align_up(o + (L.nz_blocks + 1) * sizeof(int));
     L.nz_idx = o;
     o = align_up(o + elems * sizeof(int));
-    // GRAD sums of |G psi|^2 (one per block), then the direction passes' rows
+    // GRAD sums of |G psi|^2 (one per block), then the rows of the direction
+    // sums (the direction forward passes' or, object only, the DIR kernel's)
     L.zparts = o;
-    o = align_up(o + (L.n_partials + 2 * L.z_blocks * 4) * sizeof(double));
-    L.zsums = o;
-    o = align_up(o + 16 * sizeof(double));
+    o = align_up(o + (L.n_partials + std::max<size_t>(2 * L.z_blocks, (size_t)vec_blocks((int64_t)obj_n)) * 4) *
+                         sizeof(double));
+    L.zsums = L.scalars + kZsSlot * sizeof(double);
     const size_t far_bytes = (size_t)d->k * probe_n * sizeof(float2);
     L.far_a = o;
     o = align_up(o + far_bytes);
@@ -134,8 +140,13 @@ Layout layout(const ptyg_dims* d, bool joint, bool batched = false) {
     }
     L.lsparts = o;
     o = align_up(o + (size_t)kLsBlocks * kLsRow * sizeof(double));
-    L.lsphi = o;
-    o = align_up(o + kLsRow * sizeof(double));
+    L.lsphi = L.scalars + kLsSlot * sizeof(double);
+    if (!joint) {
+      // illumination sum_k |p(x - s_k)|^2: with the probe fixed, G^H G is
+      // this diagonal, so Re<G psi, G eta> and ||G eta||^2 are object sums
+      L.illum = o;
+      o = align_up(o + obj_n * sizeof(float2));
+    }
   }
   L.total = o;
   return L;
@@ -170,7 +181,7 @@ hipStream_t S(ptyg_stream_t s) { return reinterpret_cast<hipStream_t>(s); }
 
 // ---- opt-in kernel timing (HIP events around the pattern kernels)
 struct Timing {
-  bool on = false;
+  int mask = 0;  // bit k: time kind k
   struct Rec {
     int kind;
     hipEvent_t a, b;
@@ -185,8 +196,10 @@ struct Timing {
       pool.pop_back();
       return e;
     }
+    // device-scope events: a system-scope release at every record would
+    // write back the caches between the timed kernels
     hipEvent_t e = nullptr;
-    if (hipEventCreate(&e) != hipSuccess) return nullptr;
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) != hipSuccess) return nullptr;
     return e;
   }
   // waits for every recorded pair and accumulates it
@@ -205,12 +218,26 @@ struct Timing {
 };
 Timing g_timing;
 
+// Host side of the solver's scalar readbacks: pinned, so that a copy is
+// asynchronous and one stream synchronisation covers it (a copy into pageable
+// memory is staged and waits by itself).  One buffer per host thread,
+// allocated on its first solve and kept until the process ends.
+double* readback_buffer() {
+  thread_local double* buf = nullptr;
+  if (!buf) {
+    void* p = nullptr;
+    if (hipHostMalloc(&p, kScalars * sizeof(double), hipHostMallocDefault) != hipSuccess) return nullptr;
+    buf = static_cast<double*>(p);
+  }
+  return buf;
+}
+
 struct TimedLaunch {
   int kind;
   hipStream_t s;
   hipEvent_t a = nullptr, b = nullptr;
   TimedLaunch(int k, hipStream_t st) : kind(k), s(st) {
-    if (!g_timing.on) return;
+    if (!((g_timing.mask >> kind) & 1)) return;
     a = g_timing.get();
     b = g_timing.get();
     if (a && b) hipEventRecord(a, s);
@@ -226,7 +253,7 @@ struct TimedLaunch {
 
 extern "C" {
 
-int32_t ptyg_abi_version(void) { return 3; }
+int32_t ptyg_abi_version(void) { return 4; }
 
 const char* ptyg_status_string(ptyg_status s) {
   switch (s) {
@@ -462,6 +489,10 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
   // so that the row-layout reads are coalesced
   PTYG_HIP(launch_transpose_data(data, dt, dims->k, dims->n, s));
   if (ptyg_status st = build_tiles(dims, pos, ws, L, s)) return st;
+  float2* illum = batched && !joint ? at<float2>(ws, L.illum) : nullptr;
+  if (illum)
+    PTYG_HIP(launch_illum(probe, pos, at<int>(ws, L.toff), at<int>(ws, L.tlist), dims->obj_h, dims->obj_w, dims->n,
+                          illum, s));
   // batched line search: the elements with d > 0 (or NaN) are evaluated per
   // trial; the d <= 0 ones through the zero-pixel sums
   int64_t nnz = 0;
@@ -481,7 +512,8 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
     PHIT = 10,  // a trial's (Phi, F): two slots
     BETA = 12, RST = 13, NSC = 14
   };
-  double h[16];
+  double* h = readback_buffer();
+  if (!h) return fail(PTYG_E_HIP, "pinned readback buffer: %s", hipGetErrorString(hipGetLastError()));
   bool restart = true;
   const int nvb_o = vec_blocks(on), nvb_p = vec_blocks(pn);
   // the direction update reads its coefficient from the device: start from a
@@ -522,8 +554,17 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
     v.alpha_dev = sc + BETA;
     v.restart_dev = sc + RST;
     v.partials = partials;
+    if (illum) {
+      // Re<G psi, G eta> and ||G eta||^2 for the batched search, as
+      // illumination-weighted object sums (rows of 4 like the direction
+      // forward's sums)
+      v.zs_psi = obj;
+      v.zs_w = illum;
+      v.zs_part = at<double>(ws, L.zparts) + L.n_partials;
+    }
     PTYG_HIP(launch_dir(v, s));
     PTYG_HIP(launch_finalize(partials, nvb_o, 2, sc + N3O, s));
+    if (illum) PTYG_HIP(launch_finalize(v.zs_part, nvb_o, 4, at<double>(ws, L.zsums) + 4, s));
     if (joint) {
       VecArgs vp{};
       vp.n = pn;
@@ -562,8 +603,10 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
       fa.far = far_b;
       double* zparts = at<double>(ws, L.zparts) + L.n_partials;
       double* zsums = at<double>(ws, L.zsums);
-      fa.zs_p = far_a;  // sums (Re a b*, 0, |b|^2, 0)
-      fa.zs_part = zparts;
+      if (joint) {
+        fa.zs_p = far_a;  // sums (Re a b*, 0, |b|^2, 0)
+        fa.zs_part = zparts;
+      }
       {
         TimedLaunch tl_fwd(2, s);
         if (!joint) {
@@ -587,8 +630,10 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
           PTYG_HIP(launch_fwd_t(fc, false, s));
         }
       }
-      PTYG_HIP(launch_finalize(zparts, (int)L.z_blocks, 4, zsums + 4, s));
-      if (joint) PTYG_HIP(launch_finalize(zparts + 4 * L.z_blocks, (int)L.z_blocks, 4, zsums + 8, s));
+      if (joint) {
+        PTYG_HIP(launch_finalize(zparts, (int)L.z_blocks, 4, zsums + 4, s));
+        PTYG_HIP(launch_finalize(zparts + 4 * L.z_blocks, (int)L.z_blocks, 4, zsums + 8, s));
+      }
       LsArgs la{};
       la.A = far_a;
       la.B = far_b;
@@ -599,7 +644,7 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
       la.eps = eps;
       la.est = est;
       // whole-array sums: [0] |a|^2 (GRAD), [4..7] direction pass, [8..11] joint pass
-      double zs[12] = {0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0, 0};
+      const double* zs = h + kZsSlot;
       double zc[6] = {0, 0, 0, 0, 0, 0};  // d <= 0 parts: aa, ab, bb, ac, bc, cc
       la.partials = lsparts;
       int j0 = 1;
@@ -622,13 +667,14 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
           PTYG_HIP(launch_ls_batch(la, &nb, s));
         }
         PTYG_HIP(launch_ls_finalize(lsparts, nb, lsphi, s));
-        double phis[kLsRow];
-        PTYG_HIP(hipMemcpyAsync(phis, lsphi, kLsRow * sizeof(double), hipMemcpyDeviceToHost, s));
-        if (first) {
-          PTYG_HIP(hipMemcpyAsync(h, sc, NSC * sizeof(double), hipMemcpyDeviceToHost, s));
-          PTYG_HIP(hipMemcpyAsync(zs, zsums, 12 * sizeof(double), hipMemcpyDeviceToHost, s));
-        }
+        // one copy per pass: the first reads the whole scalar region (solver
+        // scalars, zero-pixel sums, trial row), later ones the trial row
+        if (first)
+          PTYG_HIP(hipMemcpyAsync(h, sc, (kLsSlot + kLsRow) * sizeof(double), hipMemcpyDeviceToHost, s));
+        else
+          PTYG_HIP(hipMemcpyAsync(h + kLsSlot, lsphi, kLsRow * sizeof(double), hipMemcpyDeviceToHost, s));
         PTYG_HIP(hipStreamSynchronize(s));
+        const double* phis = h + kLsSlot;
         if (first) {
           if (ptyg_status st = take_scalars()) return st;
           if (stop) break;
@@ -1075,7 +1121,7 @@ ptyg_status ptyg_cg_solve_views(const ptyg_dims* dims, int32_t views, ptyg_c64* 
   return PTYG_OK;
 }
 
-void ptyg_timing_enable(int32_t on) { g_timing.on = on != 0; }
+void ptyg_timing_enable(int32_t kinds_mask) { g_timing.mask = kinds_mask & 0xF; }
 
 void ptyg_timing_reset(void) {
   g_timing.drain();

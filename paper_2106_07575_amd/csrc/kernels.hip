@@ -667,7 +667,7 @@ template <bool POLY, bool PROBE>
 __global__ __launch_bounds__(256) void k_tile_sum(const float2* __restrict__ U, const float2* __restrict__ probe,
                                                    const int2* __restrict__ pos, const int* __restrict__ offsets,
                                                    const int* __restrict__ list, int H, int W, int N,
-                                                   float2* __restrict__ out) {
+                                                   int64_t ustride, float2* __restrict__ out) {
   __shared__ int sk[kTileStage];
   __shared__ int2 sp[kTileStage];
   const int ntx = tiles_x(W);
@@ -700,7 +700,7 @@ __global__ __launch_bounds__(256) void k_tile_sum(const float2* __restrict__ U, 
         const int xx = x - rc.y;
         const bool cv = live && (unsigned)xx < (unsigned)N;
         const int xc = min(max(xx, 0), N - 1);
-        const float2* uk = U + (size_t)sk[jj] * N * N;
+        const float2* uk = U + sk[jj] * ustride;
 #pragma unroll
         for (int i = 0; i < R; ++i) {
           const int yy = yb + 4 * i - rc.x;
@@ -799,7 +799,10 @@ __global__ __launch_bounds__(kVecWG) void k_dot2(VecArgs v) {
 
 __global__ __launch_bounds__(kVecWG) void k_dir(VecArgs v) {
   __shared__ double red[2 * (kVecWG / 64)];
+  __shared__ double red4[4 * (kVecWG / 64)];
   double s1 = 0.0, s2 = 0.0;
+  double z[4] = {0.0, 0.0, 0.0, 0.0};
+  const bool zs = v.zs_part != nullptr;
   const float beta = (float)(v.alpha_dev ? *v.alpha_dev : v.alpha);
   const bool rst = v.restart_dev && *v.restart_dev != 0.0;
   for (int64_t i = (int64_t)blockIdx.x * kVecWG + threadIdx.x; i < v.n; i += (int64_t)gridDim.x * kVecWG) {
@@ -809,12 +812,19 @@ __global__ __launch_bounds__(kVecWG) void k_dir(VecArgs v) {
     v.b[i] = en;
     s1 += (double)en.x * g.x + (double)en.y * g.y;
     s2 += (double)en.x * en.x + (double)en.y * en.y;
+    if (zs) {
+      const float2 p = v.zs_psi[i];
+      const double w = v.zs_w[i].x;
+      z[0] += w * ((double)p.x * en.x + (double)p.y * en.y);
+      z[2] += w * ((double)en.x * en.x + (double)en.y * en.y);
+    }
   }
   block_sum2<kVecWG>(s1, s2, red);
   if (threadIdx.x == 0) {
     v.partials[2 * blockIdx.x] = s1;
     v.partials[2 * blockIdx.x + 1] = s2;
   }
+  if (zs) block_sum4_store<kVecWG>(z, red4, v.zs_part + 4 * blockIdx.x);
 }
 
 __global__ void k_dy_beta(double* sc, int n1, int n2, int n3, int joint_off, int beta, int rst, int restart) {
@@ -1368,17 +1378,28 @@ hipError_t launch_tile_sum(const float2* ubuf, const float2* probe, const int2* 
                            const int* list, int K, int H, int W, int N, float2* out, hipStream_t s) {
   (void)K;
   const int T = tiles_x(W) * tiles_y(H);
+  const int64_t us = (int64_t)N * N;
   if (N == 256) {
     if (!probe) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_tile_sum<true, true>), dim3(T), dim3(256), 0, s, ubuf, probe, pos, offsets, list, H, W, N,
-                       out);
+                       us, out);
   } else if (probe) {
     hipLaunchKernelGGL((k_tile_sum<false, true>), dim3(T), dim3(256), 0, s, ubuf, probe, pos, offsets, list, H, W,
-                       N, out);
+                       N, us, out);
   } else {
     hipLaunchKernelGGL((k_tile_sum<false, false>), dim3(T), dim3(256), 0, s, ubuf, probe, pos, offsets, list, H, W,
-                       N, out);
+                       N, us, out);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_illum(const float2* probe, const int2* pos, const int* offsets, const int* list, int H, int W,
+                        int N, float2* out, hipStream_t s) {
+  if (!probe || !pos || !offsets || !list || !out) return hipErrorInvalidValue;
+  const int T = tiles_x(W) * tiles_y(H);
+  // every pattern's "u_k" is the probe itself (stride 0): sum conj(p) p
+  hipLaunchKernelGGL((k_tile_sum<false, true>), dim3(T), dim3(256), 0, s, probe, probe, pos, offsets, list, H, W, N,
+                     (int64_t)0, out);
   return hipGetLastError();
 }
 

@@ -71,6 +71,12 @@ struct VecArgs {
   double* partials;
   const double* alpha_dev;    // k_dir: coefficient read on the device (overrides alpha) ...
   const double* restart_dev;  // ... and a restart flag (nonzero: b <- -a, the old b ignored)
+  // k_dir, optional: rows (sum w Re(psi conj b), 0, sum w |b|^2, 0) per block
+  // over the new direction b, w = zs_w[i].x (the illumination: these are
+  // Re<G psi, G b> and ||G b||^2 when G^H G is diagonal)
+  const float2* zs_psi;
+  const float2* zs_w;
+  double* zs_part;
 };
 
 enum class DataLayout { Rows = 0, Transposed = 1 };
@@ -116,6 +122,10 @@ hipError_t launch_tile_lists(const int2* pos, int K, int H, int W, int N, int* o
 // already holds conj(p) * u_k (PatArgs::premul, n <= 128 only).
 hipError_t launch_tile_sum(const float2* ubuf, const float2* probe, const int2* pos, const int* offsets,
                            const int* list, int K, int H, int W, int N, float2* out, hipStream_t s);
+// out[y][x].x = sum over the tile's patterns k (ascending) of |p|^2 at
+// (y - r_k, x - c_k): the illumination, the diagonal of G^H G.
+hipError_t launch_illum(const float2* probe, const int2* pos, const int* offsets, const int* list, int H, int W,
+                        int N, float2* out, hipStream_t s);
 // out[u][v] = sum_k conj(obj[r_k + u][c_k + v]) u_k[u][v], in fixed order
 // (chunks of patterns, then chunks summed in order); partial holds
 // kProbeChunks * N * N values.

@@ -354,8 +354,18 @@ def debug_lane_swap(a, b):
 KERNEL_KINDS = ("grad", "minfunc", "dir_forward", "tile_sum")
 
 
-def timing_enable(on: bool = True):
-    load().ptyg_timing_enable(int(on))
+def timing_enable(on: bool = True, kinds=None):
+    """Time the kinds named in `kinds` (default: all of KERNEL_KINDS); each
+    timed launch adds an event pair between kernels."""
+    if not on:
+        mask = 0
+    elif kinds is None:
+        mask = -1
+    else:
+        mask = 0
+        for k in kinds:
+            mask |= 1 << KERNEL_KINDS.index(k)
+    load().ptyg_timing_enable(mask)
 
 
 def timing_reset():

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
     assert set(declared()) == set(ptyg.EXPORTS)
     # host-only calls work without a GPU
     lib = ptyg.load()
-    assert lib.ptyg_abi_version() == 3
+    assert lib.ptyg_abi_version() == 4
     d = ptyg.Dims(2048, 2048, 128, 4096)
     sz = ptyg.workspace_size(d)
     assert sz > 4096 * 128 * 128 * 4
