@@ -67,14 +67,16 @@ constexpr int kGdTrace = 1024;  // objectives kept on the device between gradien
 
 struct Layout {
   size_t partials, scalars, gdtrace, flag, pparts, eta_obj, grad_obj, eta_probe, grad_probe, data_t, ubuf, toff, tlist,
-      far_a, far_b, far_c, lsparts, lsphi, nz_counts, nz_offsets, nz_idx, zparts, zsums, illum, total;
+      far_a, far_b, far_c, lsparts, lsphi, nz_counts, nz_offsets, nz_idx, zparts, zsums, illum, nz_seg, nz_dc, total;
   size_t nz_blocks, z_blocks;
   size_t n_partials;
 };
 
 // The regions of the batched line search come last, so the offsets of the
 // others do not depend on it.
-Layout layout(const ptyg_dims* d, bool joint, bool batched = false) {
+// `views`: the multi-view solver's stacked layout (no illumination or
+// compacted far fields).
+Layout layout(const ptyg_dims* d, bool joint, bool batched = false, bool views = false) {
   Layout L{};
   const size_t obj_n = (size_t)d->obj_h * d->obj_w;
   const size_t probe_n = (size_t)d->n * d->n;
@@ -111,7 +113,7 @@ Layout layout(const ptyg_dims* d, bool joint, bool batched = false) {
   const size_t nl = std::max(T, (size_t)d->k * tiles_per_patch(d->n));
   o = align_up(o + nl * sizeof(int));
   L.far_a = L.far_b = L.far_c = L.lsparts = L.lsphi = L.nz_counts = L.nz_offsets = L.nz_idx = L.zparts = L.zsums = 0;
-  L.illum = 0;
+  L.illum = L.nz_seg = L.nz_dc = 0;
   L.nz_blocks = L.z_blocks = 0;
   if (batched) {
     const size_t elems = (size_t)d->k * probe_n;
@@ -141,11 +143,19 @@ Layout layout(const ptyg_dims* d, bool joint, bool batched = false) {
     L.lsparts = o;
     o = align_up(o + (size_t)kLsBlocks * kLsRow * sizeof(double));
     L.lsphi = L.scalars + kLsSlot * sizeof(double);
-    if (!joint) {
+    if (!joint && !views) {
       // illumination sum_k |p(x - s_k)|^2: with the probe fixed, G^H G is
       // this diagonal, so Re<G psi, G eta> and ||G eta||^2 are object sums
       L.illum = o;
       o = align_up(o + obj_n * sizeof(float2));
+      if (d->n == 128) {
+        // far fields stored for the listed elements only: segment records
+        // and the listed intensities, compacted
+        L.nz_seg = o;
+        o = align_up(o + elems / 32 * sizeof(uint2));
+        L.nz_dc = o;
+        o = align_up(o + elems * sizeof(float));
+      }
     }
   }
   L.total = o;
@@ -348,10 +358,11 @@ namespace {
 ptyg_status run_grad(const ptyg_dims* dims, const float2* obj, const float2* probe, const int2* pos,
                      const float* data, DataLayout lay, float eps, int est, float2* grad_obj, float2* grad_probe,
                      double* objective, void* ws, const Layout& L, hipStream_t s, float2* gstore = nullptr,
-                     double* gsum = nullptr) {
+                     double* gsum = nullptr, const uint2* cseg = nullptr) {
   PatArgs a = base_args(dims);
   a.est = est;
   a.gstore = gstore;
+  a.cseg = cseg;
   if (gstore) a.zs_part = at<double>(ws, L.zparts);
   a.obj = obj;
   a.probe = probe;
@@ -490,6 +501,9 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
   PTYG_HIP(launch_transpose_data(data, dt, dims->k, dims->n, s));
   if (ptyg_status st = build_tiles(dims, pos, ws, L, s)) return st;
   float2* illum = batched && !joint ? at<float2>(ws, L.illum) : nullptr;
+  // n = 128, object only: G psi and G eta are stored for the listed elements only
+  uint2* cseg = L.nz_seg ? at<uint2>(ws, L.nz_seg) : nullptr;
+  float* dcomp = L.nz_dc ? at<float>(ws, L.nz_dc) : nullptr;
   if (illum)
     PTYG_HIP(launch_illum(probe, pos, at<int>(ws, L.toff), at<int>(ws, L.tlist), dims->obj_h, dims->obj_w, dims->n,
                           illum, s));
@@ -499,7 +513,7 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
   if (batched) {
     int* offs = at<int>(ws, L.nz_offsets);
     PTYG_HIP(launch_nz_compact(dt, (int64_t)dims->k * dims->n * dims->n, at<int>(ws, L.nz_counts), offs,
-                               at<int>(ws, L.nz_idx), s));
+                               at<int>(ws, L.nz_idx), cseg, dcomp, s));
     int h_nnz = 0;
     PTYG_HIP(hipMemcpyAsync(&h_nnz, offs + L.nz_blocks, sizeof(int), hipMemcpyDeviceToHost, s));
     PTYG_HIP(hipStreamSynchronize(s));
@@ -524,7 +538,7 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
   for (int m = 0; m < opts->iters; ++m) {
     // GRAD stage
     if (ptyg_status st = run_grad(dims, obj, probe, pos, dt, DataLayout::Transposed, eps, est, grad_o, grad_p,
-                                  sc + PHI, ws, L, s, far_a, batched ? at<double>(ws, L.zsums) : nullptr))
+                                  sc + PHI, ws, L, s, far_a, batched ? at<double>(ws, L.zsums) : nullptr, cseg))
       return st;
     VecArgs v{};
     v.n = on;
@@ -601,6 +615,7 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
       fa.pos = pos;
       fa.ubuf = at<float2>(ws, L.ubuf);  // staging of the 256^2 transforms
       fa.far = far_b;
+      fa.cseg = cseg;
       double* zparts = at<double>(ws, L.zparts) + L.n_partials;
       double* zsums = at<double>(ws, L.zsums);
       if (joint) {
@@ -640,6 +655,10 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
       la.C = far_c;
       la.d = dt;
       la.idx = at<int>(ws, L.nz_idx);
+      if (cseg) {
+        la.compact = 1;
+        la.d = dcomp;
+      }
       la.n = nnz;
       la.eps = eps;
       la.est = est;
@@ -848,7 +867,7 @@ ptyg_status views_layout(const ptyg_dims* d, int32_t views, const ptyg_cg_opts* 
   V.stacked = *d;
   V.stacked.obj_h = d->obj_h * views;
   V.stacked.k = d->k * views;
-  V.L = layout(&V.stacked, false, opts && opts->line_search == PTYG_LS_BATCHED);
+  V.L = layout(&V.stacked, false, opts && opts->line_search == PTYG_LS_BATCHED, true);
   size_t o = V.L.total;
   V.pos2 = o;
   o = align_up(o + (size_t)V.stacked.k * sizeof(int2));
@@ -926,7 +945,7 @@ ptyg_status ptyg_cg_solve_views(const ptyg_dims* dims, int32_t views, ptyg_c64* 
   const int cpv = (int)(pe / kNzChunk);  // compaction chunks per view
   if (batched)
     PTYG_HIP(launch_nz_compact(dt, pe * V, at<int>(ws, L.nz_counts), at<int>(ws, L.nz_offsets), at<int>(ws, L.nz_idx),
-                               s));
+                               nullptr, nullptr, s));
 
   // per-view state
   std::vector<double> h((size_t)V * 32), hbeta(V, 0.0), halpha(V, 0.0), phi_m(V), f_m(V), n3_prev(V, 0.0);

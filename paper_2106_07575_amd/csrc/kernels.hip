@@ -282,17 +282,37 @@ __device__ __forceinline__ void gather_lin(float2* v, const PatArgs& a, const La
   __builtin_amdgcn_sched_barrier(0);
 }
 
+// Compacted far-field stores (n = 128): the pattern's segment records are
+// staged in LDS at kernel start (ordered before their first use by the
+// barrier of the first transpose); the lane's element of slot s, row
+// f = kFreq[s] + (E/2) h and column `line`, lies in segment 4 f + line / 32.
+constexpr int kSegPerPattern = 128 * 128 / 32;
+
+__device__ __forceinline__ void stage_segments(uint2* srec, const PatArgs& a, int k) {
+  const uint2* src = a.cseg + (size_t)k * kSegPerPattern;
+  for (int i = threadIdx.x; i < kSegPerPattern; i += 256) srec[i] = src[i];
+}
+
+__device__ __forceinline__ void store_compact(float2* out, const uint2* srec, const Lane& L, int f, float2 v) {
+  const uint2 r = srec[f * 4 + (L.line >> 5)];
+  const uint32_t bit = (uint32_t)L.line & 31u;
+  if ((r.x >> bit) & 1u) out[r.y + __popc(r.x & ((1u << bit) - 1u))] = v;
+}
+
 // Forward transform of a direction, stored per pattern transposed (the
 // element order of the transposed intensities and of the stored G psi).
 // ZS: also the sums over this workgroup's elements of Re(P conj y),
 // Re(Q conj y) (Q nullable) and |y|^2 (P = a.zs_p, Q = a.zs_q stored far
 // fields, y = the result).  They are formed before any store: loads wait on
 // every earlier memory operation, stores included.
-template <int N, bool LIN, int ZS>
+// CP (n = 128, no sums): only the listed elements, compacted (a.cseg).
+template <int N, bool LIN, int ZS, bool CP = false>
 __global__ PTYG_PATTERN_KERNEL(N) void k_fwd_t(PatArgs a) {
   using G = Geo<N>;
+  static_assert(!CP || (N == 128 && ZS == 0), "compacted stores: n = 128 without sums");
   __shared__ float2 lds[G::LDS_ELEMS];
   __shared__ double red[4 * (G::WG / 64)];
+  __shared__ uint2 srec[CP ? kSegPerPattern : 1];
   const Lane L = lane_info<N>();
   int k;
   bool valid;
@@ -301,6 +321,7 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_fwd_t(PatArgs a) {
     if (ZS > 0 && threadIdx.x < 4) a.zs_part[4 * blockIdx.x + threadIdx.x] = 0.0;
     return;
   }
+  if constexpr (CP) stage_segments(srec, a, k);
   float2 v[G::E];
   if constexpr (LIN) gather_lin<N>(v, a, L, rc, valid);
   else gather_exit_wave<N, false, false>(v, a, L, rc, valid);
@@ -337,17 +358,22 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_fwd_t(PatArgs a) {
     __builtin_amdgcn_sched_barrier(0);
     block_sum4_store<G::WG>(z, red, a.zs_part + 4 * blockIdx.x);
   }
-  if (G::PPW == 1 || valid) {
+  if constexpr (CP) {
+#pragma unroll
+    for (int s = 0; s < G::E; ++s) store_compact(a.far, srec, L, fidx<N>(s, L.h), v[s]);
+  } else if (G::PPW == 1 || valid) {
 #pragma unroll
     for (int s = 0; s < G::E; ++s) (a.far + kb + (size_t)kFreq<N>.f[s] * N)[lo] = v[s];
   }
 }
 
-template <int N, DataLayout LAY, bool SG, int EST>
+template <int N, DataLayout LAY, bool SG, int EST, bool CP = false>
 __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
   using G = Geo<N>;
+  static_assert(!CP || (N == 128 && SG), "compacted stores: n = 128 with the G psi store");
   __shared__ float2 lds[G::LDS_ELEMS];
   __shared__ double red[2 * (G::WG / 64)];
+  __shared__ uint2 srec[CP ? kSegPerPattern : 1];
   const Lane L = lane_info<N>();
   int k;
   bool valid;
@@ -357,6 +383,7 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
     if (SG && threadIdx.x == 0) a.zs_part[blockIdx.x] = 0.0;
     return;
   }
+  if constexpr (CP) stage_segments(srec, a, k);
   float2 v[G::E];
   gather_exit_wave<N, false, false>(v, a, L, rc, valid);
   fwd_line<N>(v, L.h);
@@ -377,7 +404,8 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
       if (s % 8 == 0) __builtin_amdgcn_sched_barrier(0);
       v[s] = cscale(v[s], invN);  // scaled in place: v now holds G psi
       acc_aa += (double)v[s].x * v[s].x + (double)v[s].y * v[s].y;
-      if (G::PPW == 1 || valid) (gk + (size_t)kFreq<N>.f[s] * N)[lo] = v[s];
+      if constexpr (CP) store_compact(a.gstore, srec, L, fidx<N>(s, L.h), v[s]);
+      else if (G::PPW == 1 || valid) (gk + (size_t)kFreq<N>.f[s] * N)[lo] = v[s];
     }
     __builtin_amdgcn_sched_barrier(0);
   }
@@ -865,14 +893,14 @@ __global__ __launch_bounds__(kVecWG) void k_sum_copies(const float2* src, int co
 // A + g_j B (+ g_j^2 C), evaluated with the same per-pixel deviance as a
 // MINFUNC pass for every listed element (d > 0 or NaN), FP64 accumulation
 // per trial, per-workgroup partials in a fixed order.
-template <bool QUAD, int EST>
+template <bool QUAD, int EST, bool CP>
 __global__ __launch_bounds__(256) void k_ls_batch(LsArgs a) {
   __shared__ double red[4][kLsRow];
   double acc[kLsRow];
 #pragma unroll
   for (int j = 0; j < kLsRow; ++j) acc[j] = 0.0;
   for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < a.n; i += (int64_t)gridDim.x * 256) {
-    const int e = a.idx[i];
+    const int64_t e = CP ? i : (int64_t)a.idx[i];
     const float2 av = a.A[e], bv = a.B[e];
     float2 cv = make_float2(0.f, 0.f);
     if constexpr (QUAD) cv = a.C[e];
@@ -934,7 +962,8 @@ __global__ __launch_bounds__(256) void k_nz_count(const float* __restrict__ d, i
 }
 
 __global__ __launch_bounds__(256) void k_nz_fill(const float* __restrict__ d, int64_t n,
-                                                 const int* __restrict__ offsets, int* __restrict__ idx) {
+                                                 const int* __restrict__ offsets, int* __restrict__ idx,
+                                                 uint2* __restrict__ seg, float* __restrict__ dc) {
   __shared__ int wcnt[4];
   const int64_t base = (int64_t)blockIdx.x * kNzChunk;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
@@ -942,13 +971,21 @@ __global__ __launch_bounds__(256) void k_nz_fill(const float* __restrict__ d, in
   int run = offsets[blockIdx.x];
   for (int r = 0; r < kNzChunk / 256; ++r) {
     const int64_t e = base + r * 256 + threadIdx.x;
-    const bool nz = e < n && !(d[e] <= 0.0f);
+    const float de = e < n ? d[e] : 0.0f;
+    const bool nz = e < n && !(de <= 0.0f);
     const uint64_t m = __ballot(nz);
     if (l == 0) wcnt[w] = __popcll(m);
     __syncthreads();
     int pre = 0;
     for (int i = 0; i < w; ++i) pre += wcnt[i];
-    if (nz) idx[run + pre + __popcll(m & below)] = (int)e;
+    const int at = run + pre + __popcll(m & below);
+    if (nz) {
+      idx[at] = (int)e;
+      if (dc) dc[at] = de;
+    }
+    // segment records: lanes 0 and 32 of the wave (32 elements each)
+    if (seg && (l & 31) == 0 && e < n)
+      seg[e >> 5] = make_uint2((uint32_t)(l ? (m >> 32) : (m & 0xffffffffull)), (uint32_t)at);
     run += wcnt[0] + wcnt[1] + wcnt[2] + wcnt[3];
     __syncthreads();
   }
@@ -1216,8 +1253,14 @@ hipError_t launch_grad(const PatArgs& a, DataLayout lay, int* blocks_out, hipStr
     return dispatch_est(a.est, [&](auto ec) {
       constexpr int E = decltype(ec)::value;
       if (lay == DataLayout::Transposed) {
-        if (a.gstore) hipLaunchKernelGGL((k_grad<N, DataLayout::Transposed, true, E>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_grad<N, DataLayout::Transposed, false, E>), g, b, 0, s, a);
+        if (a.gstore && a.cseg) {
+          if constexpr (N == 128) hipLaunchKernelGGL((k_grad<N, DataLayout::Transposed, true, E, true>), g, b, 0, s, a);
+          else return hipErrorInvalidValue;
+        } else if (a.gstore) {
+          hipLaunchKernelGGL((k_grad<N, DataLayout::Transposed, true, E>), g, b, 0, s, a);
+        } else {
+          hipLaunchKernelGGL((k_grad<N, DataLayout::Transposed, false, E>), g, b, 0, s, a);
+        }
       } else {
         hipLaunchKernelGGL((k_grad<N, DataLayout::Rows, false, E>), g, b, 0, s, a);
       }
@@ -1231,6 +1274,11 @@ hipError_t launch_fwd_t(const PatArgs& a, bool lin, hipStream_t s) {
   if (lin && (!a.dobj || !a.dprobe)) return hipErrorInvalidValue;
   const bool zs = a.zs_part != nullptr;
   if (zs && !a.zs_p) return hipErrorInvalidValue;
+  if (a.cseg) {
+    if (a.N != 128 || zs || lin) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((k_fwd_t<128, false, 0, true>), dim3(pattern_blocks<128>(a.K)), dim3(Geo<128>::WG), 0, s, a);
+    return hipGetLastError();
+  }
   if (a.N == 256) return launch_fwd_t256(a, lin, s);
   return dispatch_n(a.N, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
@@ -1259,26 +1307,30 @@ int fwd_t_blocks(int N, int K) {
   return nb;
 }
 
-hipError_t launch_nz_compact(const float* d, int64_t n, int* counts, int* offsets, int* idx, hipStream_t s) {
+hipError_t launch_nz_compact(const float* d, int64_t n, int* counts, int* offsets, int* idx, uint2* seg,
+                             float* dc, hipStream_t s) {
   if (!d || !counts || !offsets || !idx || n < 1) return hipErrorInvalidValue;
+  if (seg && n % 32) return hipErrorInvalidValue;
   const int64_t blocks = (n + kNzChunk - 1) / kNzChunk;
   if (blocks > (1 << 30)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_nz_count, dim3((unsigned)blocks), dim3(256), 0, s, d, n, counts);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, (int)blocks, offsets);
-  hipLaunchKernelGGL(k_nz_fill, dim3((unsigned)blocks), dim3(256), 0, s, d, n, offsets, idx);
+  hipLaunchKernelGGL(k_nz_fill, dim3((unsigned)blocks), dim3(256), 0, s, d, n, offsets, idx, seg, dc);
   return hipGetLastError();
 }
 
 hipError_t launch_ls_batch(const LsArgs& a, int* blocks_out, hipStream_t s) {
-  if (!a.A || !a.B || !a.d || !a.idx || !a.partials || a.n < 0 || a.J < 1 || a.J > kLsBatch)
+  if (!a.A || !a.B || !a.d || (!a.idx && !a.compact) || !a.partials || a.n < 0 || a.J < 1 || a.J > kLsBatch)
     return hipErrorInvalidValue;
+  if (a.compact && a.C) return hipErrorInvalidValue;
   const int64_t want = (a.n + 255) / 256;
   const int nb = (int)(want < 1 ? 1 : (want < kLsBlocks ? want : kLsBlocks));
   if (blocks_out) *blocks_out = nb;
   return dispatch_est(a.est, [&](auto ec) {
     constexpr int E = decltype(ec)::value;
-    if (a.C) hipLaunchKernelGGL((k_ls_batch<true, E>), dim3(nb), dim3(256), 0, s, a);
-    else hipLaunchKernelGGL((k_ls_batch<false, E>), dim3(nb), dim3(256), 0, s, a);
+    if (a.compact) hipLaunchKernelGGL((k_ls_batch<false, E, true>), dim3(nb), dim3(256), 0, s, a);
+    else if (a.C) hipLaunchKernelGGL((k_ls_batch<true, E, false>), dim3(nb), dim3(256), 0, s, a);
+    else hipLaunchKernelGGL((k_ls_batch<false, E, false>), dim3(nb), dim3(256), 0, s, a);
     return hipGetLastError();
   });
 }

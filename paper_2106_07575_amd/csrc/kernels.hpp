@@ -34,6 +34,12 @@ struct PatArgs {
   const float2* zs_p;
   const float2* zs_q;
   double* zs_part;
+  // n = 128, batched search with the sums formed elsewhere: records of the
+  // per-pattern transposed far field, one per 32-element segment {mask of
+  // the listed elements (d > 0 or NaN), compacted index of the first}; when
+  // set, gstore (GRAD) and far (direction forward) receive only the listed
+  // elements, compacted in ascending element order
+  const uint2* cseg;
 };
 
 // Batched line search over stored far fields: trial j evaluates the
@@ -51,7 +57,8 @@ struct LsArgs {
   const float2* B;
   const float2* C;  // joint mode only (else null)
   const float* d;
-  const int* idx;   // compacted element indices
+  const int* idx;   // compacted element indices (unused when compact)
+  int compact;      // A, B and d hold the listed elements only, compacted
   int64_t n;        // number of listed elements
   int J;            // trials in this pass, 1..kLsBatch
   int est;          // estimator (as PatArgs::est)
@@ -144,7 +151,10 @@ hipError_t launch_ls_batch(const LsArgs& a, int* blocks_out, hipStream_t s);
 // idx = ascending indices e < n with !(d[e] <= 0), count in offsets[blocks]
 // (blocks = ceil(n / kNzChunk); offsets holds blocks + 1 ints, counts
 // blocks ints of scratch).
-hipError_t launch_nz_compact(const float* d, int64_t n, int* counts, int* offsets, int* idx, hipStream_t s);
+// seg (nullable, n a multiple of 32): one {mask, first compacted index}
+// record per 32 elements; dc (nullable): the listed d values, compacted.
+hipError_t launch_nz_compact(const float* d, int64_t n, int* counts, int* offsets, int* idx, uint2* seg,
+                             float* dc, hipStream_t s);
 // Zero-pixel sums of the direction forward: rows of 4 doubles per block.
 int fwd_t_blocks(int N, int K);
 
