@@ -378,8 +378,14 @@ ptyg_status run_grad(const ptyg_dims* dims, const float2* obj, const float2* pro
     TimedLaunch tl(0, s);
     PTYG_HIP(launch_grad(a, lay, &nb, s));
   }
-  if (objective) PTYG_HIP(launch_finalize(a.partials, nb, 2, objective, s));
-  if (gstore && gsum) PTYG_HIP(launch_finalize(a.zs_part, nb, 1, gsum, s));
+  {
+    // (phi, f) and, for the batched search, sum |G psi|^2: one launch
+    FinJob jobs[2];
+    int nj = 0;
+    if (objective) jobs[nj++] = FinJob{a.partials, nb, 2, objective};
+    if (gstore && gsum) jobs[nj++] = FinJob{a.zs_part, nb, 1, gsum};
+    if (nj) PTYG_HIP(launch_finalize2(jobs[0], jobs[nj - 1], nj, s));
+  }
   {
     TimedLaunch tl(3, s);
     PTYG_HIP(launch_tile_sum(a.ubuf, a.premul ? nullptr : probe, pos, at<int>(ws, L.toff), at<int>(ws, L.tlist),
@@ -577,8 +583,11 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
       v.zs_part = at<double>(ws, L.zparts) + L.n_partials;
     }
     PTYG_HIP(launch_dir(v, s));
-    PTYG_HIP(launch_finalize(partials, nvb_o, 2, sc + N3O, s));
-    if (illum) PTYG_HIP(launch_finalize(v.zs_part, nvb_o, 4, at<double>(ws, L.zsums) + 4, s));
+    {
+      const FinJob a{partials, nvb_o, 2, sc + N3O};
+      const FinJob b{v.zs_part, nvb_o, 4, at<double>(ws, L.zsums) + 4};
+      PTYG_HIP(launch_finalize2(a, b, illum ? 2 : 1, s));
+    }
     if (joint) {
       VecArgs vp{};
       vp.n = pn;

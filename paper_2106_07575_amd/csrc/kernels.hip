@@ -1185,22 +1185,50 @@ __global__ void k_shift_views(const int2* pos, int k, int views, int rows_per_vi
 }
 
 // In-order reduction of `count` rows of `width` (<= 4) doubles, one workgroup.
-__global__ __launch_bounds__(256) void k_finalize(const double* partials, int count, int width, double* out) {
-  __shared__ double red[256 * 4];
+// Ordered sum of per-block partial rows: each thread adds a contiguous run of
+// rows in order (four rows loaded ahead of their adds), then a fixed tree.
+template <int W>
+__device__ __forceinline__ void finalize_rows(const FinJob& j, double* red) {
   double acc[4] = {0.0, 0.0, 0.0, 0.0};
-  // contiguous chunk per thread keeps the order fixed
-  const int per = (count + 255) / 256;
-  const int lo = threadIdx.x * per, hi = min(count, lo + per);
-  for (int i = lo; i < hi; ++i)
-    for (int j = 0; j < width; ++j) acc[j] += partials[(size_t)i * width + j];
-  for (int j = 0; j < 4; ++j) red[threadIdx.x * 4 + j] = acc[j];
+  const int per = (j.count + 255) / 256;
+  const int lo = threadIdx.x * per, hi = min(j.count, lo + per);
+  int i = lo;
+  for (; i + 4 <= hi; i += 4) {
+    double r[4][W];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < W; ++c) r[q][c] = j.p[(size_t)(i + q) * W + c];
+#pragma unroll
+    for (int q = 0; q < 4; ++q)
+#pragma unroll
+      for (int c = 0; c < W; ++c) acc[c] += r[q][c];
+  }
+  for (; i < hi; ++i)
+#pragma unroll
+    for (int c = 0; c < W; ++c) acc[c] += j.p[(size_t)i * W + c];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) red[threadIdx.x * 4 + c] = acc[c];
   __syncthreads();
   for (int off = 128; off > 0; off >>= 1) {
     if (threadIdx.x < off)
-      for (int j = 0; j < 4; ++j) red[threadIdx.x * 4 + j] += red[(threadIdx.x + off) * 4 + j];
+#pragma unroll
+      for (int c = 0; c < 4; ++c) red[threadIdx.x * 4 + c] += red[(threadIdx.x + off) * 4 + c];
     __syncthreads();
   }
-  if (threadIdx.x < width) out[threadIdx.x] = red[threadIdx.x];
+  if (threadIdx.x < W) j.out[threadIdx.x] = red[threadIdx.x];
+}
+
+// Workgroup b finalizes job b (one or two independent reductions per launch).
+__global__ __launch_bounds__(256) void k_finalize(FinJob a, FinJob b) {
+  __shared__ double red[256 * 4];
+  const FinJob j = blockIdx.x == 0 ? a : b;
+  switch (j.width) {
+    case 1: finalize_rows<1>(j, red); break;
+    case 2: finalize_rows<2>(j, red); break;
+    case 3: finalize_rows<3>(j, red); break;
+    default: finalize_rows<4>(j, red); break;
+  }
 }
 
 template <int N>
@@ -1591,7 +1619,17 @@ hipError_t launch_dy_beta(double* sc, int n1, int n2, int n3, int joint_off, int
 }
 
 hipError_t launch_finalize(const double* partials, int count, int width, double* out, hipStream_t s) {
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(256), 0, s, partials, count, width, out);
+  const FinJob j{partials, count, width, out};
+  return launch_finalize2(j, j, 1, s);
+}
+
+hipError_t launch_finalize2(const FinJob& a, const FinJob& b, int jobs, hipStream_t s) {
+  for (int i = 0; i < jobs; ++i) {
+    const FinJob& j = i == 0 ? a : b;
+    if (!j.p || !j.out || j.count < 1 || j.width < 1 || j.width > 4) return hipErrorInvalidValue;
+  }
+  if (jobs < 1 || jobs > 2) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_finalize, dim3(jobs), dim3(256), 0, s, a, b);
   return hipGetLastError();
 }
 

@@ -116,7 +116,7 @@ hipError_t launch_grad256(const PatArgs& a, DataLayout lay, int* blocks_out, hip
 hipError_t launch_minfunc256(const PatArgs& a, DataLayout lay, int* blocks_out, hipStream_t s);
 
 // Object tiles of the deterministic scatter: kTileH x kTileW pixels.
-constexpr int kTileH = 32, kTileW = 64;
+constexpr int kTileH = 16, kTileW = 64;
 __host__ __device__ inline int tiles_x(int W) { return (W + kTileW - 1) / kTileW; }
 __host__ __device__ inline int tiles_y(int H) { return (H + kTileH - 1) / kTileH; }
 // Upper bound of tiles one n x n patch overlaps.
@@ -217,5 +217,12 @@ hipError_t launch_dy_beta(double* sc, int n1, int n2, int n3, int joint_off, int
 hipError_t launch_sum_copies(const float2* src, int copies, int64_t n, float2* out, hipStream_t s);
 // out[0..width) = in-order sums of `count` rows of `width` doubles
 hipError_t launch_finalize(const double* partials, int count, int width, double* out, hipStream_t s);
+// One or two independent finalizations in one launch (jobs = 1 or 2).
+struct FinJob {
+  const double* p;  // [count][width] partial rows
+  int count, width;  // width 1..4
+  double* out;       // [width]
+};
+hipError_t launch_finalize2(const FinJob& a, const FinJob& b, int jobs, hipStream_t s);
 
 }  // namespace ptyg

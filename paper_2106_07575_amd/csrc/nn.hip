@@ -540,14 +540,17 @@ __global__ void k_sync_step(const double2* c, const int* cnt, const int* nb, int
 __global__ __launch_bounds__(256) void k_stitch(const float2* P, const double2* z, const int2* wpos,
                                                 const int* offsets, const int* list, int H, int W, int q,
                                                 float2* psi0) {
-  const int ntx = (W + 63) / 64;
+  // object tiles of the solver's tile lists: kTileH x kTileW, lane column x,
+  // rows yb + 4 i
+  constexpr int R = kTileH / 4;
+  const int ntx = tiles_x(W);
   const int t = blockIdx.x;
-  const int x = (t % ntx) * 64 + (threadIdx.x & 63);
-  const int yb = (t / ntx) * 32 + (threadIdx.x >> 6);
-  float2 acc[8];
-  int n[8];
+  const int x = (t % ntx) * kTileW + (threadIdx.x & 63);
+  const int yb = (t / ntx) * kTileH + (threadIdx.x >> 6);
+  float2 acc[R];
+  int n[R];
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
+  for (int i = 0; i < R; ++i) {
     acc[i] = make_float2(0.f, 0.f);
     n[i] = 0;
   }
@@ -558,7 +561,7 @@ __global__ __launch_bounds__(256) void k_stitch(const float2* P, const double2* 
     if ((unsigned)xx >= (unsigned)q) continue;
     const float2 zk = make_float2((float)z[k].x, (float)z[k].y);
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < R; ++i) {
       const int yy = yb + 4 * i - rc.x;
       if ((unsigned)yy < (unsigned)q) {
         acc[i] = cadd(acc[i], cmul(zk, P[(size_t)k * q * q + yy * q + xx]));
@@ -568,7 +571,7 @@ __global__ __launch_bounds__(256) void k_stitch(const float2* P, const double2* 
   }
   if (x >= W) return;
 #pragma unroll
-  for (int i = 0; i < 8; ++i) {
+  for (int i = 0; i < R; ++i) {
     const int y = yb + 4 * i;
     if (y < H) psi0[(size_t)y * W + x] = n[i] ? cscale(acc[i], 1.0f / n[i]) : make_float2(1.f, 0.f);
   }
@@ -606,20 +609,23 @@ __global__ void k_stitch_adj(const float2* g, const float* out, const double2* z
 // count[y][x] = number of windows covering the pixel
 __global__ void k_cover_count(const int2* wpos, int K, int H, int W, int q, const int* offsets, const int* list,
                               int* count) {
-  const int ntx = (W + 63) / 64;
+  constexpr int R = kTileH / 4;
+  const int ntx = tiles_x(W);
   const int t = blockIdx.x;
-  const int x = (t % ntx) * 64 + (threadIdx.x & 63);
-  const int yb = (t / ntx) * 32 + (threadIdx.x >> 6);
-  int n[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  const int x = (t % ntx) * kTileW + (threadIdx.x & 63);
+  const int yb = (t / ntx) * kTileH + (threadIdx.x >> 6);
+  int n[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) n[i] = 0;
   for (int e = offsets[t]; e < offsets[t + 1]; ++e) {
     const int2 rc = wpos[list[e]];
     if ((unsigned)(x - rc.y) >= (unsigned)q) continue;
 #pragma unroll
-    for (int i = 0; i < 8; ++i) n[i] += ((unsigned)(yb + 4 * i - rc.x) < (unsigned)q) ? 1 : 0;
+    for (int i = 0; i < R; ++i) n[i] += ((unsigned)(yb + 4 * i - rc.x) < (unsigned)q) ? 1 : 0;
   }
   if (x >= W) return;
 #pragma unroll
-  for (int i = 0; i < 8; ++i)
+  for (int i = 0; i < R; ++i)
     if (yb + 4 * i < H) count[(size_t)(yb + 4 * i) * W + x] = n[i];
 }
 
@@ -863,7 +869,7 @@ int32_t ptyg_ws_phase_sync(const void* patches, const int32_t* wpos, int32_t K, 
 int32_t ptyg_ws_stitch(const void* patches, const void* z, const int32_t* wpos, const int32_t* offsets,
                        const int32_t* list, int32_t H, int32_t W, int32_t q, void* psi0, void* stream) {
   if (!patches || !z || !wpos || !offsets || !list || !psi0) return nn_fail("NULL argument");
-  const int T = ((W + 63) / 64) * ((H + 31) / 32);
+  const int T = tiles_x(W) * tiles_y(H);
   hipLaunchKernelGGL(k_stitch, dim3(T), dim3(256), 0, SS(stream), static_cast<const float2*>(patches),
                      static_cast<const double2*>(z), reinterpret_cast<const int2*>(wpos), offsets, list, H, W, q,
                      static_cast<float2*>(psi0));
@@ -874,7 +880,7 @@ int32_t ptyg_ws_stitch(const void* patches, const void* z, const int32_t* wpos, 
 int32_t ptyg_ws_cover_count(const int32_t* wpos, int32_t K, int32_t H, int32_t W, int32_t q, const int32_t* offsets,
                             const int32_t* list, int32_t* count, void* stream) {
   if (!wpos || !offsets || !list || !count) return nn_fail("NULL argument");
-  const int T = ((W + 63) / 64) * ((H + 31) / 32);
+  const int T = tiles_x(W) * tiles_y(H);
   hipLaunchKernelGGL(k_cover_count, dim3(T), dim3(256), 0, SS(stream), reinterpret_cast<const int2*>(wpos), K, H, W,
                      q, offsets, list, count);
   NN_HIP(hipGetLastError());
