@@ -36,14 +36,27 @@ if ROOT not in sys.path:
 #         B 8 B + intensity 4 B
 #   direction forward: eta patch 8 B + far field 8 B + stored A read 8 B
 #   overlap sum: back-propagated waves 8 B per pixel + object gradient write
-def kernel_bytes(kind: str, cfg, batched: bool, nnz: int) -> int:
+def kernel_bytes(kind: str, cfg, batched: bool, nnz: int, joint: bool = False) -> int:
+    """Algorithmic bytes per launch: 20 B per pattern pixel for GRAD (patch,
+    intensity, gradient contribution) plus the far field it stores for the
+    batched search, 8 B per stored value; far fields stored for the listed
+    elements only (object-only search at n = 128) add 8 B per listed element
+    and an 8-byte record per 32 elements."""
     px = cfg.k * cfg.n * cfg.n
+    compact = batched and not joint and cfg.n == 128
+    stored = 8 * nnz + px // 4 if compact else 8 * px
     if kind == "grad":
-        return (28 if batched else 20) * px
+        return 20 * px + (stored if batched else 0)
     if kind == "minfunc":
-        return 24 * nnz if batched else 20 * px
+        if not batched:
+            return 20 * px
+        # A, B (and C) and d per listed element, plus its index unless compacted
+        return (20 if compact else 24 + (8 if joint else 0)) * nnz
     if kind == "dir_forward":
-        return 24 * px
+        if joint:
+            # (psi, eta patches, a read, b stored) then (eta patch, a and b read, c stored)
+            return 64 * px
+        return 8 * px + stored
     if kind == "tile_sum":
         return 8 * px + 8 * cfg.obj_h * cfg.obj_w
     raise KeyError(kind)
@@ -55,14 +68,13 @@ KERNEL_NAMES = {"grad": "k_grad (fused GRAD)", "minfunc": "k_minfunc (line-searc
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch (FETCH_SIZE x 2 + WRITE_SIZE x 1, the factors from a
 # 512 MiB device copy measured by the same counters) of the current kernels,
-# from the rocprofv3 --pmc runs summarised in
-# profiles/cg_c2_batched_ls_hbm_bytes.md; keyed (kind, workload, line search);
-# absent = not measured for that kernel build
+# from the rocprofv3 --pmc runs summarised in profiles/; keyed (kind,
+# workload, line search); absent = not measured for the current kernel build
 TRAFFIC_BYTES = {
-    ("grad", "c2", "batched"): 1539236164,
-    ("dir_forward", "c2", "batched"): 1195023212,
-    ("tile_sum", "c2", "batched"): 707885457,
-    ("ls_batched", "c2", "batched"): 402561581,
+    ("grad", "c2", "batched"): 1020147849,
+    ("dir_forward", "c2", "batched"): 113390496,
+    ("tile_sum", "c2", "batched"): 706655013,
+    ("ls_batched", "c2", "batched"): 157930441,
 }
 FP32_PEAK_TFLOPS = 157.3
 
@@ -298,9 +310,9 @@ def main():
                 name = "ls_batched" if (kind == "minfunc" and batched) else kind
                 avg_s = ms / cnt / 1e3
                 ffts = {"grad": 2, "minfunc": 1, "dir_forward": 1 + int(joint), "ls_batched": 0, "tile_sum": 0}[name]
+                kb = kernel_bytes(kind, cfg, batched, nnz, joint)
                 kinds[name] = {"kind": kind, "launches": cnt, "avg_us": avg_s * 1e6, "total_ms": ms,
-                               "bytes_per_launch": kernel_bytes(kind, cfg, batched, nnz),
-                               "alg_GBs": kernel_bytes(kind, cfg, batched, nnz) / avg_s / 1e9,
+                               "bytes_per_launch": kb, "alg_GBs": kb / avg_s / 1e9,
                                "fft_TFLOPs": ffts * K * fft_flops(cfg.n) / avg_s / 1e12}
         return kinds
 
