@@ -54,8 +54,8 @@ def kernel_bytes(kind: str, cfg, batched: bool, nnz: int, joint: bool = False) -
         return (20 if compact else 24 + (8 if joint else 0)) * nnz
     if kind == "dir_forward":
         if joint:
-            # (psi, eta patches, a read, b stored) then (eta patch, a and b read, c stored)
-            return 64 * px
+            # (psi and eta patches, b stored) then (eta patch, c stored)
+            return 40 * px
         return 8 * px + stored
     if kind == "tile_sum":
         return 8 * px + 8 * cfg.obj_h * cfg.obj_w

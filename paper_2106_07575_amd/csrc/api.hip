@@ -126,10 +126,11 @@ Layout layout(const ptyg_dims* d, bool joint, bool batched = false, bool views =
     L.nz_idx = o;
     o = align_up(o + elems * sizeof(int));
     // GRAD sums of |G psi|^2 (one per block), then the rows of the direction
-    // sums (the direction forward passes' or, object only, the DIR kernel's)
+    // sums (object only the DIR kernel's, joint the patch sums')
     L.zparts = o;
-    o = align_up(o + (L.n_partials + std::max<size_t>(2 * L.z_blocks, (size_t)vec_blocks((int64_t)obj_n)) * 4) *
-                         sizeof(double));
+    const size_t rows = std::max<size_t>({2 * L.z_blocks, (size_t)vec_blocks((int64_t)obj_n),
+                                          2 * (size_t)patch_sums_blocks(d->k, d->n)});
+    o = align_up(o + (L.n_partials + rows * 4) * sizeof(double));
     L.zsums = L.scalars + kZsSlot * sizeof(double);
     const size_t far_bytes = (size_t)d->k * probe_n * sizeof(float2);
     L.far_a = o;
@@ -627,10 +628,6 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
       fa.cseg = cseg;
       double* zparts = at<double>(ws, L.zparts) + L.n_partials;
       double* zsums = at<double>(ws, L.zsums);
-      if (joint) {
-        fa.zs_p = far_a;  // sums (Re a b*, 0, |b|^2, 0)
-        fa.zs_part = zparts;
-      }
       {
         TimedLaunch tl_fwd(2, s);
         if (!joint) {
@@ -643,20 +640,23 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
           fa.probe = probe;
           fa.dprobe = eta_p;
           PTYG_HIP(launch_fwd_t(fa, true, s));
-          PatArgs fc = fa;  // (Re a c*, Re b c*, |c|^2, 0)
+          PatArgs fc = fa;
           fc.far = far_c;
           fc.obj = eta_o;
           fc.probe = eta_p;
           fc.dobj = nullptr;
           fc.dprobe = nullptr;
-          fc.zs_q = far_b;
-          fc.zs_part = zparts + 4 * L.z_blocks;
           PTYG_HIP(launch_fwd_t(fc, false, s));
         }
       }
       if (joint) {
-        PTYG_HIP(launch_finalize(zparts, (int)L.z_blocks, 4, zsums + 4, s));
-        PTYG_HIP(launch_finalize(zparts + 4 * L.z_blocks, (int)L.z_blocks, 4, zsums + 8, s));
+        // the polynomial's coefficients over the patches (Parseval): rows
+        // (Re a b*, 0, |b|^2, 0) and (Re a c*, Re b c*, |c|^2, 0)
+        const int psb = patch_sums_blocks(dims->k, dims->n);
+        PTYG_HIP(launch_patch_sums(obj, eta_o, probe, eta_p, pos, dims->k, dims->obj_w, dims->n, zparts,
+                                   zparts + 4 * psb, s));
+        PTYG_HIP(launch_finalize2(FinJob{zparts, psb, 4, zsums + 4}, FinJob{zparts + 4 * psb, psb, 4, zsums + 8}, 2,
+                                  s));
       }
       LsArgs la{};
       la.A = far_a;

@@ -991,6 +991,49 @@ __global__ __launch_bounds__(256) void k_nz_fill(const float* __restrict__ d, in
   }
 }
 
+// Joint-mode coefficients of the batched search in the pattern domain: with
+// a' = p psi_k, b' = p eta_k + eta_p psi_k, c' = eta_p eta_k on every patch
+// pixel, the unitary transform keeps the inner products, so the sums of
+// Re(a b*), |b|^2, Re(a c*), Re(b c*), |c|^2 over the far fields equal the
+// same sums over the patches.  Rows of 4 per block in two arrays:
+// (Re a'b'*, 0, |b'|^2, 0) and (Re a'c'*, Re b'c'*, |c'|^2, 0); blocks walk
+// 4096-pixel chunks in a fixed order.
+constexpr int kPsChunk = 4096;
+constexpr int kPsMaxBlocks = 8192;
+
+__global__ __launch_bounds__(256) void k_patch_sums(const float2* __restrict__ obj, const float2* __restrict__ eta,
+                                                     const float2* __restrict__ probe,
+                                                     const float2* __restrict__ eta_p, const int2* __restrict__ pos,
+                                                     int K, int W, int lgN, double* __restrict__ parts1,
+                                                     double* __restrict__ parts2) {
+  __shared__ double red1[4 * 4], red2[4 * 4];
+  const int N = 1 << lgN;
+  const int nn = N * N;
+  const int cpp = (nn + kPsChunk - 1) / kPsChunk;
+  const int64_t chunks = (int64_t)K * cpp;
+  double z1[4] = {0.0, 0.0, 0.0, 0.0}, z2[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t c = blockIdx.x; c < chunks; c += gridDim.x) {
+    const int k = (int)(c / cpp);
+    const int base = (int)(c % cpp) * kPsChunk;
+    const int lim = min(kPsChunk, nn - base);
+    const int2 rc = pos[k];
+    for (int i = threadIdx.x; i < lim; i += 256) {
+      const int px = base + i;
+      const int u = px >> lgN, v = px & (N - 1);
+      const size_t o = (size_t)(rc.x + u) * W + rc.y + v;
+      const float2 x = obj[o], y = eta[o], p = probe[px], q = eta_p[px];
+      const float2 a = cmul(p, x), b = cadd(cmul(p, y), cmul(q, x)), cc = cmul(q, y);
+      z1[0] += (double)a.x * b.x + (double)a.y * b.y;
+      z1[2] += (double)b.x * b.x + (double)b.y * b.y;
+      z2[0] += (double)a.x * cc.x + (double)a.y * cc.y;
+      z2[1] += (double)b.x * cc.x + (double)b.y * cc.y;
+      z2[2] += (double)cc.x * cc.x + (double)cc.y * cc.y;
+    }
+  }
+  block_sum4_store<256>(z1, red1, parts1 + 4 * blockIdx.x);
+  block_sum4_store<256>(z2, red2, parts2 + 4 * blockIdx.x);
+}
+
 // out[j] = sum over rows (in order) of partials[row][j]; one workgroup per j.
 __global__ __launch_bounds__(256) void k_ls_finalize(const double* partials, int count, double* out) {
   __shared__ double red[256];
@@ -1361,6 +1404,22 @@ hipError_t launch_ls_batch(const LsArgs& a, int* blocks_out, hipStream_t s) {
     else hipLaunchKernelGGL((k_ls_batch<false, E, false>), dim3(nb), dim3(256), 0, s, a);
     return hipGetLastError();
   });
+}
+
+int patch_sums_blocks(int K, int N) {
+  const int64_t chunks = (int64_t)K * ((N * N + kPsChunk - 1) / kPsChunk);
+  return (int)(chunks < kPsMaxBlocks ? chunks : kPsMaxBlocks);
+}
+
+hipError_t launch_patch_sums(const float2* obj, const float2* eta, const float2* probe, const float2* eta_p,
+                             const int2* pos, int K, int W, int N, double* parts1, double* parts2, hipStream_t s) {
+  if (!obj || !eta || !probe || !eta_p || !pos || !parts1 || !parts2 || K < 1 || N < 1 || (N & (N - 1)))
+    return hipErrorInvalidValue;
+  int lg = 0;
+  while ((1 << lg) < N) ++lg;
+  hipLaunchKernelGGL(k_patch_sums, dim3(patch_sums_blocks(K, N)), dim3(256), 0, s, obj, eta, probe, eta_p, pos, K,
+                     W, lg, parts1, parts2);
+  return hipGetLastError();
 }
 
 hipError_t launch_ls_finalize(const double* partials, int count, double* out, hipStream_t s) {

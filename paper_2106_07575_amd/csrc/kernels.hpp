@@ -148,6 +148,13 @@ hipError_t launch_fwd_t256(const PatArgs& a, bool lin, hipStream_t s);
 int fwd_t256_blocks(int K);
 // Objective partials of a.J trials; `blocks_out` rows of kLsRow doubles.
 hipError_t launch_ls_batch(const LsArgs& a, int* blocks_out, hipStream_t s);
+// Joint-mode search coefficients over the patches (a' = p psi_k,
+// b' = p eta_k + eta_p psi_k, c' = eta_p eta_k): rows of 4 per block,
+// parts1 (Re a'b'*, 0, |b'|^2, 0), parts2 (Re a'c'*, Re b'c'*, |c'|^2, 0);
+// patch_sums_blocks rows each.  N a power of two.
+int patch_sums_blocks(int K, int N);
+hipError_t launch_patch_sums(const float2* obj, const float2* eta, const float2* probe, const float2* eta_p,
+                             const int2* pos, int K, int W, int N, double* parts1, double* parts2, hipStream_t s);
 // idx = ascending indices e < n with !(d[e] <= 0), count in offsets[blocks]
 // (blocks = ceil(n / kNzChunk); offsets holds blocks + 1 ints, counts
 // blocks ints of scratch).
