@@ -89,7 +89,7 @@ def test_batched_object_within_fp32_floor(P, case, iters):
     assert e_gpu <= 1.25 * e_ora
 
 
-@pytest.mark.parametrize("case", ["m32", "m128"])
+@pytest.mark.parametrize("case", ["m32", "m64", "m128"])
 def test_batched_equals_sequential_steps(P, case):
     """Same workload, both GPU searches: identical step sequences over the
     first iterations (before FP32 chaos can separate the trajectories)."""
@@ -135,6 +135,21 @@ def test_batched_joint_probe(P):
     assert ep <= max(1e-3, FLOOR_FACTOR * fp)
 
 
+def test_batched_joint_probe_128(P):
+    """n = 128 joint: full far fields, coefficients over the patches."""
+    cfg, inp, probe, obj, data = workload("m128")
+    rng = np.random.default_rng(4)
+    p0 = (probe * (1 + 0.05 * rng.standard_normal(probe.shape))).astype(np.complex64)
+    res, (ro, rp, rtr), (po, pp, ptr), mask = run(P, "m128", 4, probe0=p0, update_probe=True)
+    eo = rel(res.obj.cpu().numpy()[mask], ro[mask])
+    ep = rel(res.probe.cpu().numpy(), rp)
+    fo, fp = rel(po[mask], ro[mask]), rel(pp, rp)
+    print(f"joint 128: object rel {eo:.2e} (floor {fo:.2e}) probe rel {ep:.2e} (floor {fp:.2e})")
+    assert gammas(res.trace) == gammas(rtr)
+    assert eo <= max(1e-3, FLOOR_FACTOR * fo)
+    assert ep <= max(1e-3, FLOOR_FACTOR * fp)
+
+
 def test_batched_joint_probe_256(P):
     cfg, inp, probe, obj, data = workload("m256")
     rng = np.random.default_rng(3)
@@ -169,10 +184,12 @@ def test_batched_needs_its_workspace(P):
     assert e.value.status == -5
 
 
-def test_batched_all_zero_intensities(P):
-    """d = 0 everywhere: no element is listed for the per-trial pass and every
-    trial's objective comes from the zero-pixel polynomial."""
-    cfg, inp, probe, obj, data = workload("m32")
+@pytest.mark.parametrize("case", ["m32", "m128"])
+def test_batched_all_zero_intensities(P, case):
+    """d = 0 everywhere: no element is listed for the per-trial pass (at
+    n = 128 nothing is stored compacted) and every trial's objective comes
+    from the zero-pixel polynomial."""
+    cfg, inp, probe, obj, data = workload(case)
     zero = np.zeros_like(data)
     o0 = np.ones(obj.shape, np.complex64)
     res = P.cg_solve(dev(o0), dev(probe), dev(inp.pos), dev(zero), 3, line_search=B)
