@@ -76,11 +76,15 @@ int32_t ptyg_nn_adam(float* w, const float* g, float* m, float* v, int64_t n, fl
  * blind to a constant phase of its patch, so the windows' phases are first
  * synchronised: z = leading eigenvector (power iteration, unit-modulus
  * entries) of the overlap matrix c_kj = sum_overlap conj(P_k) P_j. */
-/* Per-tile lists (32 x 64 tiles, ascending window order) of the q x q windows at wpos:
- * offsets int32[tiles + 1], tiles = ceil(H/32) * ceil(W/64); list int32[capacity]. */
+/* Per-tile lists (the solver's object tiles, ascending window order) of the
+ * q x q windows at wpos: offsets int32[ptyg_ws_tile_count(H, W) + 1], list
+ * int32[ptyg_ws_tile_list_capacity(K, H, W, q)]; offsets_len and list_len
+ * give the caller's buffer lengths in elements, and buffers shorter than
+ * those sizes are rejected (nothing is written).  Host functions, no GPU. */
+int64_t ptyg_ws_tile_count(int32_t H, int32_t W);
 int64_t ptyg_ws_tile_list_capacity(int32_t K, int32_t H, int32_t W, int32_t q);
 int32_t ptyg_ws_tile_lists(const int32_t* wpos, int32_t K, int32_t H, int32_t W, int32_t q, int32_t* offsets,
-                           int32_t* list, void* stream);
+                           int64_t offsets_len, int32_t* list, int64_t list_len, void* stream);
 /* patches [npx] complex64 = amp e^{i phase} from the network output fp32 [npx][8]. */
 int32_t ptyg_ws_patches(const float* out, int64_t npx, void* patches, void* stream);
 /* out[k] = pos[k] + (off, off). */

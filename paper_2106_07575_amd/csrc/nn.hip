@@ -817,6 +817,11 @@ int32_t ptyg_nn_adam(float* w, const float* g, float* m, float* v, int64_t n, fl
   return 0;
 }
 
+int64_t ptyg_ws_tile_count(int32_t H, int32_t W) {
+  if (H < 1 || W < 1) return 0;
+  return (int64_t)tiles_x(W) * tiles_y(H);
+}
+
 int64_t ptyg_ws_tile_list_capacity(int32_t K, int32_t H, int32_t W, int32_t q) {
   const int64_t T = (int64_t)tiles_x(W) * tiles_y(H);
   const int64_t per = (int64_t)((q - 1) / kTileH + 2) * ((q - 1) / kTileW + 2);
@@ -824,8 +829,10 @@ int64_t ptyg_ws_tile_list_capacity(int32_t K, int32_t H, int32_t W, int32_t q) {
 }
 
 int32_t ptyg_ws_tile_lists(const int32_t* wpos, int32_t K, int32_t H, int32_t W, int32_t q, int32_t* offsets,
-                           int32_t* list, void* stream) {
-  if (!wpos || !offsets || !list || K < 1 || q < 1) return nn_fail("bad arguments");
+                           int64_t offsets_len, int32_t* list, int64_t list_len, void* stream) {
+  if (!wpos || !offsets || !list || K < 1 || q < 1 || H < 1 || W < 1) return nn_fail("bad arguments");
+  if (offsets_len < ptyg_ws_tile_count(H, W) + 1) return nn_fail("offsets buffer too short");
+  if (list_len < ptyg_ws_tile_list_capacity(K, H, W, q)) return nn_fail("list buffer too short");
   NN_HIP(launch_tile_lists(reinterpret_cast<const int2*>(wpos), K, H, W, q, offsets, list, SS(stream)));
   return 0;
 }

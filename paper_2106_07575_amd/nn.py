@@ -27,7 +27,8 @@ _SIGS = {
     "ptyg_nn_mse": (_I, [_P, _P, _L, _P, _P, _I, _P]),
     "ptyg_nn_adam": (_I, [_P, _P, _P, _P, _L, _F, _F, _F, _F, _I, _P]),
     "ptyg_ws_tile_list_capacity": (_L, [_I, _I, _I, _I]),
-    "ptyg_ws_tile_lists": (_I, [_P, _I, _I, _I, _I, _P, _P, _P]),
+    "ptyg_ws_tile_count": (_L, [_I, _I]),
+    "ptyg_ws_tile_lists": (_I, [_P, _I, _I, _I, _I, _P, _L, _P, _L, _P]),
     "ptyg_ws_patches": (_I, [_P, _L, _P, _P]),
     "ptyg_ws_shift_positions": (_I, [_P, _I, _I, _P, _P]),
     "ptyg_ws_phase_sync": (_I, [_P, _P, _I, _I, _I, _I, _P, _P, _P, _P, _P, _P]),
@@ -124,10 +125,10 @@ def adam(w, g, m, v, lr, step, b1=0.9, b2=0.999, eps=1e-8):
 def tile_lists(wpos, H, W, q):
     """(offsets, list) int32 device tensors of the windows' tile lists."""
     K = wpos.shape[0]
-    T = ((W + 63) // 64) * ((H + 31) // 32)
+    T = int(lib().ptyg_ws_tile_count(H, W))
     offsets = torch.empty(T + 1, dtype=torch.int32, device=wpos.device)
     lst = torch.empty(int(lib().ptyg_ws_tile_list_capacity(K, H, W, q)), dtype=torch.int32, device=wpos.device)
-    _ck(lib().ptyg_ws_tile_lists(_p(wpos), K, H, W, q, _p(offsets), _p(lst), _s()))
+    _ck(lib().ptyg_ws_tile_lists(_p(wpos), K, H, W, q, _p(offsets), offsets.numel(), _p(lst), lst.numel(), _s()))
     return offsets, lst
 
 

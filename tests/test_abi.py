@@ -69,3 +69,28 @@ def test_nn_library_exports():
     assert nn.weight_sizes(1, 32) == (32 * 96, 8 * 288)
     with pytest.raises(RuntimeError):
         nn.weight_sizes(0, 32)
+
+
+def test_tile_list_buffers_are_length_checked():
+    """The stitch's tile lists: buffer sizes come from the library, and short
+    buffers are rejected before anything is launched (host-only calls)."""
+    from paper_2106_07575_amd import ptyg
+    if not os.path.exists(ptyg.lib_path()):
+        pytest.skip("libptyg.so not built")
+    lib = ctypes.CDLL(ptyg.lib_path())
+    lib.ptyg_ws_tile_count.restype = ctypes.c_int64
+    lib.ptyg_ws_tile_count.argtypes = [ctypes.c_int32, ctypes.c_int32]
+    lib.ptyg_ws_tile_list_capacity.restype = ctypes.c_int64
+    lib.ptyg_ws_tile_list_capacity.argtypes = [ctypes.c_int32] * 4
+    lib.ptyg_ws_tile_lists.restype = ctypes.c_int32
+    lib.ptyg_ws_tile_lists.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                       ctypes.c_int32, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                       ctypes.c_int64, ctypes.c_void_p]
+    T = lib.ptyg_ws_tile_count(2048, 2048)
+    assert T > 0 and lib.ptyg_ws_tile_count(2048, 4096) == 2 * T
+    cap = lib.ptyg_ws_tile_list_capacity(4096, 2048, 2048, 64)
+    assert cap >= T
+    dummy = ctypes.create_string_buffer(16)
+    p = ctypes.cast(dummy, ctypes.c_void_p)
+    assert lib.ptyg_ws_tile_lists(p, 4096, 2048, 2048, 64, p, T, p, cap, None) != 0
+    assert lib.ptyg_ws_tile_lists(p, 4096, 2048, 2048, 64, p, T + 1, p, cap - 1, None) != 0

@@ -238,6 +238,32 @@ def stitch_reference(P, z, wpos, H, W, q):
     return out, cnt
 
 
+def test_stitch_tile_lists_at_object_scale(NN):
+    """Stitch and cover count of 400 windows on a ~1000^2 object (thousands
+    of tiles): the tile lists are sized by the library and built at the
+    scale of a training object; the phases are given, not synchronised."""
+    rng = np.random.default_rng(11)
+    wpos, H, W = _grid_positions(20, 48, 64)
+    q = 64
+    K = len(wpos)
+    T = _smooth_field(rng, H, W)
+    theta = rng.uniform(-np.pi, np.pi, K)
+    P = np.stack([T[r:r + q, c:c + q] * np.exp(-1j * theta[k]) for k, (r, c) in enumerate(wpos)])
+    Pd = torch.from_numpy(P.astype(np.complex64)).cuda()
+    wposd = torch.from_numpy(wpos).cuda()
+    offsets, lst = NN.tile_lists(wposd, H, W, q)
+    assert offsets.numel() == NN.lib().ptyg_ws_tile_count(H, W) + 1
+    z = np.exp(1j * theta)
+    zd = torch.from_numpy(np.stack([z.real, z.imag], 1)).cuda()
+    psi0 = torch.empty((H, W), dtype=torch.complex64, device="cuda")
+    NN.stitch(Pd, zd, wposd, offsets, lst, H, W, q, psi0)
+    ref, cnt = stitch_reference(P.astype(np.complex64).astype(np.complex128), z, wpos, H, W, q)
+    assert np.abs(psi0.cpu().numpy() - ref).max() <= 1e-5
+    count = torch.empty((H, W), dtype=torch.int32, device="cuda")
+    NN.cover_count(wposd, H, W, q, offsets, lst, count)
+    assert np.array_equal(count.cpu().numpy(), cnt)
+
+
 @pytest.mark.parametrize("K_side,step,q", [(6, 20, 32), (9, 24, 64)])
 def test_phase_sync_and_stitch(NN, K_side, step, q):
     rng = np.random.default_rng(K_side)
