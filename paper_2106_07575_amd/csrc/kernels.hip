@@ -128,19 +128,37 @@ __device__ __forceinline__ void gather_exit_wave(float2* v, const PatArgs& a, co
       }
     }
   }
+  // probe (and probe direction) values one chunk ahead of their multiplies
   const uint32_t plo = lane_off<N>(L, N);
+  constexpr int DP = LINC_P ? kChunk : 1;
+  float2 pn[kChunk], dn[DP];
+#pragma unroll
+  for (int j = 0; j < kChunk; ++j) {
+    pn[j] = (a.probe + j * T * N)[plo];
+    if constexpr (LINC_P) dn[j] = (a.dprobe + j * T * N)[plo];
+  }
 #pragma unroll
   for (int c = 0; c < G::E; c += kChunk) {
     __builtin_amdgcn_sched_barrier(0);
+    float2 pc[kChunk], dc[DP];
 #pragma unroll
-    for (int m = c; m < c + kChunk; ++m) {
-      float2 p = (a.probe + m * T * N)[plo];
-      if constexpr (LINC_P) {
-        const float2 dp = (a.dprobe + m * T * N)[plo];
-        p = make_float2(fmaf(a.gamma, dp.x, p.x), fmaf(a.gamma, dp.y, p.y));
+    for (int j = 0; j < kChunk; ++j) {
+      pc[j] = pn[j];
+      if constexpr (LINC_P) dc[j] = dn[j];
+    }
+    if (c + kChunk < G::E) {
+#pragma unroll
+      for (int j = 0; j < kChunk; ++j) {
+        pn[j] = (a.probe + (c + kChunk + j) * T * N)[plo];
+        if constexpr (LINC_P) dn[j] = (a.dprobe + (c + kChunk + j) * T * N)[plo];
       }
+    }
+#pragma unroll
+    for (int j = 0; j < kChunk; ++j) {
+      float2 p = pc[j];
+      if constexpr (LINC_P) p = make_float2(fmaf(a.gamma, dc[j].x, p.x), fmaf(a.gamma, dc[j].y, p.y));
       if (!valid) p = make_float2(0.f, 0.f);
-      v[m] = cmul(p, v[m]);
+      v[c + j] = cmul(p, v[c + j]);
     }
   }
   __builtin_amdgcn_sched_barrier(0);
@@ -409,18 +427,32 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
     }
     __builtin_amdgcn_sched_barrier(0);
   }
+  // intensities one chunk ahead: chunk c + 1's loads are issued before
+  // chunk c's arithmetic, so their latency overlaps it
+  float dn[kResChunk];
 #pragma unroll
-  for (int s = 0; s < G::E; ++s) {
-    if (s % kResChunk == 0) __builtin_amdgcn_sched_barrier(0);
-    const int b = fidx<N>(s, L.h);
-    const float d = load_data<N, LAY>(a.data, k, L, s);
-    const float2 g = SG ? v[s] : cscale(v[s], invN);
-    const float x = fmaf(g.x, g.x, g.y * g.y);
-    float phi, ft, fac;
-    pixel_terms<true, EST>(x, d, a.eps, phi, ft, fac);
-    acc_phi += (double)phi;
-    acc_f += (double)ft;
-    v[s] = cscale(g, fac * invN);
+  for (int j = 0; j < kResChunk; ++j) dn[j] = load_data<N, LAY>(a.data, k, L, j);
+#pragma unroll
+  for (int c = 0; c < G::E; c += kResChunk) {
+    __builtin_amdgcn_sched_barrier(0);
+    float dc[kResChunk];
+#pragma unroll
+    for (int j = 0; j < kResChunk; ++j) dc[j] = dn[j];
+    if (c + kResChunk < G::E) {
+#pragma unroll
+      for (int j = 0; j < kResChunk; ++j) dn[j] = load_data<N, LAY>(a.data, k, L, c + kResChunk + j);
+    }
+#pragma unroll
+    for (int j = 0; j < kResChunk; ++j) {
+      const int s = c + j;
+      const float2 g = SG ? v[s] : cscale(v[s], invN);
+      const float x = fmaf(g.x, g.x, g.y * g.y);
+      float phi, ft, fac;
+      pixel_terms<true, EST>(x, dc[j], a.eps, phi, ft, fac);
+      acc_phi += (double)phi;
+      acc_f += (double)ft;
+      v[s] = cscale(g, fac * invN);
+    }
   }
   // The sums are only consumed by the final reduction; without this the
   // compiler sinks the objective terms past the inverse transform and keeps
@@ -467,19 +499,31 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_minfunc(PatArgs a) {
   fwd_line<N>(v, L.h);
   const float invN = 1.0f / N;
   double acc_phi = 0.0, acc_f = 0.0;
+  // intensities one chunk ahead (as in GRAD)
+  float dn[kResChunk];
 #pragma unroll
-  for (int s = 0; s < G::E; ++s) {
-    if (s % kResChunk == 0) __builtin_amdgcn_sched_barrier(0);
-    const int b = fidx<N>(s, L.h);
-    const float d = load_data<N, LAY>(a.data, k, L, s);
-    const float2 g = cscale(v[s], invN);
-    const float x = fmaf(g.x, g.x, g.y * g.y);
-    float phi, ft, fac;
-    // the solver's line search (transposed intensities) needs only Phi
-    constexpr bool WANT_F = LAY == DataLayout::Rows;
-    pixel_terms<WANT_F, EST>(x, d, a.eps, phi, ft, fac);
-    acc_phi += (double)phi;
-    if constexpr (WANT_F) acc_f += (double)ft;
+  for (int j = 0; j < kResChunk; ++j) dn[j] = load_data<N, LAY>(a.data, k, L, j);
+#pragma unroll
+  for (int c = 0; c < G::E; c += kResChunk) {
+    __builtin_amdgcn_sched_barrier(0);
+    float dc[kResChunk];
+#pragma unroll
+    for (int j = 0; j < kResChunk; ++j) dc[j] = dn[j];
+    if (c + kResChunk < G::E) {
+#pragma unroll
+      for (int j = 0; j < kResChunk; ++j) dn[j] = load_data<N, LAY>(a.data, k, L, c + kResChunk + j);
+    }
+#pragma unroll
+    for (int j = 0; j < kResChunk; ++j) {
+      const float2 g = cscale(v[c + j], invN);
+      const float x = fmaf(g.x, g.x, g.y * g.y);
+      float phi, ft, fac;
+      // the solver's line search (transposed intensities) needs only Phi
+      constexpr bool WANT_F = LAY == DataLayout::Rows;
+      pixel_terms<WANT_F, EST>(x, dc[j], a.eps, phi, ft, fac);
+      acc_phi += (double)phi;
+      if constexpr (WANT_F) acc_f += (double)ft;
+    }
   }
   if (!valid) {
     acc_phi = 0.0;
