@@ -409,6 +409,12 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
   fwd_line<N>(v, L.h);
   const float invN = 1.0f / N;
   double acc_phi = 0.0, acc_f = 0.0, acc_aa = 0.0;
+  // intensities one chunk ahead: chunk c + 1's loads are issued before
+  // chunk c's arithmetic, so their latency overlaps it; the first chunk goes
+  // out before the G psi stores (a load waits for every earlier store)
+  float dn[kResChunk];
+#pragma unroll
+  for (int j = 0; j < kResChunk; ++j) dn[j] = load_data<N, LAY>(a.data, k, L, j);
   if constexpr (SG) {
     // G psi for the batched line search, in the element order of the
     // transposed intensities, with sum |G psi|^2.  All stores go out before
@@ -427,11 +433,6 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
     }
     __builtin_amdgcn_sched_barrier(0);
   }
-  // intensities one chunk ahead: chunk c + 1's loads are issued before
-  // chunk c's arithmetic, so their latency overlaps it
-  float dn[kResChunk];
-#pragma unroll
-  for (int j = 0; j < kResChunk; ++j) dn[j] = load_data<N, LAY>(a.data, k, L, j);
 #pragma unroll
   for (int c = 0; c < G::E; c += kResChunk) {
     __builtin_amdgcn_sched_barrier(0);
