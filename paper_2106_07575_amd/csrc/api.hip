@@ -67,7 +67,8 @@ constexpr int kGdTrace = 1024;  // objectives kept on the device between gradien
 
 struct Layout {
   size_t partials, scalars, gdtrace, flag, pparts, eta_obj, grad_obj, eta_probe, grad_probe, data_t, ubuf, toff, tlist,
-      far_a, far_b, far_c, lsparts, lsphi, nz_counts, nz_offsets, nz_idx, zparts, zsums, illum, nz_seg, nz_dc, total;
+      far_a, far_b, far_c, lsparts, lsphi, nz_counts, nz_offsets, nz_idx, zparts, zsums, illum, nz_seg, nz_dc, tparts,
+      total;
   size_t nz_blocks, z_blocks;
   size_t n_partials;
 };
@@ -112,6 +113,8 @@ Layout layout(const ptyg_dims* d, bool joint, bool batched = false, bool views =
   L.tlist = o;
   const size_t nl = std::max(T, (size_t)d->k * tiles_per_patch(d->n));
   o = align_up(o + nl * sizeof(int));
+  L.tparts = o;  // per-tile (|grad|^2, Re<eta, grad>) rows of the overlap sum
+  o = align_up(o + 2 * T * sizeof(double));
   L.far_a = L.far_b = L.far_c = L.lsparts = L.lsphi = L.nz_counts = L.nz_offsets = L.nz_idx = L.zparts = L.zsums = 0;
   L.illum = L.nz_seg = L.nz_dc = 0;
   L.nz_blocks = L.z_blocks = 0;
@@ -359,7 +362,8 @@ namespace {
 ptyg_status run_grad(const ptyg_dims* dims, const float2* obj, const float2* probe, const int2* pos,
                      const float* data, DataLayout lay, float eps, int est, float2* grad_obj, float2* grad_probe,
                      double* objective, void* ws, const Layout& L, hipStream_t s, float2* gstore = nullptr,
-                     double* gsum = nullptr, const uint2* cseg = nullptr) {
+                     double* gsum = nullptr, const uint2* cseg = nullptr, const float2* dot_b = nullptr,
+                     double* dot_out = nullptr) {
   PatArgs a = base_args(dims);
   a.est = est;
   a.gstore = gstore;
@@ -379,18 +383,21 @@ ptyg_status run_grad(const ptyg_dims* dims, const float2* obj, const float2* pro
     TimedLaunch tl(0, s);
     PTYG_HIP(launch_grad(a, lay, &nb, s));
   }
-  {
-    // (phi, f) and, for the batched search, sum |G psi|^2: one launch
-    FinJob jobs[2];
-    int nj = 0;
-    if (objective) jobs[nj++] = FinJob{a.partials, nb, 2, objective};
-    if (gstore && gsum) jobs[nj++] = FinJob{a.zs_part, nb, 1, gsum};
-    if (nj) PTYG_HIP(launch_finalize2(jobs[0], jobs[nj - 1], nj, s));
-  }
+  double* tparts = dot_out ? at<double>(ws, L.tparts) : nullptr;
   {
     TimedLaunch tl(3, s);
     PTYG_HIP(launch_tile_sum(a.ubuf, a.premul ? nullptr : probe, pos, at<int>(ws, L.toff), at<int>(ws, L.tlist),
-                             dims->k, dims->obj_h, dims->obj_w, dims->n, grad_obj, s));
+                             dims->k, dims->obj_h, dims->obj_w, dims->n, grad_obj, s, dot_b, tparts));
+  }
+  {
+    // (phi, f), for the batched search sum |G psi|^2, and the overlap sum's
+    // (||grad||^2, Re<dot_b, grad>): one launch
+    FinJob jobs[3];
+    int nj = 0;
+    if (objective) jobs[nj++] = FinJob{a.partials, nb, 2, objective};
+    if (gstore && gsum) jobs[nj++] = FinJob{a.zs_part, nb, 1, gsum};
+    if (dot_out) jobs[nj++] = FinJob{tparts, tiles_x(dims->obj_w) * tiles_y(dims->obj_h), 2, dot_out};
+    if (nj) PTYG_HIP(launch_finalize_n(jobs, nj, s));
   }
   if (grad_probe)
     PTYG_HIP(launch_probe_grad(a.ubuf, obj, pos, dims->k, dims->obj_w, dims->n, at<float2>(ws, L.pparts),
@@ -544,16 +551,12 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
 
   for (int m = 0; m < opts->iters; ++m) {
     // GRAD stage
+    // the overlap sum also forms ||g_m||^2 and Re<eta_{m-1}, g_m> (sc[N1O], sc[N2O])
     if (ptyg_status st = run_grad(dims, obj, probe, pos, dt, DataLayout::Transposed, eps, est, grad_o, grad_p,
-                                  sc + PHI, ws, L, s, far_a, batched ? at<double>(ws, L.zsums) : nullptr, cseg))
+                                  sc + PHI, ws, L, s, far_a, batched ? at<double>(ws, L.zsums) : nullptr, cseg,
+                                  restart ? nullptr : eta_o, sc + N1O))
       return st;
     VecArgs v{};
-    v.n = on;
-    v.a = grad_o;
-    v.b = restart ? nullptr : eta_o;
-    v.partials = partials;
-    PTYG_HIP(launch_dot2(v, s));
-    PTYG_HIP(launch_finalize(partials, nvb_o, 2, sc + N1O, s));
     if (joint) {
       VecArgs vp{};
       vp.n = pn;

@@ -736,13 +736,17 @@ __device__ __forceinline__ int u_off(int yy, int xx, int N) {
 #endif
 constexpr int kTileDepth = PTYG_TILE_DEPTH;
 
+// dot_parts (nullable): per tile (sum |out|^2, sum Re(conj(dot_b) out)) over
+// the tile's pixels (the second 0 when dot_b is null), as written.
 template <bool POLY, bool PROBE>
 __global__ __launch_bounds__(256) void k_tile_sum(const float2* __restrict__ U, const float2* __restrict__ probe,
                                                    const int2* __restrict__ pos, const int* __restrict__ offsets,
                                                    const int* __restrict__ list, int H, int W, int N,
-                                                   int64_t ustride, float2* __restrict__ out) {
+                                                   int64_t ustride, float2* __restrict__ out,
+                                                   const float2* __restrict__ dot_b, double* __restrict__ dot_parts) {
   __shared__ int sk[kTileStage];
   __shared__ int2 sp[kTileStage];
+  __shared__ double red[2 * 4];
   const int ntx = tiles_x(W);
   const int t = blockIdx.x;
   const int x = (t % ntx) * kTileW + (threadIdx.x & 63);
@@ -795,11 +799,28 @@ __global__ __launch_bounds__(256) void k_tile_sum(const float2* __restrict__ U, 
       }
     }
   }
+  double s1 = 0.0, s2 = 0.0;
   if (x < W) {
 #pragma unroll
     for (int i = 0; i < R; ++i) {
       const int y = yb + 4 * i;
-      if (y < H) out[(size_t)y * W + x] = acc[i];
+      if (y < H) {
+        out[(size_t)y * W + x] = acc[i];
+        if (dot_parts) {
+          s1 += (double)acc[i].x * acc[i].x + (double)acc[i].y * acc[i].y;
+          if (dot_b) {
+            const float2 e = dot_b[(size_t)y * W + x];
+            s2 += (double)e.x * acc[i].x + (double)e.y * acc[i].y;
+          }
+        }
+      }
+    }
+  }
+  if (dot_parts) {
+    block_sum2<256>(s1, s2, red);
+    if (threadIdx.x == 0) {
+      dot_parts[2 * (size_t)t] = s1;
+      dot_parts[2 * (size_t)t + 1] = s2;
     }
   }
 }
@@ -1307,10 +1328,13 @@ __device__ __forceinline__ void finalize_rows(const FinJob& j, double* red) {
   if (threadIdx.x < W) j.out[threadIdx.x] = red[threadIdx.x];
 }
 
-// Workgroup b finalizes job b (one or two independent reductions per launch).
-__global__ __launch_bounds__(256) void k_finalize(FinJob a, FinJob b) {
+// Workgroup b finalizes job b (up to four independent reductions per launch).
+struct FinJobs {
+  FinJob j[4];
+};
+__global__ __launch_bounds__(256) void k_finalize(FinJobs jobs) {
   __shared__ double red[256 * 4];
-  const FinJob j = blockIdx.x == 0 ? a : b;
+  const FinJob j = jobs.j[blockIdx.x];
   switch (j.width) {
     case 1: finalize_rows<1>(j, red); break;
     case 2: finalize_rows<2>(j, red); break;
@@ -1559,20 +1583,21 @@ hipError_t launch_tile_lists(const int2* pos, int K, int H, int W, int N, int* o
 }
 
 hipError_t launch_tile_sum(const float2* ubuf, const float2* probe, const int2* pos, const int* offsets,
-                           const int* list, int K, int H, int W, int N, float2* out, hipStream_t s) {
+                           const int* list, int K, int H, int W, int N, float2* out, hipStream_t s,
+                           const float2* dot_b, double* dot_parts) {
   (void)K;
   const int T = tiles_x(W) * tiles_y(H);
   const int64_t us = (int64_t)N * N;
   if (N == 256) {
     if (!probe) return hipErrorInvalidValue;
     hipLaunchKernelGGL((k_tile_sum<true, true>), dim3(T), dim3(256), 0, s, ubuf, probe, pos, offsets, list, H, W, N,
-                       us, out);
+                       us, out, dot_b, dot_parts);
   } else if (probe) {
     hipLaunchKernelGGL((k_tile_sum<false, true>), dim3(T), dim3(256), 0, s, ubuf, probe, pos, offsets, list, H, W,
-                       N, us, out);
+                       N, us, out, dot_b, dot_parts);
   } else {
     hipLaunchKernelGGL((k_tile_sum<false, false>), dim3(T), dim3(256), 0, s, ubuf, probe, pos, offsets, list, H, W,
-                       N, us, out);
+                       N, us, out, dot_b, dot_parts);
   }
   return hipGetLastError();
 }
@@ -1583,7 +1608,7 @@ hipError_t launch_illum(const float2* probe, const int2* pos, const int* offsets
   const int T = tiles_x(W) * tiles_y(H);
   // every pattern's "u_k" is the probe itself (stride 0): sum conj(p) p
   hipLaunchKernelGGL((k_tile_sum<false, true>), dim3(T), dim3(256), 0, s, probe, probe, pos, offsets, list, H, W, N,
-                     (int64_t)0, out);
+                     (int64_t)0, out, nullptr, nullptr);
   return hipGetLastError();
 }
 
@@ -1728,12 +1753,20 @@ hipError_t launch_finalize(const double* partials, int count, int width, double*
 }
 
 hipError_t launch_finalize2(const FinJob& a, const FinJob& b, int jobs, hipStream_t s) {
-  for (int i = 0; i < jobs; ++i) {
-    const FinJob& j = i == 0 ? a : b;
-    if (!j.p || !j.out || j.count < 1 || j.width < 1 || j.width > 4) return hipErrorInvalidValue;
-  }
   if (jobs < 1 || jobs > 2) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_finalize, dim3(jobs), dim3(256), 0, s, a, b);
+  const FinJob js[2] = {a, b};
+  return launch_finalize_n(js, jobs, s);
+}
+
+hipError_t launch_finalize_n(const FinJob* jobs, int n, hipStream_t s) {
+  if (!jobs || n < 1 || n > 4) return hipErrorInvalidValue;
+  FinJobs all{};
+  for (int i = 0; i < n; ++i) {
+    const FinJob& j = jobs[i];
+    if (!j.p || !j.out || j.count < 1 || j.width < 1 || j.width > 4) return hipErrorInvalidValue;
+    all.j[i] = j;
+  }
+  hipLaunchKernelGGL(k_finalize, dim3(n), dim3(256), 0, s, all);
   return hipGetLastError();
 }
 

@@ -127,8 +127,11 @@ hipError_t launch_tile_lists(const int2* pos, int K, int H, int W, int N, int* o
 // out[y][x] = sum over the tile's patterns k (ascending) of conj(p) * u_k at
 // (y - r_k, x - c_k); every object pixel is written.  probe = NULL: ubuf
 // already holds conj(p) * u_k (PatArgs::premul, n <= 128 only).
+// dot_parts (nullable): per tile t, rows (sum |out|^2, sum Re(conj(dot_b) out))
+// over the tile's pixels (dot_b nullable: second entry 0); tiles_x * tiles_y rows.
 hipError_t launch_tile_sum(const float2* ubuf, const float2* probe, const int2* pos, const int* offsets,
-                           const int* list, int K, int H, int W, int N, float2* out, hipStream_t s);
+                           const int* list, int K, int H, int W, int N, float2* out, hipStream_t s,
+                           const float2* dot_b = nullptr, double* dot_parts = nullptr);
 // out[y][x].x = sum over the tile's patterns k (ascending) of |p|^2 at
 // (y - r_k, x - c_k): the illumination, the diagonal of G^H G.
 hipError_t launch_illum(const float2* probe, const int2* pos, const int* offsets, const int* list, int H, int W,
@@ -231,5 +234,7 @@ struct FinJob {
   double* out;       // [width]
 };
 hipError_t launch_finalize2(const FinJob& a, const FinJob& b, int jobs, hipStream_t s);
+// Up to four independent finalizations in one launch.
+hipError_t launch_finalize_n(const FinJob* jobs, int n, hipStream_t s);
 
 }  // namespace ptyg
