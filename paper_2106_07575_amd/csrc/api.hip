@@ -40,7 +40,9 @@ constexpr size_t kScalars = 64;
 // Slots of the scalar region read back together once per line-search pass:
 // solver scalars [0, 16), zero-pixel sums [16, 32), line-search row [32, 56).
 constexpr int kZsSlot = 16, kLsSlot = 32;
-static_assert(kLsSlot + kLsRow <= (int)kScalars, "scalar region too small");
+// and the device's decision on the pass [56, 59): step, accepted trial, stop
+constexpr int kAccSlot = kLsSlot + kLsRow;
+static_assert(kAccSlot + 3 <= (int)kScalars, "scalar region too small");
 
 size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
 
@@ -542,6 +544,14 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
   };
   double* h = readback_buffer();
   if (!h) return fail(PTYG_E_HIP, "pinned readback buffer: %s", hipGetErrorString(hipGetLastError()));
+  struct EventGuard {
+    hipEvent_t e = nullptr;
+    ~EventGuard() {
+      if (e) (void)hipEventDestroy(e);
+    }
+  } rb;
+  if (batched) PTYG_HIP(hipEventCreateWithFlags(&rb.e, hipEventDisableTiming));
+  hipEvent_t rb_ev = rb.e;
   bool restart = true;
   const int nvb_o = vec_blocks(on), nvb_p = vec_blocks(pn);
   // the direction update reads its coefficient from the device: start from a
@@ -556,6 +566,7 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
                                   sc + PHI, ws, L, s, far_a, batched ? at<double>(ws, L.zsums) : nullptr, cseg,
                                   restart ? nullptr : eta_o, sc + N1O))
       return st;
+    bool applied = false;  // the update was applied with the device's step
     VecArgs v{};
     if (joint) {
       VecArgs vp{};
@@ -675,8 +686,6 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
       la.eps = eps;
       la.est = est;
       // whole-array sums: [0] |a|^2 (GRAD), [4..7] direction pass, [8..11] joint pass
-      const double* zs = h + kZsSlot;
-      double zc[6] = {0, 0, 0, 0, 0, 0};  // d <= 0 parts: aa, ab, bb, ac, bc, cc
       la.partials = lsparts;
       int j0 = 1;
       bool first = true;
@@ -685,10 +694,10 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
         // the first pass covers up to two trials past the previous accepted index
         int J = std::min(kLsBatch, opts->max_halvings - j0 + 1);
         if (first) J = std::min(J, std::max(4, last_trials + 2));
-        double gam[kLsBatch];
+        LsAccept acc{};
         for (int i = 0; i < J; ++i) {
           g_run *= opts->tau;  // the same sequence of doubles as the sequential search
-          gam[i] = g_run;
+          acc.gam[i] = g_run;
           la.g[i] = (float)g_run;
         }
         la.J = J;
@@ -698,42 +707,55 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
           PTYG_HIP(launch_ls_batch(la, &nb, s));
         }
         PTYG_HIP(launch_ls_finalize(lsparts, nb, lsphi, s));
-        // one copy per pass: the first reads the whole scalar region (solver
-        // scalars, zero-pixel sums, trial row), later ones the trial row
-        if (first)
-          PTYG_HIP(hipMemcpyAsync(h, sc, (kLsSlot + kLsRow) * sizeof(double), hipMemcpyDeviceToHost, s));
-        else
-          PTYG_HIP(hipMemcpyAsync(h + kLsSlot, lsphi, kLsRow * sizeof(double), hipMemcpyDeviceToHost, s));
-        PTYG_HIP(hipStreamSynchronize(s));
-        const double* phis = h + kLsSlot;
+        // the decision is taken on the device (one source of truth for the
+        // update below and for the step applied ahead of the host)
+        acc.J = J;
+        acc.t = opts->t;
+        acc.target = opts->target_phi;
+        acc.joint = joint ? 1 : 0;
+        acc.stop_check = first ? 1 : 0;
+        PTYG_HIP(launch_ls_accept(sc, sc + kZsSlot, lsphi, sc + kAccSlot, acc, s));
+        if (first) {
+          // one copy of the scalar region, then, ahead of the host, the update
+          // with the device's step (0 when this pass accepted nothing or the
+          // target is reached): the host waits for the copy only, so the
+          // update runs during the round trip
+          PTYG_HIP(hipMemcpyAsync(h, sc, (kAccSlot + 3) * sizeof(double), hipMemcpyDeviceToHost, s));
+          PTYG_HIP(hipEventRecord(rb_ev, s));
+          VecArgs u{};
+          u.n = on;
+          u.a = obj;
+          u.c = eta_o;
+          u.alpha_dev = sc + kAccSlot;
+          PTYG_HIP(launch_axpy(u, s));
+          if (joint) {
+            VecArgs up{};
+            up.n = pn;
+            up.a = probe;
+            up.c = eta_p;
+            up.alpha_dev = sc + kAccSlot;
+            PTYG_HIP(launch_axpy(up, s));
+          }
+          PTYG_HIP(hipEventSynchronize(rb_ev));
+        } else {
+          PTYG_HIP(hipMemcpyAsync(h + kLsSlot, lsphi, (kAccSlot + 3 - kLsSlot) * sizeof(double),
+                                  hipMemcpyDeviceToHost, s));
+          PTYG_HIP(hipStreamSynchronize(s));
+        }
         if (first) {
           if (ptyg_status st = take_scalars()) return st;
           if (stop) break;
           n3 = h[N3O] + (joint ? h[N3P] : 0.0);
           eta2 = h[EEO] + (joint ? h[EEP] : 0.0);
-          // whole-array sums minus the listed elements' shares (the same FP32
-          // values summed in FP64): the d <= 0 parts
-          const double* sh = phis + kLsBatch;
-          zc[0] = zs[0] - sh[0];
-          zc[1] = zs[4] - sh[1];
-          zc[2] = zs[6] - sh[2];
-          if (joint) {
-            zc[3] = zs[8] - sh[3];
-            zc[4] = zs[9] - sh[4];
-            zc[5] = zs[10] - sh[5];
-          }
         }
-        for (int i = 0; i < J; ++i) {
-          trials = j0 + i;
-          gamma = gam[i];
-          // d <= 0 pixels: sum |a + g b + g^2 c|^2 at the trial's FP32 step
-          const double g = (double)la.g[i];
-          double zero = zc[0] + 2.0 * g * zc[1] + g * g * zc[2];
-          if (joint) zero += 2.0 * g * g * zc[3] + 2.0 * g * g * g * zc[4] + g * g * g * g * zc[5];
-          if (phis[i] + zero <= phi_m + gamma * opts->t) {
-            accepted = true;
-            break;
-          }
+        const int acc_trial = (int)h[kAccSlot + 1];
+        if (acc_trial > 0) {
+          accepted = true;
+          trials = j0 + acc_trial - 1;
+          gamma = h[kAccSlot];
+          applied = first;  // the update already ran with the device's step
+        } else {
+          trials = j0 + J - 1;
         }
         j0 += J;
         first = false;
@@ -763,8 +785,8 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
     if (stop) break;  // target objective reached at psi_m: no update
     if (!accepted) gamma = 0.0;
 
-    // Update stage (Eq. update)
-    if (gamma != 0.0) {
+    // Update stage (Eq. update); already applied when the first batched pass accepted
+    if (gamma != 0.0 && !applied) {
       VecArgs u{};
       u.n = on;
       u.a = obj;

@@ -936,7 +936,7 @@ __global__ void k_dy_beta(double* sc, int n1, int n2, int n3, int joint_off, int
 }
 
 __global__ __launch_bounds__(kVecWG) void k_axpy(VecArgs v) {
-  const float al = (float)v.alpha;
+  const float al = (float)(v.alpha_dev ? *v.alpha_dev : v.alpha);
   for (int64_t i = (int64_t)blockIdx.x * kVecWG + threadIdx.x; i < v.n; i += (int64_t)gridDim.x * kVecWG) {
     const float2 x = v.a[i], c = v.c[i];
     v.a[i] = make_float2(fmaf(al, c.x, x.x), fmaf(al, c.y, x.y));
@@ -1098,6 +1098,37 @@ __global__ __launch_bounds__(256) void k_patch_sums(const float2* __restrict__ o
   }
   block_sum4_store<256>(z1, red1, parts1 + 4 * blockIdx.x);
   block_sum4_store<256>(z2, red2, parts2 + 4 * blockIdx.x);
+}
+
+// One thread: the batched pass's decision (see launch_ls_accept).
+__global__ void k_ls_accept(const double* sc, const double* zs, const double* row, double* out, LsAccept a) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const double phi = sc[0];
+  const double* sh = row + kLsBatch;
+  double zc[6] = {zs[0] - sh[0], zs[4] - sh[1], zs[6] - sh[2], 0.0, 0.0, 0.0};
+  if (a.joint) {
+    zc[3] = zs[8] - sh[3];
+    zc[4] = zs[9] - sh[4];
+    zc[5] = zs[10] - sh[5];
+  }
+  double gamma = 0.0, idx = 0.0, stop = 0.0;
+  if (a.stop_check && a.target >= 0.0 && phi <= a.target) {
+    stop = 1.0;
+  } else {
+    for (int i = 0; i < a.J; ++i) {
+      const double g = (double)(float)a.gam[i];
+      double zero = zc[0] + 2.0 * g * zc[1] + g * g * zc[2];
+      if (a.joint) zero += 2.0 * g * g * zc[3] + 2.0 * g * g * g * zc[4] + g * g * g * g * zc[5];
+      if (row[i] + zero <= phi + a.gam[i] * a.t) {
+        gamma = a.gam[i];
+        idx = (double)(i + 1);
+        break;
+      }
+    }
+  }
+  out[0] = gamma;
+  out[1] = idx;
+  out[2] = stop;
 }
 
 // out[j] = sum over rows (in order) of partials[row][j]; one workgroup per j.
@@ -1488,6 +1519,13 @@ hipError_t launch_patch_sums(const float2* obj, const float2* eta, const float2*
   while ((1 << lg) < N) ++lg;
   hipLaunchKernelGGL(k_patch_sums, dim3(patch_sums_blocks(K, N)), dim3(256), 0, s, obj, eta, probe, eta_p, pos, K,
                      W, lg, parts1, parts2);
+  return hipGetLastError();
+}
+
+hipError_t launch_ls_accept(double* sc, const double* zs, const double* row, double* out, const LsAccept& a,
+                            hipStream_t s) {
+  if (!sc || !zs || !row || !out || a.J < 1 || a.J > kLsBatch) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_ls_accept, dim3(1), dim3(64), 0, s, sc, zs, row, out, a);
   return hipGetLastError();
 }
 

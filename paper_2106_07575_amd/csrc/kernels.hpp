@@ -76,7 +76,7 @@ struct VecArgs {
   const float2* c;
   double alpha;
   double* partials;
-  const double* alpha_dev;    // k_dir: coefficient read on the device (overrides alpha) ...
+  const double* alpha_dev;    // k_dir, k_axpy: coefficient read on the device (overrides alpha); k_dir also ...
   const double* restart_dev;  // ... and a restart flag (nonzero: b <- -a, the old b ignored)
   // k_dir, optional: rows (sum w Re(psi conj b), 0, sum w |b|^2, 0) per block
   // over the new direction b, w = zs_w[i].x (the illumination: these are
@@ -199,6 +199,20 @@ hipError_t launch_shift_views(const int2* pos, int k, int views, int rows_per_vi
 hipError_t launch_ls_finalize_views(const double* partials, int views, double* out, hipStream_t s);
 // out[j] = in-order sum over `count` rows of partials[row][j], j < kLsRow.
 hipError_t launch_ls_finalize(const double* partials, int count, double* out, hipStream_t s);
+// Acceptance of a batched line-search pass on the device (Eq. linesearch):
+// trial i (0-based) passes when row[i] + zero(g_i) <= phi + gam[i] t, with
+// zero(g) the d <= 0 polynomial at the FP32 step g = (float) gam[i] whose
+// coefficients are the whole-array sums minus the listed shares; the first
+// passing trial is taken.  With stop_check, phi <= target (target >= 0)
+// stops instead.  Writes out[0] = accepted step (0 if none or stop),
+// out[1] = accepted trial (1-based, 0 if none), out[2] = 1 on stop.
+struct LsAccept {
+  double gam[kLsBatch];
+  double t, target;
+  int J, joint, stop_check;
+};
+hipError_t launch_ls_accept(double* sc, const double* zs, const double* row, double* out, const LsAccept& a,
+                            hipStream_t s);
 hipError_t launch_transpose_data(const float* d, float* dt, int K, int N, hipStream_t s);
 hipError_t launch_debug_gather(const PatArgs& a, float2* patches, hipStream_t s);
 hipError_t launch_debug_scatter(const PatArgs& a, const float2* patches, hipStream_t s);
