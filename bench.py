@@ -71,10 +71,10 @@ HBM_PEAK_GBS = 8000.0
 # from the rocprofv3 --pmc runs summarised in profiles/; keyed (kind,
 # workload, line search); absent = not measured for the current kernel build
 TRAFFIC_BYTES = {
-    ("grad", "c2", "batched"): 1020147849,
-    ("dir_forward", "c2", "batched"): 113390496,
-    ("tile_sum", "c2", "batched"): 706655013,
-    ("ls_batched", "c2", "batched"): 157930441,
+    ("grad", "c2", "batched"): 1083741074,
+    ("dir_forward", "c2", "batched"): 113416434,
+    ("tile_sum", "c2", "batched"): 725889829,
+    ("ls_batched", "c2", "batched"): 157934318,
 }
 FP32_PEAK_TFLOPS = 157.3
 
