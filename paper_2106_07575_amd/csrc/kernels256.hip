@@ -198,11 +198,19 @@ __global__ __launch_bounds__(256) void k_combine(PatArgs a, int64_t items) {
         r[j] = a.far[(size_t)k * NB * NB + (size_t)A * NB + B];
       }
     } else {
+      // the four intensities before any store (a load waits for every
+      // earlier store)
+      float dv[4];
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int A = ai + 128 * (j >> 1), B = bi + 128 * (j & 1);
-        const float d = (LAY == DataLayout::Transposed) ? a.data[(size_t)k * NB * NB + (size_t)B * NB + A]
-                                                        : a.data[(size_t)k * NB * NB + (size_t)A * NB + B];
+        dv[j] = (LAY == DataLayout::Transposed) ? a.data[(size_t)k * NB * NB + (size_t)B * NB + A]
+                                                : a.data[(size_t)k * NB * NB + (size_t)A * NB + B];
+      }
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int A = ai + 128 * (j >> 1), B = bi + 128 * (j & 1);
+        const float d = dv[j];
         if constexpr (MODE == 1 && LAY == DataLayout::Transposed) {
           if (a.gstore) {
             a.gstore[(size_t)k * NB * NB + (size_t)B * NB + A] = g[j];
