@@ -581,14 +581,25 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
     // DIR stage (Eq. DaiYuan) on the device: beta = ||g_m||^2 /
     // Re<eta_{m-1}, g_m - g_{m-1}> (sc[N3O] still holds Re<eta_{m-1}, g_{m-1}>),
     // restart on a failed search or a bad denominator; no host round trip
-    PTYG_HIP(launch_dy_beta(sc, N1O, N2O, N3O, joint ? 2 : 0, BETA, RST, restart ? 1 : 0, s));
     v = VecArgs{};
     v.n = on;
     v.a = grad_o;
     v.b = eta_o;
-    v.alpha_dev = sc + BETA;
-    v.restart_dev = sc + RST;
     v.partials = partials;
+    if (joint) {
+      // both blocks' directions take the coefficient from the object and
+      // probe scalars together
+      PTYG_HIP(launch_dy_beta(sc, N1O, N2O, N3O, 2, BETA, RST, restart ? 1 : 0, s));
+      v.alpha_dev = sc + BETA;
+      v.restart_dev = sc + RST;
+    } else {
+      // the direction kernel forms the coefficient itself
+      v.dy_n1 = sc + N1O;
+      v.dy_n2 = sc + N2O;
+      v.dy_n3 = sc + N3O;
+      v.dy_out = sc + BETA;
+      v.dy_restart = restart ? 1 : 0;
+    }
     if (illum) {
       // Re<G psi, G eta> and ||G eta||^2 for the batched search, as
       // illumination-weighted object sums (rows of 4 like the direction

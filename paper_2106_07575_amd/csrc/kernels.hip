@@ -897,8 +897,22 @@ __global__ __launch_bounds__(kVecWG) void k_dir(VecArgs v) {
   double s1 = 0.0, s2 = 0.0;
   double z[4] = {0.0, 0.0, 0.0, 0.0};
   const bool zs = v.zs_part != nullptr;
-  const float beta = (float)(v.alpha_dev ? *v.alpha_dev : v.alpha);
-  const bool rst = v.restart_dev && *v.restart_dev != 0.0;
+  double beta_d;
+  bool rst;
+  if (v.dy_n1) {
+    const double num = *v.dy_n1, den = *v.dy_n2 - *v.dy_n3;
+    const bool ok = !v.dy_restart && isfinite(den) && den > 0.0 && isfinite(num);
+    beta_d = ok ? num / den : 0.0;
+    rst = !ok;
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+      v.dy_out[0] = beta_d;
+      v.dy_out[1] = rst ? 1.0 : 0.0;
+    }
+  } else {
+    beta_d = v.alpha_dev ? *v.alpha_dev : v.alpha;
+    rst = v.restart_dev && *v.restart_dev != 0.0;
+  }
+  const float beta = (float)beta_d;
   for (int64_t i = (int64_t)blockIdx.x * kVecWG + threadIdx.x; i < v.n; i += (int64_t)gridDim.x * kVecWG) {
     const float2 g = v.a[i];
     const float2 e = v.b[i];

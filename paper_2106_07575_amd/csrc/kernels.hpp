@@ -84,6 +84,15 @@ struct VecArgs {
   const float2* zs_psi;
   const float2* zs_w;
   double* zs_part;
+  // k_dir, optional (overrides alpha / alpha_dev): the Dai-Yuan coefficient
+  // beta = n1 / (n2 - n3) from device scalars, restart (beta 0) when
+  // dy_restart is set or the denominator is not finite and positive;
+  // workgroup 0 writes beta and the restart flag (0 / 1) to dy_out[0..1]
+  const double* dy_n1;
+  const double* dy_n2;
+  const double* dy_n3;
+  double* dy_out;
+  int dy_restart;
 };
 
 enum class DataLayout { Rows = 0, Transposed = 1 };
