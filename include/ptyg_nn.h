@@ -94,7 +94,7 @@ int32_t ptyg_ws_shift_positions(const int32_t* pos, int32_t K, int32_t off, int3
 int32_t ptyg_ws_phase_sync(const void* patches, const int32_t* wpos, int32_t K, int32_t q, int32_t maxnb,
                            int32_t iters, int32_t* cnt, int32_t* nb, void* c, void* z, void* ztmp, void* stream);
 /* psi0[y][x] = mean over covering windows (ascending k) of z_k P_k, 1 where none covers.
- * offsets/list: tile lists of the windows (32 x 64 tiles, as built for the object gradient). */
+ * offsets/list: tile lists of the windows (ptyg_ws_tile_lists: the object gradient's tiles). */
 int32_t ptyg_ws_stitch(const void* patches, const void* z, const int32_t* wpos, const int32_t* offsets,
                        const int32_t* list, int32_t H, int32_t W, int32_t q, void* psi0, void* stream);
 /* count[y][x] = number of windows covering each object pixel. */
