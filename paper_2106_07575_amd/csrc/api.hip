@@ -154,14 +154,15 @@ Layout layout(const ptyg_dims* d, bool joint, bool batched = false, bool views =
       // this diagonal, so Re<G psi, G eta> and ||G eta||^2 are object sums
       L.illum = o;
       o = align_up(o + obj_n * sizeof(float2));
-      if (d->n == 128) {
-        // far fields stored for the listed elements only: segment records
-        // and the listed intensities, compacted
-        L.nz_seg = o;
-        o = align_up(o + elems / 32 * sizeof(uint2));
-        L.nz_dc = o;
-        o = align_up(o + elems * sizeof(float));
-      }
+    }
+    if (!views && (d->n == 128 || d->n == 256)) {
+      // far fields stored for the listed elements only (the d <= 0 part of
+      // the search comes from sums formed elsewhere): segment records and
+      // the listed intensities, compacted
+      L.nz_seg = o;
+      o = align_up(o + elems / 32 * sizeof(uint2));
+      L.nz_dc = o;
+      o = align_up(o + elems * sizeof(float));
     }
   }
   L.total = o;
@@ -517,7 +518,7 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
   PTYG_HIP(launch_transpose_data(data, dt, dims->k, dims->n, s));
   if (ptyg_status st = build_tiles(dims, pos, ws, L, s)) return st;
   float2* illum = batched && !joint ? at<float2>(ws, L.illum) : nullptr;
-  // n = 128, object only: G psi and G eta are stored for the listed elements only
+  // n = 128 and 256: G psi, G eta (and G(eta_p eta)) are stored for the listed elements only
   uint2* cseg = L.nz_seg ? at<uint2>(ws, L.nz_seg) : nullptr;
   float* dcomp = L.nz_dc ? at<float>(ws, L.nz_dc) : nullptr;
   if (illum)

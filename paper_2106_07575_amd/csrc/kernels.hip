@@ -1459,11 +1459,14 @@ hipError_t launch_fwd_t(const PatArgs& a, bool lin, hipStream_t s) {
   if (lin && (!a.dobj || !a.dprobe)) return hipErrorInvalidValue;
   const bool zs = a.zs_part != nullptr;
   if (zs && !a.zs_p) return hipErrorInvalidValue;
-  if (a.cseg) {
-    if (a.N != 128 || zs || lin) return hipErrorInvalidValue;
-    hipLaunchKernelGGL((k_fwd_t<128, false, 0, true>), dim3(pattern_blocks<128>(a.K)), dim3(Geo<128>::WG), 0, s, a);
+  if (a.cseg && a.N == 128) {
+    if (zs) return hipErrorInvalidValue;
+    const dim3 g(pattern_blocks<128>(a.K)), b(Geo<128>::WG);
+    if (lin) hipLaunchKernelGGL((k_fwd_t<128, true, 0, true>), g, b, 0, s, a);
+    else hipLaunchKernelGGL((k_fwd_t<128, false, 0, true>), g, b, 0, s, a);
     return hipGetLastError();
   }
+  if (a.cseg && a.N != 256) return hipErrorInvalidValue;
   if (a.N == 256) return launch_fwd_t256(a, lin, s);
   return dispatch_n(a.N, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
@@ -1507,13 +1510,13 @@ hipError_t launch_nz_compact(const float* d, int64_t n, int* counts, int* offset
 hipError_t launch_ls_batch(const LsArgs& a, int* blocks_out, hipStream_t s) {
   if (!a.A || !a.B || !a.d || (!a.idx && !a.compact) || !a.partials || a.n < 0 || a.J < 1 || a.J > kLsBatch)
     return hipErrorInvalidValue;
-  if (a.compact && a.C) return hipErrorInvalidValue;
   const int64_t want = (a.n + 255) / 256;
   const int nb = (int)(want < 1 ? 1 : (want < kLsBlocks ? want : kLsBlocks));
   if (blocks_out) *blocks_out = nb;
   return dispatch_est(a.est, [&](auto ec) {
     constexpr int E = decltype(ec)::value;
-    if (a.compact) hipLaunchKernelGGL((k_ls_batch<false, E, true>), dim3(nb), dim3(256), 0, s, a);
+    if (a.compact && a.C) hipLaunchKernelGGL((k_ls_batch<true, E, true>), dim3(nb), dim3(256), 0, s, a);
+    else if (a.compact) hipLaunchKernelGGL((k_ls_batch<false, E, true>), dim3(nb), dim3(256), 0, s, a);
     else if (a.C) hipLaunchKernelGGL((k_ls_batch<true, E, false>), dim3(nb), dim3(256), 0, s, a);
     else hipLaunchKernelGGL((k_ls_batch<false, E, false>), dim3(nb), dim3(256), 0, s, a);
     return hipGetLastError();

@@ -135,6 +135,14 @@ __global__ PTYG_SUB_KERNEL void k_sub_inv(PatArgs a) {
   for (int m = 0; m < G::E; ++m) (y + 2 * m * NS)[plo] = v[m];
 }
 
+// Compacted store of element e (a.cseg records, one per 32 elements of the
+// per-pattern transposed far field): listed elements only, at the record's
+// first index plus the listed elements before e in its segment.
+__device__ __forceinline__ void store_listed(float2* out, uint2 r, size_t e, float2 v) {
+  const uint32_t bit = (uint32_t)e & 31u;
+  if ((r.x >> bit) & 1u) out[r.y + __popc(r.x & ((1u << bit) - 1u))] = v;
+}
+
 // Pointwise radix-2x2 stage.  Thread item i: a = i & 127, b = (i >> 7) & 127,
 // k = i >> 14.  MODE 0: forward only (writes far, unitary).  MODE 1: GRAD
 // (objective partials, residual adjoint written back as R).  MODE 2:
@@ -181,6 +189,21 @@ __global__ __launch_bounds__(256) void k_combine(PatArgs a, int64_t items) {
           z[2] += (double)y.x * y.x + (double)y.y * y.y;
         }
       }
+      if (LAY == DataLayout::Transposed && a.cseg) {
+        // records first: a load waits for every earlier store
+        uint2 rec[4];
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int A = ai + 128 * (j >> 1), B = bi + 128 * (j & 1);
+          rec[j] = a.cseg[((size_t)k * NB * NB + (size_t)B * NB + A) >> 5];
+        }
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          const int A = ai + 128 * (j >> 1), B = bi + 128 * (j & 1);
+          store_listed(a.far, rec[j], (size_t)k * NB * NB + (size_t)B * NB + A, g[j]);
+        }
+        continue;
+      }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int A = ai + 128 * (j >> 1), B = bi + 128 * (j & 1);
@@ -201,11 +224,14 @@ __global__ __launch_bounds__(256) void k_combine(PatArgs a, int64_t items) {
       // the four intensities before any store (a load waits for every
       // earlier store)
       float dv[4];
+      uint2 rec[4];
+      const bool cp = MODE == 1 && LAY == DataLayout::Transposed && a.gstore && a.cseg;
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const int A = ai + 128 * (j >> 1), B = bi + 128 * (j & 1);
         dv[j] = (LAY == DataLayout::Transposed) ? a.data[(size_t)k * NB * NB + (size_t)B * NB + A]
                                                 : a.data[(size_t)k * NB * NB + (size_t)A * NB + B];
+        if (cp) rec[j] = a.cseg[((size_t)k * NB * NB + (size_t)B * NB + A) >> 5];
       }
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
@@ -213,7 +239,8 @@ __global__ __launch_bounds__(256) void k_combine(PatArgs a, int64_t items) {
         const float d = dv[j];
         if constexpr (MODE == 1 && LAY == DataLayout::Transposed) {
           if (a.gstore) {
-            a.gstore[(size_t)k * NB * NB + (size_t)B * NB + A] = g[j];
+            if (cp) store_listed(a.gstore, rec[j], (size_t)k * NB * NB + (size_t)B * NB + A, g[j]);
+            else a.gstore[(size_t)k * NB * NB + (size_t)B * NB + A] = g[j];
             z[0] += (double)g[j].x * g[j].x + (double)g[j].y * g[j].y;
           }
         }
