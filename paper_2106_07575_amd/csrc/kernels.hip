@@ -731,10 +731,7 @@ __device__ __forceinline__ int u_off(int yy, int xx, int N) {
 // loads from a clamped in-patch address (valid memory) and an out-of-patch
 // value is dropped by a select, so no load sits behind a branch and the adds
 // still run in ascending pattern order.
-#ifndef PTYG_TILE_DEPTH
-#define PTYG_TILE_DEPTH 4
-#endif
-constexpr int kTileDepth = PTYG_TILE_DEPTH;
+constexpr int kTileDepth = 4;
 
 // dot_parts (nullable): per tile (sum |out|^2, sum Re(conj(dot_b) out)) over
 // the tile's pixels (the second 0 when dot_b is null), as written.
