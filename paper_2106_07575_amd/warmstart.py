@@ -319,13 +319,34 @@ def finetune(net: Net, objects, probe, steps: int = 20, lr: float = 2e-4, batch_
     return hist
 
 
+def thin_positions(pos, min_sep: int) -> np.ndarray:
+    """Indices of a subset of the scan positions, greedy in scan order, with
+    every kept pair at least `min_sep` apart in row or column.  With
+    `min_sep` below the predicted window (64) the kept windows still overlap,
+    so they cover the scanned area and can be phase-synchronised."""
+    p = pos.cpu().numpy() if torch.is_tensor(pos) else np.asarray(pos)
+    kept = np.zeros((0, 2), p.dtype)
+    idx = []
+    for k in range(len(p)):
+        if len(kept) == 0 or np.all(np.maximum(np.abs(kept[:, 0] - p[k, 0]), np.abs(kept[:, 1] - p[k, 1])) >= min_sep):
+            idx.append(k)
+            kept = np.vstack([kept, p[k:k + 1]])
+    return np.asarray(idx, np.int64)
+
+
 def time_to_objective(net: Net, probe, pos, data, obj_shape, obj_true=None, plain_iters: int = 100,
-                      max_iters: int = 200, sync_iters: int = 100, line_search: str = "batched"):
+                      max_iters: int = 200, sync_iters: int = 100, line_search: str = "batched",
+                      infer_sep: int = 0):
     """Plain CG (psi_0 = 1, `plain_iters` iterations) against the warm start
     (inference + stitch + CG until its objective reaches plain CG's final
-    one).  Wall times are synchronised host timings."""
+    one).  Wall times are synchronised host timings.  infer_sep > 0: the
+    network sees only the patterns of thin_positions(pos, infer_sep) (the
+    selection, like the stitcher's lists, is set-up and not timed)."""
     H, W = int(obj_shape[0]), int(obj_shape[1])
     K = pos.shape[0]
+    sel = None
+    if infer_sep > 0:
+        sel = torch.from_numpy(thin_positions(pos, infer_sep)).to(pos.device)
     ws = ptyg.workspace(ptyg.dims_of((H, W), probe.shape[0], K), probe.device, line_search=line_search)
     ones = torch.ones((H, W), dtype=torch.complex64, device=probe.device)
     torch.cuda.synchronize()
@@ -336,10 +357,12 @@ def time_to_objective(net: Net, probe, pos, data, obj_shape, obj_true=None, plai
     phi_plain = plain.trace[-1]["phi"] if plain.trace else float("nan")
     # the objective of plain CG's final iterate (after its last update)
     phi_plain_final = float(ptyg.minfunc(plain.obj, probe, pos, data, ws=ws)[0])
-    st = Stitcher(pos, (H, W), iters=sync_iters)
+    pos_in = pos if sel is None else pos[sel].contiguous()
+    data_in = data if sel is None else data[sel].contiguous()
+    st = Stitcher(pos_in, (H, W), iters=sync_iters)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    out = predict(net, data)
+    out = predict(net, data_in)
     torch.cuda.synchronize()
     t_infer = time.perf_counter() - t1
     t2 = time.perf_counter()
@@ -360,6 +383,7 @@ def time_to_objective(net: Net, probe, pos, data, obj_shape, obj_true=None, plai
            "plain_iters": plain.iters_done, "phi0_ones": plain.trace[0]["phi"] if plain.trace else None,
            "phi0_warm": phi0_warm, "t_infer_s": t_infer, "t_stitch_s": t_stitch, "t_cg_warm_s": t_cg,
            "warm_iters": warm.iters_done, "warm_reached_target": bool(reached),
+           "infer_patterns": int(K if sel is None else len(sel)),
            "t_warm_total_s": t_infer + t_stitch + t_cg, "phi_warm_final": phi_warm_final,
            "warm_faster": bool(reached) and t_infer + t_stitch + t_cg < t_plain,
            "break_even_iters": (t_plain - t_infer - t_stitch) / t_plain_per_iter,
@@ -416,6 +440,8 @@ def main(argv=None):
     ap.add_argument("--finetune", type=int, default=400, help="fine-tuning steps through the operator")
     ap.add_argument("--finetune-lr", type=float, default=3e-4)
     ap.add_argument("--sync-iters", type=int, default=100)
+    ap.add_argument("--infer-sep", type=int, default=40,
+                    help="infer only a subset of patterns at least this many pixels apart (0: all)")
     ap.add_argument("--line-search", default="batched", choices=["batched", "sequential"])
     args = ap.parse_args(argv)
     dev = torch.device("cuda:0")
@@ -456,7 +482,7 @@ def main(argv=None):
         t_ft = time.perf_counter() - t2
         log(f"fine-tuned {args.finetune} steps in {t_ft:.1f} s: Phi {ft[0]:.4e} -> {ft[-1]:.4e}")
     res = time_to_objective(net, probe, pos, data, tuple(obj_true.shape), obj_true, sync_iters=args.sync_iters,
-                            line_search=args.line_search)
+                            line_search=args.line_search, infer_sep=args.infer_sep)
     res.update({"train_patterns": args.objects * args.per_side ** 2, "train_epochs": args.epochs,
                 "t_data_s": round(t_data, 2), "t_train_s": round(t_train, 2), "loss_history": hist[-5:],
                 "finetune_steps": args.finetune, "t_finetune_s": round(t_ft, 2),
