@@ -568,7 +568,6 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
                                   restart ? nullptr : eta_o, sc + N1O))
       return st;
     bool applied = false;  // the update was applied with the device's step
-    VecArgs v{};
     if (joint) {
       VecArgs vp{};
       vp.n = pn;
@@ -582,7 +581,7 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
     // DIR stage (Eq. DaiYuan) on the device: beta = ||g_m||^2 /
     // Re<eta_{m-1}, g_m - g_{m-1}> (sc[N3O] still holds Re<eta_{m-1}, g_{m-1}>),
     // restart on a failed search or a bad denominator; no host round trip
-    v = VecArgs{};
+    VecArgs v{};
     v.n = on;
     v.a = grad_o;
     v.b = eta_o;

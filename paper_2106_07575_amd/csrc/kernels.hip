@@ -753,6 +753,13 @@ __global__ __launch_bounds__(256) void k_tile_sum(const float2* __restrict__ U, 
   float2 acc[R];
 #pragma unroll
   for (int i = 0; i < R; ++i) acc[i] = make_float2(0.f, 0.f);
+  // the dot products' other operand, loaded ahead of the sum
+  float2 eb[R];
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int y = yb + 4 * i;
+    eb[i] = (dot_b && x < W && y < H) ? dot_b[(size_t)y * W + x] : make_float2(0.f, 0.f);
+  }
   const int beg = offsets[t], end = offsets[t + 1];
   for (int s0 = beg; s0 < end; s0 += kTileStage) {
     const int n = min(kTileStage, end - s0);
@@ -805,10 +812,7 @@ __global__ __launch_bounds__(256) void k_tile_sum(const float2* __restrict__ U, 
         out[(size_t)y * W + x] = acc[i];
         if (dot_parts) {
           s1 += (double)acc[i].x * acc[i].x + (double)acc[i].y * acc[i].y;
-          if (dot_b) {
-            const float2 e = dot_b[(size_t)y * W + x];
-            s2 += (double)e.x * acc[i].x + (double)e.y * acc[i].y;
-          }
+          if (dot_b) s2 += (double)eb[i].x * acc[i].x + (double)eb[i].y * acc[i].y;
         }
       }
     }
