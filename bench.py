@@ -71,10 +71,10 @@ HBM_PEAK_GBS = 8000.0
 # from the rocprofv3 --pmc runs summarised in profiles/; keyed (kind,
 # workload, line search); absent = not measured for the current kernel build
 TRAFFIC_BYTES = {
-    ("grad", "c2", "batched"): 1083741074,
-    ("dir_forward", "c2", "batched"): 113416434,
-    ("tile_sum", "c2", "batched"): 725889829,
-    ("ls_batched", "c2", "batched"): 157934318,
+    ("grad", "c2", "batched"): 1084702482,
+    ("dir_forward", "c2", "batched"): 113414743,
+    ("tile_sum", "c2", "batched"): 725436379,
+    ("ls_batched", "c2", "batched"): 157936402,
 }
 FP32_PEAK_TFLOPS = 157.3
 
