@@ -95,8 +95,13 @@ typedef struct {
                            mode): the GRAD pass stores G psi, one forward pass forms
                            G eta, and up to 16 trials are evaluated per streaming pass
                            over the stored far fields (no transforms); the accepted
-                           trial is the first that passes, as in the sequential order.
-                           Needs 2 (joint: 3) extra k*n*n complex64 of workspace. */
+                           trial is the first that passes, as in the sequential order,
+                           decided on the device.  The pixels with d <= 0 enter through
+                           a polynomial in gamma whose coefficients are object sums
+                           weighted by the illumination (object only) or patch sums
+                           (joint); at n = 128 and 256 the far fields are stored for
+                           the d > 0 pixels only.  Needs 2 (joint: 3) extra k*n*n
+                           complex64 of workspace (ptyg_workspace_size counts it). */
   int32_t estimator;    /* PTYG_EST_ML or PTYG_EST_LS */
 } ptyg_cg_opts;
 
