@@ -246,6 +246,31 @@ ptyg_status ptyg_debug_gather(const ptyg_dims* dims, const ptyg_c64* obj, const 
                               ptyg_c64* patches, ptyg_stream_t stream);
 ptyg_status ptyg_debug_scatter(const ptyg_dims* dims, const ptyg_c64* patches, const int32_t* pos,
                                ptyg_c64* obj_out, ptyg_stream_t stream);
+/* Test hook: the GRAD stage (Eq. gradient) from a GIVEN far field g instead
+ * of g = G(obj): the residual and objective terms, the inverse transform and
+ * the ordered overlap sum run exactly as in ptyg_grad (the same kernels and
+ * reductions).  far: [k][n][n] (the far field ptyg_forward would write);
+ * grad_obj = Q^H F^H (g - d g / |g|^2) (residual g where |g|^2 < eps);
+ * grad_probe (nullable, needs obj) and objective (nullable, device
+ * double[2]) as for ptyg_grad; residual (nullable): [k][n][n], receives the
+ * residual g - d g / |g|^2 itself.  Used to check the residual and adjoint
+ * half of GRAD on an exactly known far field. */
+ptyg_status ptyg_debug_grad_far(const ptyg_dims* dims, const ptyg_c64* far, const ptyg_c64* probe,
+                                const int32_t* pos, const float* data, float eps, int32_t estimator,
+                                ptyg_c64* grad_obj, const ptyg_c64* obj, ptyg_c64* grad_probe, double* objective,
+                                ptyg_c64* residual, void* ws, size_t ws_bytes, ptyg_stream_t stream);
+/* Test hook: the ordered overlap sum of the object gradient (the index part
+ * of Q^H, text after Eq. gradient) as GRAD runs it -- tile lists built from
+ * pos, then obj_out[y][x] = sum over the patterns k covering (y, x), in
+ * ascending k, of conj(probe) * waves[k] at (y - r_k, x - c_k).
+ * waves: [k][n*n] in the per-pattern layout GRAD stores: row-major
+ * [u][v] for n <= 128; for n = 256 the polyphase layout, element (u, v) at
+ * (2 (u & 1) + (v & 1)) n^2/4 + (u / 2) (n / 2) + v / 2.
+ * probe: NULL for n <= 128 sums the waves themselves (GRAD's layout when no
+ * probe gradient is wanted); required for n = 256.  obj_out is overwritten. */
+ptyg_status ptyg_debug_tile_sum(const ptyg_dims* dims, const ptyg_c64* waves, const ptyg_c64* probe,
+                                const int32_t* pos, ptyg_c64* obj_out, void* ws, size_t ws_bytes,
+                                ptyg_stream_t stream);
 /* Test hook: applies the lane exchange used by the split-line transforms to
  * two device float[64] arrays (lanes 32..63 of a <-> lanes 0..31 of b). */
 ptyg_status ptyg_debug_lane_swap(float* a, float* b, ptyg_stream_t stream);

@@ -261,14 +261,17 @@ def line_search(phi_of_gamma, phi_m: float, gamma0: float = 1.0,
 def cg_solve(obj0, probe0, pos, d, iters: int, gamma0: float = 1.0,
              tau: float = 0.5, t: float = 0.0, lmax: int = 40,
              eps: float = EPS, update_probe: bool = False,
-             target_phi: float | None = None, estimator: str = "ml"):
+             target_phi: float | None = None, estimator: str = "ml",
+             callback=None):
     """ML-CG reconstruction of Algorithm 1 on one device.
 
     Each iteration: GRAD (Eq. gradient) -> DIR (Eq. DaiYuan, eta_0 = -grad_0)
     -> LS (Eq. linesearch) -> Update (Eq. update).  Object only (the paper)
     or joint object+probe.  Returns (obj, probe, trace) with one trace row
     per iteration: phi, f (at psi_m), gamma, halvings, beta, step_norm
-    (||psi_{m+1} - psi_m||, the paper's convergence 2-norm), restarted."""
+    (||psi_{m+1} - psi_m||, the paper's convergence 2-norm), restarted.
+    callback (optional): called as callback(m + 1, obj, probe) after each
+    update, for recording iterates; it must not modify them."""
     x = [np.array(obj0, dtype=np.complex128)]
     if update_probe:
         x.append(np.array(probe0, dtype=np.complex128))
@@ -310,6 +313,8 @@ def cg_solve(obj0, probe0, pos, d, iters: int, gamma0: float = 1.0,
                       "restarted": bool(restarted)})
         g_old = g_new
         restart = not accepted
+        if callback is not None:
+            callback(m + 1, *unpack(x))
     o, p = unpack(x)
     return o, p, trace
 

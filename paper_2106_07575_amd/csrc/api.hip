@@ -366,7 +366,7 @@ ptyg_status run_grad(const ptyg_dims* dims, const float2* obj, const float2* pro
                      const float* data, DataLayout lay, float eps, int est, float2* grad_obj, float2* grad_probe,
                      double* objective, void* ws, const Layout& L, hipStream_t s, float2* gstore = nullptr,
                      double* gsum = nullptr, const uint2* cseg = nullptr, const float2* dot_b = nullptr,
-                     double* dot_out = nullptr) {
+                     double* dot_out = nullptr, const float2* far_in = nullptr, float2* res_out = nullptr) {
   PatArgs a = base_args(dims);
   a.est = est;
   a.gstore = gstore;
@@ -382,7 +382,12 @@ ptyg_status run_grad(const ptyg_dims* dims, const float2* obj, const float2* pro
   // conj(p) folded into the stored waves unless the probe gradient needs them plain
   a.premul = !grad_probe && dims->n <= 128;
   int nb = 0;
-  {
+  if (far_in) {
+    // test hook: the far field is given (row layout)
+    a.far = const_cast<float2*>(far_in);
+    a.gstore = res_out;
+    PTYG_HIP(launch_grad_far(a, &nb, s));
+  } else {
     TimedLaunch tl(0, s);
     PTYG_HIP(launch_grad(a, lay, &nb, s));
   }
@@ -1225,6 +1230,41 @@ ptyg_status ptyg_debug_scatter(const ptyg_dims* dims, const ptyg_c64* patches, c
   a.gobj = reinterpret_cast<float2*>(obj_out);
   PTYG_HIP(launch_zero(a.gobj, (int64_t)dims->obj_h * dims->obj_w, S(stream)));
   PTYG_HIP(launch_debug_scatter(a, reinterpret_cast<const float2*>(patches), S(stream)));
+  return PTYG_OK;
+}
+
+ptyg_status ptyg_debug_grad_far(const ptyg_dims* dims, const ptyg_c64* far, const ptyg_c64* probe,
+                                const int32_t* pos, const float* data, float eps, int32_t estimator,
+                                ptyg_c64* grad_obj, const ptyg_c64* obj, ptyg_c64* grad_probe, double* objective,
+                                ptyg_c64* residual, void* ws, size_t ws_bytes, ptyg_stream_t stream) {
+  if (ptyg_status st = check_dims(dims)) return st;
+  if (!far || !probe || !pos || !data || !grad_obj) return fail(PTYG_E_INVAL, "NULL array argument");
+  if (grad_probe && !obj) return fail(PTYG_E_INVAL, "grad_probe requires obj");
+  if (!(eps >= 0.0f)) return fail(PTYG_E_INVAL, "eps must be >= 0");
+  if (ptyg_status st = check_est(estimator)) return st;
+  Layout L;
+  if (ptyg_status st = check_ws(dims, ws, ws_bytes, false, &L)) return st;
+  if (ptyg_status st = build_tiles(dims, reinterpret_cast<const int2*>(pos), ws, L, S(stream))) return st;
+  return run_grad(dims, reinterpret_cast<const float2*>(obj), reinterpret_cast<const float2*>(probe),
+                  reinterpret_cast<const int2*>(pos), data, DataLayout::Rows, eps, estimator,
+                  reinterpret_cast<float2*>(grad_obj), reinterpret_cast<float2*>(grad_probe), objective, ws, L,
+                  S(stream), nullptr, nullptr, nullptr, nullptr, nullptr, reinterpret_cast<const float2*>(far),
+                  reinterpret_cast<float2*>(residual));
+}
+
+ptyg_status ptyg_debug_tile_sum(const ptyg_dims* dims, const ptyg_c64* waves, const ptyg_c64* probe,
+                                const int32_t* pos, ptyg_c64* obj_out, void* ws, size_t ws_bytes,
+                                ptyg_stream_t stream) {
+  if (ptyg_status st = check_dims(dims)) return st;
+  if (!waves || !pos || !obj_out) return fail(PTYG_E_INVAL, "NULL array argument");
+  if (dims->n == 256 && !probe) return fail(PTYG_E_INVAL, "n = 256 needs the probe (the product path multiplies it in)");
+  Layout L;
+  if (ptyg_status st = check_ws(dims, ws, ws_bytes, false, &L)) return st;
+  const int2* p = reinterpret_cast<const int2*>(pos);
+  if (ptyg_status st = build_tiles(dims, p, ws, L, S(stream))) return st;
+  PTYG_HIP(launch_tile_sum(reinterpret_cast<const float2*>(waves), reinterpret_cast<const float2*>(probe), p,
+                           at<int>(ws, L.toff), at<int>(ws, L.tlist), dims->k, dims->obj_h, dims->obj_w, dims->n,
+                           reinterpret_cast<float2*>(obj_out), S(stream)));
   return PTYG_OK;
 }
 

@@ -385,10 +385,15 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_fwd_t(PatArgs a) {
   }
 }
 
-template <int N, DataLayout LAY, bool SG, int EST, bool CP = false>
+// FARIN (test hook): the far field g = G psi is given in a.far (row layout)
+// instead of being formed; everything after it -- residual and objective
+// terms, inverse transform, stored waves -- is the same code as GRAD's.
+// With a.gstore set it also writes the residual r (row layout).
+template <int N, DataLayout LAY, bool SG, int EST, bool CP = false, bool FARIN = false>
 __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
   using G = Geo<N>;
   static_assert(!CP || (N == 128 && SG), "compacted stores: n = 128 with the G psi store");
+  static_assert(!FARIN || (!SG && LAY == DataLayout::Rows), "given far field: row layout, no G psi store");
   __shared__ float2 lds[G::LDS_ELEMS];
   __shared__ double red[2 * (G::WG / 64)];
   __shared__ uint2 srec[CP ? kSegPerPattern : 1];
@@ -403,10 +408,18 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
   }
   if constexpr (CP) stage_segments(srec, a, k);
   float2 v[G::E];
-  gather_exit_wave<N, false, false>(v, a, L, rc, valid);
-  fwd_line<N>(v, L.h);
-  transpose_c2r<N>(v, lds, L);
-  fwd_line<N>(v, L.h);
+  if constexpr (FARIN) {
+    // v = N g: the 1/N scaling below gives g back exactly (N a power of 2)
+#pragma unroll
+    for (int s = 0; s < G::E; ++s)
+      v[s] = cscale((a.far + (size_t)k * N * N + kFreq<N>.f[s])[(uint32_t)L.line * N + (L.h ? G::E / 2 : 0)],
+                    valid ? (float)N : 0.0f);
+  } else {
+    gather_exit_wave<N, false, false>(v, a, L, rc, valid);
+    fwd_line<N>(v, L.h);
+    transpose_c2r<N>(v, lds, L);
+    fwd_line<N>(v, L.h);
+  }
   const float invN = 1.0f / N;
   double acc_phi = 0.0, acc_f = 0.0, acc_aa = 0.0;
   // intensities one chunk ahead: chunk c + 1's loads are issued before
@@ -453,6 +466,15 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
       acc_phi += (double)phi;
       acc_f += (double)ft;
       v[s] = cscale(g, fac * invN);
+    }
+  }
+  if constexpr (FARIN) {
+    // test hook: the residual r = g fac itself, row layout like a.far
+    if (a.gstore && valid) {
+#pragma unroll
+      for (int s = 0; s < G::E; ++s)
+        (a.gstore + (size_t)k * N * N + kFreq<N>.f[s])[(uint32_t)L.line * N + (L.h ? G::E / 2 : 0)] =
+            cscale(v[s], (float)N);
     }
   }
   // The sums are only consumed by the final reduction; without this the
@@ -1450,6 +1472,21 @@ hipError_t launch_grad(const PatArgs& a, DataLayout lay, int* blocks_out, hipStr
       } else {
         hipLaunchKernelGGL((k_grad<N, DataLayout::Rows, false, E>), g, b, 0, s, a);
       }
+      return hipGetLastError();
+    });
+  });
+}
+
+hipError_t launch_grad_far(const PatArgs& a, int* blocks_out, hipStream_t s) {
+  if (!a.ubuf || !a.far || !a.data || !a.partials || !a.probe || !a.pos) return hipErrorInvalidValue;
+  if (a.N == 256) return launch_grad_far256(a, blocks_out, s);
+  return dispatch_n(a.N, [&](auto nc) {
+    constexpr int N = decltype(nc)::value;
+    const int nb = pattern_blocks<N>(a.K);
+    if (blocks_out) *blocks_out = nb;
+    return dispatch_est(a.est, [&](auto ec) {
+      constexpr int E = decltype(ec)::value;
+      hipLaunchKernelGGL((k_grad<N, DataLayout::Rows, false, E, false, true>), dim3(nb), dim3(Geo<N>::WG), 0, s, a);
       return hipGetLastError();
     });
   });

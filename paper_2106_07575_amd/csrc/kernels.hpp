@@ -116,6 +116,11 @@ hipError_t launch_forward(const PatArgs& a, hipStream_t s);
 // launch_probe_grad (no atomics, fixed summation order).
 hipError_t launch_adjoint(const PatArgs& a, hipStream_t s);
 hipError_t launch_grad(const PatArgs& a, DataLayout lay, int* blocks_out, hipStream_t s);
+// Test hook: GRAD from a given far field a.far (row layout [K][N][N]) in
+// place of G psi -- residual and objective partials, inverse transform and
+// the stored waves in a.ubuf exactly as launch_grad writes them.
+hipError_t launch_grad_far(const PatArgs& a, int* blocks_out, hipStream_t s);
+hipError_t launch_grad_far256(const PatArgs& a, int* blocks_out, hipStream_t s);
 
 // 256^2 patterns (kernels256.hip): four polyphase 128^2 sub-transforms and
 // a pointwise radix stage; u_k is left in the polyphase layout.

@@ -147,8 +147,13 @@ __device__ __forceinline__ void store_listed(float2* out, uint2 r, size_t e, flo
 // k = i >> 14.  MODE 0: forward only (writes far, unitary).  MODE 1: GRAD
 // (objective partials, residual adjoint written back as R).  MODE 2:
 // objective only.  MODE 3: adjoint of a given far field (writes R).
+// MODE 4 (test hook): MODE 1 with the far field taken from a.far (rows)
+// instead of the forward radix stage; with a.gstore set the residual r is
+// also written there (rows).
 template <int MODE, DataLayout LAY, int EST = 0>
 __global__ __launch_bounds__(256) void k_combine(PatArgs a, int64_t items) {
+  static_assert(MODE != 4 || LAY == DataLayout::Rows, "given far field: row layout");
+  constexpr bool RES = MODE == 1 || MODE == 4;  // residual and objective terms
   __shared__ double red[16];
   double acc_phi = 0.0, acc_f = 0.0;
   double z[4] = {0.0, 0.0, 0.0, 0.0};  // with a.zs_part: MODE 0 direction sums, MODE 1 sum |G psi|^2
@@ -158,7 +163,13 @@ __global__ __launch_bounds__(256) void k_combine(PatArgs a, int64_t items) {
     const int64_t k = i >> 14;
     float2* y = a.ubuf + (size_t)k * NB * NB + (size_t)bi * NS + ai;
     float2 g[4];  // index al * 2 + be
-    if constexpr (MODE != 3) {
+    if constexpr (MODE == 4) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const int A = ai + 128 * (j >> 1), B = bi + 128 * (j & 1);
+        g[j] = a.far[(size_t)k * NB * NB + (size_t)A * NB + B];
+      }
+    } else if constexpr (MODE != 3) {
       const float2 y00 = y[0], y01 = y[SUB], y10 = y[2 * SUB], y11 = y[3 * SUB];
       const float2 t00 = y00;
       const float2 t01 = cmul(w256(bi, -1), y01);
@@ -246,13 +257,22 @@ __global__ __launch_bounds__(256) void k_combine(PatArgs a, int64_t items) {
         }
         const float x = fmaf(g[j].x, g[j].x, g[j].y * g[j].y);
         float phi, ft, fac;
-        pixel_terms<MODE == 1 || LAY == DataLayout::Rows, EST>(x, d, a.eps, phi, ft, fac);
+        pixel_terms<RES || LAY == DataLayout::Rows, EST>(x, d, a.eps, phi, ft, fac);
         acc_phi += (double)phi;
-        if constexpr (MODE == 1 || LAY == DataLayout::Rows) acc_f += (double)ft;
+        if constexpr (RES || LAY == DataLayout::Rows) acc_f += (double)ft;
         r[j] = cscale(g[j], fac);
       }
+      if constexpr (MODE == 4) {
+        if (a.gstore) {
+#pragma unroll
+          for (int j = 0; j < 4; ++j) {
+            const int A = ai + 128 * (j >> 1), B = bi + 128 * (j & 1);
+            a.gstore[(size_t)k * NB * NB + (size_t)A * NB + B] = r[j];
+          }
+        }
+      }
     }
-    if constexpr (MODE == 1 || MODE == 3) {
+    if constexpr (RES || MODE == 3) {
       // adjoint radix stage: R_pq = conj(W^(ap+bq)) sum (-1)^(al p + be q) r / 256
       const float2 s0 = cadd(r[0], r[2]), s1 = csub(r[0], r[2]);  // over al
       const float2 u0 = cadd(r[1], r[3]), u1 = csub(r[1], r[3]);
@@ -284,7 +304,7 @@ __global__ __launch_bounds__(256) void k_combine(PatArgs a, int64_t items) {
       __syncthreads();  // red is reused by the objective reduction below
     }
   }
-  if constexpr (MODE == 1 || MODE == 2) {
+  if constexpr (RES || MODE == 2) {
     asm volatile("" : "+v"(acc_phi), "+v"(acc_f));
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) {
@@ -317,13 +337,17 @@ hipError_t combine(const PatArgs& a, DataLayout lay, int* blocks_out, hipStream_
   const int64_t items = (int64_t)a.K * SUB;
   if (blocks_out) *blocks_out = nb;
   // the estimator only enters the modes with objective terms
-  const int est = (MODE == 1 || MODE == 2) ? a.est : 0;
+  constexpr bool OBJ = MODE == 1 || MODE == 2 || MODE == 4;
+  const int est = OBJ ? a.est : 0;
   return dispatch_est(est, [&](auto ec) {
-    constexpr int E = (MODE == 1 || MODE == 2) ? decltype(ec)::value : 0;
-    if (lay == DataLayout::Transposed)
+    constexpr int E = OBJ ? decltype(ec)::value : 0;
+    if constexpr (MODE == 4) {
+      if (lay != DataLayout::Rows) return hipErrorInvalidValue;
+    } else if (lay == DataLayout::Transposed) {
       hipLaunchKernelGGL((k_combine<MODE, DataLayout::Transposed, E>), dim3(nb), dim3(256), 0, s, a, items);
-    else
-      hipLaunchKernelGGL((k_combine<MODE, DataLayout::Rows, E>), dim3(nb), dim3(256), 0, s, a, items);
+      return hipGetLastError();
+    }
+    hipLaunchKernelGGL((k_combine<MODE, DataLayout::Rows, E>), dim3(nb), dim3(256), 0, s, a, items);
     return hipGetLastError();
   });
 }
@@ -372,6 +396,12 @@ hipError_t launch_grad256(const PatArgs& a, DataLayout lay, int* blocks_out, hip
   if (hipError_t e = sub_fwd(b, s)) return e;
   if (hipError_t e = combine<1>(b, lay, blocks_out, s)) return e;
   return sub_inv(b, s);
+}
+
+hipError_t launch_grad_far256(const PatArgs& a, int* blocks_out, hipStream_t s) {
+  if (!staged_ok(a) || !a.far || !a.data || !a.partials) return hipErrorInvalidValue;
+  if (hipError_t e = combine<4>(a, DataLayout::Rows, blocks_out, s)) return e;
+  return sub_inv(a, s);
 }
 
 int fwd_t256_blocks(int K) { return combine_blocks(K); }

@@ -78,6 +78,9 @@ _SIGS = {
     "ptyg_debug_gather": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P]),
     "ptyg_debug_scatter": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P]),
     "ptyg_debug_lane_swap": (ctypes.c_int32, [_P, _P, _P]),
+    "ptyg_debug_grad_far": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P, ctypes.c_float, ctypes.c_int32,
+                                             _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
+    "ptyg_debug_tile_sum": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "ptyg_timing_enable": (None, [ctypes.c_int32]),
     "ptyg_timing_reset": (None, []),
     "ptyg_timing_read": (ctypes.c_int32, [ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_int32),
@@ -340,6 +343,52 @@ def debug_scatter(patches, pos, obj_shape) -> torch.Tensor:
     d = dims_of(obj_shape, patches.shape[-1], pos.shape[0])
     out = torch.empty(tuple(obj_shape), dtype=torch.complex64, device=patches.device)
     _check(load().ptyg_debug_scatter(ctypes.byref(d), _ptr(patches), _ptr(pos), _ptr(out), _stream()))
+    return out
+
+
+def debug_grad_far(far, probe, pos, data, obj_shape, obj=None, want_probe: bool = False, eps: float = 1e-32,
+                   estimator: str = "ml"):
+    """GRAD from a given far field [k, n, n] (test hook): returns
+    (objective f64 [2], grad_obj, grad_probe or None, residual [k, n, n])."""
+    far = _dev(far, "far", torch.complex64)
+    probe = _dev(probe, "probe", torch.complex64)
+    pos = _dev(positions(pos), "pos", torch.int32)
+    data = _dev(data, "data", torch.float32)
+    d = dims_of(obj_shape, probe.shape[0], pos.shape[0])
+    if tuple(far.shape) != (d.k, d.n, d.n) or tuple(data.shape) != (d.k, d.n, d.n):
+        raise ValueError("far and data must be [k, n, n]")
+    if want_probe:
+        if obj is None:
+            raise ValueError("the probe gradient needs obj")
+        obj = _dev(obj, "obj", torch.complex64)
+    g = torch.empty(tuple(obj_shape), dtype=torch.complex64, device=far.device)
+    gp = torch.empty_like(probe) if want_probe else None
+    objective = torch.empty(2, dtype=torch.float64, device=far.device)
+    res = torch.empty_like(far)
+    ws = workspace(d, far.device)
+    _check(load().ptyg_debug_grad_far(ctypes.byref(d), _ptr(far), _ptr(probe), _ptr(pos), _ptr(data), float(eps),
+                                      ESTIMATOR[estimator], _ptr(g), _ptr(obj if want_probe else None), _ptr(gp),
+                                      _ptr(objective), _ptr(res), _ptr(ws), ws.numel(), _stream()))
+    return objective, g, gp, res
+
+
+def debug_tile_sum(waves, pos, obj_shape, probe=None) -> torch.Tensor:
+    """Ordered overlap sum of per-pattern waves [k, n*n] in GRAD's stored
+    layout (natural for n <= 128, polyphase for 256), times conj(probe)
+    when a probe is given (test hook)."""
+    waves = _dev(waves, "waves", torch.complex64)
+    pos = _dev(positions(pos), "pos", torch.int32)
+    k = pos.shape[0]
+    n = int(round((waves.numel() // max(k, 1)) ** 0.5))
+    if waves.numel() != k * n * n:
+        raise ValueError("waves must hold k * n * n values")
+    if probe is not None:
+        probe = _dev(probe, "probe", torch.complex64)
+    d = dims_of(obj_shape, n, k)
+    out = torch.empty(tuple(obj_shape), dtype=torch.complex64, device=waves.device)
+    ws = workspace(d, waves.device)
+    _check(load().ptyg_debug_tile_sum(ctypes.byref(d), _ptr(waves), _ptr(probe), _ptr(pos), _ptr(out), _ptr(ws),
+                                      ws.numel(), _stream()))
     return out
 
 

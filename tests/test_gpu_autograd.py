@@ -1,18 +1,25 @@
 """torch.autograd wrappers (differentiable operator, joint object+probe
 gradient) on the c3 workload: 1024^2 object and 128^2 probe as leaves, 2048
-uniform positions, Poisson data at 1e4 photons.  Checked by central finite
-differences (64 seeded directions, each a random unit vector plus the unit
-gradient, scaled to ||v|| = ||x||) and against the oracle gradient.  The
-step is h = 1e-6: the Poisson log term is nearly singular at dim far-field
-pixels with counts, and along such directions the FP64 oracle's own central
-difference is off by 1.6e-2 at h = 1e-5 and 1.1e-4 at h = 1e-6 (O(h^2));
-at h = 1e-3 it is off by up to 40% even along random directions."""
+uniform positions, Poisson data at 1e4 photons.
+
+The loss gradient is checked against central finite differences of the FP64
+ORACLE objective (Eq. ML, deviance form) along purely random directions --
+object directions supported on four 192 x 192 windows (only the patterns
+touching a window change, so the oracle evaluates those alone) and probe
+directions -- against 2 Re <grad_W, v> = Re <torch grad, v>.  For Gaussian
+random directions the projections of the gradient and of its error have
+the same spread, so over the set of directions the relative L2 mismatch is
+the gradient's relative error: it must stay within 1.5x the gradient bound
+of _cases.grad_bound (1.5: the spread of a 16-sample ratio of norms) plus
+the finite differences' own truncation error, estimated per direction by
+the difference between steps h and 2h.  The gradient is also compared with
+2x the oracle's Wirtinger gradient directly."""
 import numpy as np
 import pytest
 
 from oracle import ptycho as O
 
-from _cases import grad_tol, grad_with_floor, rel, workload
+from _cases import grad_bound, rel, workload
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -33,39 +40,66 @@ def env():
     return AG, ptyg, dev, inp, psi, p, data
 
 
-def test_ml_loss_finite_differences_joint(env):
+def _local(pos, n, y0, x0, size):
+    """Patterns touching the window and their positions in a local frame."""
+    r, c = pos[:, 0], pos[:, 1]
+    touch = np.nonzero((r < y0 + size) & (r + n > y0) & (c < x0 + size) & (c + n > x0))[0]
+    org = pos[touch].min(axis=0)
+    return touch, org
+
+
+def test_ml_loss_finite_differences_oracle(env):
     AG, ptyg, dev, inp, psi, p, data = env
     pos, d = dev(inp.pos), dev(data)
     o = dev(psi).requires_grad_(True)
     q = dev(p).requires_grad_(True)
     loss = AG.ml_loss(o, q, pos, d)
     loss.backward()
-    go, gq = o.grad, q.grad
-    assert loss.dtype == torch.float64
-    gen = torch.Generator(device="cuda").manual_seed(5)
-    gnorm = torch.sqrt(torch.linalg.vector_norm(go) ** 2 + torch.linalg.vector_norm(gq) ** 2)
-    h = 1e-6
-    errs = []
-    with torch.no_grad():
-        for j in range(64):
-            # random direction plus the gradient direction: a purely random
-            # direction in 2.1M real dimensions is nearly orthogonal to the
-            # gradient, and its tiny derivative drowns in FP32 loss noise
-            vo = torch.randn(o.shape, dtype=torch.complex64, device="cuda", generator=gen)
-            vq = torch.randn(q.shape, dtype=torch.complex64, device="cuda", generator=gen)
-            vo = vo / torch.linalg.vector_norm(vo) + go / gnorm
-            vq = vq / torch.linalg.vector_norm(vq) + gq / gnorm
-            vo *= torch.linalg.vector_norm(o) / torch.linalg.vector_norm(vo)
-            vq *= torch.linalg.vector_norm(q) / torch.linalg.vector_norm(vq)
-            lp = AG.ml_loss(o + h * vo, q + h * vq, pos, d).item()
-            lm = AG.ml_loss(o - h * vo, q - h * vq, pos, d).item()
-            fd = (lp - lm) / (2 * h)
-            # torch convention: dL = Re <grad, dz> summed over leaves
-            an = (torch.vdot(go.flatten().to(torch.complex128), vo.flatten().to(torch.complex128)).real
-                  + torch.vdot(gq.flatten().to(torch.complex128), vq.flatten().to(torch.complex128)).real).item()
-            errs.append(abs(fd - an) / abs(an))
-    print(f"FD over 64 directions: max rel {max(errs):.2e}, median {np.median(errs):.2e}")
-    assert max(errs) <= 1e-3
+    go = o.grad.cpu().numpy().astype(np.complex128)
+    gq = q.grad.cpu().numpy().astype(np.complex128)
+    psi64, p64, d64 = psi.astype(np.complex128), p.astype(np.complex128), data.astype(np.float64)
+    n = p.shape[0]
+    rng = np.random.default_rng(77)
+    fds, ans, trunc = [], [], []
+    size = 192
+    for y0, x0 in [(100, 120), (420, 700), (700, 260), (830, 830)]:
+        touch, org = _local(inp.pos, n, y0, x0, size)
+        lpos = (inp.pos[touch] - org).astype(np.int32)
+        sh = tuple(int(v) for v in lpos.max(axis=0) + n)
+        base = psi64[org[0]:org[0] + sh[0], org[1]:org[1] + sh[1]]
+        wy, wx = slice(y0 - org[0], y0 - org[0] + size), slice(x0 - org[1], x0 - org[1] + size)
+        for _ in range(4):
+            v = np.zeros(sh, np.complex128)
+            v[wy, wx] = rng.standard_normal((size, size)) + 1j * rng.standard_normal((size, size))
+            h = 1e-6 * np.linalg.norm(base) / np.linalg.norm(v)
+            f = lambda t: O.minfunc(base + t * v, p64, lpos, d64[touch])[0]
+            c1 = (f(h) - f(-h)) / (2 * h)
+            c2 = (f(2 * h) - f(-2 * h)) / (4 * h)
+            gv = np.zeros(sh, np.complex128)
+            gv[wy, wx] = go[y0:y0 + size, x0:x0 + size]
+            fds.append(c1)
+            ans.append(np.vdot(gv, v).real)
+            trunc.append(abs(c2 - c1) / 3.0)
+    for _ in range(4):
+        v = rng.standard_normal(p.shape) + 1j * rng.standard_normal(p.shape)
+        h = 1e-6 * np.linalg.norm(p64) / np.linalg.norm(v)
+        f = lambda t: O.minfunc(psi64, p64 + t * v, inp.pos, d64)[0]
+        c1 = (f(h) - f(-h)) / (2 * h)
+        c2 = (f(2 * h) - f(-2 * h)) / (4 * h)
+        fds.append(c1)
+        ans.append(np.vdot(gq, v).real)
+        trunc.append(abs(c2 - c1) / 3.0)
+    fds, ans, trunc = map(np.asarray, (fds, ans, trunc))
+    far = ptyg.forward(o.detach(), q.detach(), pos).cpu().numpy()
+    _, bo, bp, fo, fp = grad_bound(far, psi, p, inp.pos, data, want_probe=True)
+    eo = np.linalg.norm(fds[:16] - ans[:16]) / np.linalg.norm(fds[:16])
+    ep = np.linalg.norm(fds[16:] - ans[16:]) / np.linalg.norm(fds[16:])
+    to = np.linalg.norm(trunc[:16]) / np.linalg.norm(fds[:16])
+    tp = np.linalg.norm(trunc[16:]) / np.linalg.norm(fds[16:])
+    print(f"oracle FD vs autograd over random directions: object {eo:.2e} (gradient bound {bo:.2e}, FD "
+          f"truncation {to:.1e}), probe {ep:.2e} (bound {bp:.2e}, truncation {tp:.1e})")
+    assert eo <= 1.5 * bo + to
+    assert ep <= 1.5 * bp + tp
 
 
 def test_ml_loss_gradient_matches_oracle(env):
@@ -74,12 +108,14 @@ def test_ml_loss_gradient_matches_oracle(env):
     q = dev(p).requires_grad_(True)
     loss = AG.ml_loss(o, q, dev(inp.pos), dev(data))
     loss.backward()
-    ref, fo, fp = grad_with_floor(psi, p, inp.pos, data, want_probe=True)
+    far = ptyg.forward(dev(psi), dev(p), dev(inp.pos)).cpu().numpy()
+    ref, bo, bp, fo, fp = grad_bound(far, psi, p, inp.pos, data, want_probe=True)
     assert abs(loss.item() - ref["phi"]) <= 1e-5 * ref["phi"]
     eo = rel(o.grad.cpu().numpy(), 2 * ref["grad_obj"])
     ep = rel(q.grad.cpu().numpy(), 2 * ref["grad_probe"])
-    print(f"autograd vs 2x oracle gradient: object {eo:.2e} (floor {fo:.2e}), probe {ep:.2e} (floor {fp:.2e})")
-    assert eo <= grad_tol(fo) and ep <= grad_tol(fp)
+    print(f"autograd vs 2x oracle gradient: object {eo:.2e} (bound {bo:.2e}, floor {fo:.2e}), probe {ep:.2e} "
+          f"(bound {bp:.2e}, floor {fp:.2e})")
+    assert eo <= bo and ep <= bp
     # Eq. ML form: same gradient, value F
     o2 = dev(psi).requires_grad_(True)
     l2 = AG.ml_loss(o2, dev(p), dev(inp.pos), dev(data), which="eq_ml")

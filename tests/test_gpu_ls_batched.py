@@ -7,13 +7,14 @@ The batched search evaluates the trials from those stored far fields and
 accepts the first that passes, so its step sequence must equal the
 sequential one wherever the decisions are not within FP32 rounding of a tie:
 the same bars as the sequential tests (identical steps on well-conditioned
-workloads, the FP32-floor-derived object bound elsewhere)."""
+workloads, the object bound of _cases.trajectory_factor elsewhere)."""
 import numpy as np
 import pytest
 
 from oracle import ptycho as O
 
-from _cases import FLOOR_FACTOR, cg_with_floor, rel, workload
+from _cases import cg_with_floor, rel, workload
+from _gpu import start_factors
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -52,6 +53,14 @@ def run(P, case, iters, probe0=None, **kw):
     return res, ref, pert, mask_of(probe, inp.pos, obj.shape)
 
 
+def factors(P, case, probe0=None, joint=False):
+    """Iterate-bound factors (object, probe) of the solver started at
+    psi_0 = 1 and probe0 (_cases.trajectory_factor)."""
+    cfg, inp, probe, obj, data = workload(case)
+    p0 = probe if probe0 is None else probe0
+    return start_factors(P, np.ones(obj.shape, np.complex64), p0, inp.pos, data, want_probe=joint)
+
+
 def gammas(tr):
     return [r["gamma"] for r in tr]
 
@@ -77,7 +86,8 @@ def test_batched_object_within_fp32_floor(P, case, iters):
     floor = rel(po[mask], ro[mask])
     print(f"{case}/{iters}: object rel {err:.2e}; fp32 floor {floor:.2e}")
     assert res.iters_done == iters
-    assert err <= max(1e-3, FLOOR_FACTOR * floor)
+    c, _ = factors(P, case)
+    assert err <= max(1e-3, c * floor)
     assert res.trace[0]["gamma"] == rtr[0]["gamma"]
     phis = [r["phi"] for r in res.trace]
     assert all(b <= a for a, b in zip(phis, phis[1:]))
@@ -86,7 +96,10 @@ def test_batched_object_within_fp32_floor(P, case, iters):
     e_gpu = rel(O.align_phase(res.obj.cpu().numpy().astype(np.complex128), truth, mask)[mask], truth[mask])
     e_ora = rel(O.align_phase(ro, truth, mask)[mask], truth[mask])
     print(f"   error vs truth: gpu {e_gpu:.4e} oracle {e_ora:.4e}")
-    assert e_gpu <= 1.25 * e_ora
+    # the phase-aligned error is a minimum over phases, so it can exceed the
+    # oracle's by at most the iterate difference (triangle inequality)
+    slack = np.linalg.norm((res.obj.cpu().numpy() - ro)[mask]) / np.linalg.norm(truth[mask])
+    assert e_gpu <= e_ora + slack * (1 + 1e-6)
 
 
 @pytest.mark.parametrize("case", ["m32", "m64", "m128"])
@@ -126,13 +139,14 @@ def test_batched_joint_probe(P):
     cfg, inp, probe, obj, data = workload("m16r")
     p0 = (np.abs(probe) * np.exp(0.2j)).astype(np.complex64)
     res, (ro, rp, rtr), (po, pp, ptr), mask = run(P, "m16r", 6, probe0=p0, update_probe=True)
+    co, cp = factors(P, "m16r", probe0=p0, joint=True)
     eo = rel(res.obj.cpu().numpy()[mask], ro[mask])
     ep = rel(res.probe.cpu().numpy(), rp)
     fo, fp = rel(po[mask], ro[mask]), rel(pp, rp)
     print(f"joint: object rel {eo:.2e} (floor {fo:.2e}) probe rel {ep:.2e} (floor {fp:.2e})")
     assert gammas(res.trace) == gammas(rtr)
-    assert eo <= max(1e-3, FLOOR_FACTOR * fo)
-    assert ep <= max(1e-3, FLOOR_FACTOR * fp)
+    assert eo <= max(1e-3, co * fo)
+    assert ep <= max(1e-3, cp * fp)
 
 
 def test_batched_joint_probe_128(P):
@@ -141,13 +155,14 @@ def test_batched_joint_probe_128(P):
     rng = np.random.default_rng(4)
     p0 = (probe * (1 + 0.05 * rng.standard_normal(probe.shape))).astype(np.complex64)
     res, (ro, rp, rtr), (po, pp, ptr), mask = run(P, "m128", 4, probe0=p0, update_probe=True)
+    co, cp = factors(P, "m128", probe0=p0, joint=True)
     eo = rel(res.obj.cpu().numpy()[mask], ro[mask])
     ep = rel(res.probe.cpu().numpy(), rp)
     fo, fp = rel(po[mask], ro[mask]), rel(pp, rp)
     print(f"joint 128: object rel {eo:.2e} (floor {fo:.2e}) probe rel {ep:.2e} (floor {fp:.2e})")
     assert gammas(res.trace) == gammas(rtr)
-    assert eo <= max(1e-3, FLOOR_FACTOR * fo)
-    assert ep <= max(1e-3, FLOOR_FACTOR * fp)
+    assert eo <= max(1e-3, co * fo)
+    assert ep <= max(1e-3, cp * fp)
 
 
 def test_batched_joint_probe_256(P):
@@ -155,13 +170,14 @@ def test_batched_joint_probe_256(P):
     rng = np.random.default_rng(3)
     p0 = (probe * (1 + 0.05 * rng.standard_normal(probe.shape))).astype(np.complex64)
     res, (ro, rp, rtr), (po, pp, ptr), mask = run(P, "m256", 3, probe0=p0, update_probe=True)
+    co, cp = factors(P, "m256", probe0=p0, joint=True)
     eo = rel(res.obj.cpu().numpy()[mask], ro[mask])
     ep = rel(res.probe.cpu().numpy(), rp)
     fo, fp = rel(po[mask], ro[mask]), rel(pp, rp)
     print(f"joint 256: object rel {eo:.2e} (floor {fo:.2e}) probe rel {ep:.2e} (floor {fp:.2e})")
     assert gammas(res.trace) == gammas(rtr)
-    assert eo <= max(1e-3, FLOOR_FACTOR * fo)
-    assert ep <= max(1e-3, FLOOR_FACTOR * fp)
+    assert eo <= max(1e-3, co * fo)
+    assert ep <= max(1e-3, cp * fp)
 
 
 def test_batched_is_bit_reproducible(P):

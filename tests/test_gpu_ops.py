@@ -1,15 +1,20 @@
 """Parity of the HIP operators with the FP64 oracle (through the C ABI).
 
 Tolerances: transforms are FP32 (unit roundoff 6e-8); a 2-D transform of
-n^2 <= 16384 points adds O(log2 n^2) roundings, so per-operator relative L2
-errors are ~1e-6.  The bound 1e-5 is the per-operator target.  Indexing
-(gather / scatter of integer-coded values) must be bit-exact."""
+n^2 <= 65536 points adds O(log2 n^2) roundings, so per-operator relative L2
+errors are ~1e-6.  The bound 1e-5 is the per-operator target; the forward
+transform must also stay within twice the error of scipy's single-precision
+FFT of the same exit waves (the same class of algorithm: radix-2/4 stages
+with correctly rounded twiddles).  The gradient is held to the bound that
+forward error implies through the residual's conditioning (_cases.grad_bound;
+its residual and adjoint half alone is held to 1e-5 in test_gpu_grad_half).
+Indexing (gather / scatter of integer-coded values) must be bit-exact."""
 import numpy as np
 import pytest
 
 from oracle import ptycho as O
 
-from _cases import grad_tol, grad_with_floor, rel, workload
+from _cases import grad_bound, rel, workload
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -66,6 +71,7 @@ def test_forward_adjoint_parity(P, case):
     sp32 = scipy.fft.fft2((probe[None] * O.gather(psi, inp.pos, n)).astype(np.complex64), norm="ortho")
     print(f"{case}: forward rel {rel(far, ref):.2e} (scipy float32 FFT {rel(sp32, ref):.2e})")
     assert rel(far, ref) <= TOL
+    assert rel(far, ref) <= 2.0 * rel(sp32, ref)
     y = (rng.standard_normal(far.shape) + 1j * rng.standard_normal(far.shape)).astype(np.complex64)
     go, gp = P.adjoint(dev(y), dev(probe), dev(inp.pos), shape, obj=dev(psi), want_probe=True)
     ro, rp = O.adjoint(y.astype(np.complex128), probe.astype(np.complex128), inp.pos, shape,
@@ -94,15 +100,16 @@ def test_grad_and_objective_parity(P, case):
     for psi in [np.ones(obj.shape, np.complex64),
                 (obj * (1 + 0.05 * rng.standard_normal(obj.shape))).astype(np.complex64)]:
         objective, g, gp = P.grad(dev(psi), dev(probe), dev(inp.pos), dev(data), want_probe=True)
-        ref, fo, fp = grad_with_floor(psi, probe, inp.pos, data, want_probe=True)
+        far = P.forward(dev(psi), dev(probe), dev(inp.pos)).cpu().numpy()
+        ref, bo, bp, fo, fp = grad_bound(far, psi, probe, inp.pos, data, want_probe=True)
         phi, f = objective.cpu().numpy()
         eo, ep = rel(g.cpu().numpy(), ref["grad_obj"]), rel(gp.cpu().numpy(), ref["grad_probe"])
-        print(f"{case}: phi rel {abs(phi - ref['phi']) / ref['phi']:.2e} grad_obj rel {eo:.2e} (fp32 floor "
-              f"{fo:.2e}) grad_probe rel {ep:.2e} (floor {fp:.2e})")
+        print(f"{case}: phi rel {abs(phi - ref['phi']) / ref['phi']:.2e} grad_obj rel {eo:.2e} (bound {bo:.2e}, "
+              f"fp32 floor {fo:.2e}) grad_probe rel {ep:.2e} (bound {bp:.2e}, floor {fp:.2e})")
         assert abs(phi - ref["phi"]) <= TOL * abs(ref["phi"])
         assert abs(f - ref["f"]) <= TOL * max(abs(ref["f"]), ref["phi"])
-        assert eo <= grad_tol(fo)
-        assert ep <= grad_tol(fp)
+        assert eo <= bo
+        assert ep <= bp
 
 
 @pytest.mark.parametrize("case", CASES)

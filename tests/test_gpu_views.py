@@ -1,13 +1,15 @@
 """Multi-view batch (ptyg_cg_solve_views): V independent projections in one
 set of launches must give, view by view, what the oracle's CG gives for each
 view alone -- identical line-search decisions on the well-conditioned
-32^2 workload, the FP32-floor bound on the 128^2 one."""
+32^2 workload, the iterate bound of _cases.trajectory_factor on the 128^2
+one."""
 import numpy as np
 import pytest
 
 from oracle import ptycho as O
 
-from _cases import FLOOR_FACTOR, cg_with_floor, rel, views_workload
+from _cases import cg_with_floor, rel, views_workload
+from _gpu import start_factors
 
 pytestmark = pytest.mark.gpu
 torch = pytest.importorskip("torch")
@@ -56,7 +58,8 @@ def test_views_within_fp32_floor_128(P):
         mask = illum >= 1e-3 * illum.max()
         err, floor = rel(out[v].cpu().numpy()[mask], ro[mask]), rel(po[mask], ro[mask])
         print(f"views 128 view {v}: object rel {err:.2e} (floor {floor:.2e})")
-        assert err <= max(1e-3, FLOOR_FACTOR * floor)
+        c, _ = start_factors(P, obj0[v], probe, pos[v], data[v])
+        assert err <= max(1e-3, c * floor)
         assert traces[v][0]["gamma"] == rtr[0]["gamma"]
 
 

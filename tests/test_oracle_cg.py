@@ -124,3 +124,85 @@ def test_joint_cg_monotone(c1):
     phis = [r["phi"] for r in tr]
     assert all(b <= a for a, b in zip(phis, phis[1:]))
     assert not np.allclose(p, p0)
+
+
+# ------------------------------------------------------------------
+# Joint object+probe mode and the target stop, pinned by a brute-force
+# evaluation on the hand-worked 2x2 fixture (tests/golden/hand_2x2.json):
+# the 2x2 unitary DFT written as its four +-1 sums, the deviance written per
+# pixel, no oracle function used.  The fixture's hand-derived gradients give
+# the first (steepest-descent) direction of both blocks.
+
+def _hand():
+    import json
+    import os
+    f = os.path.join(os.path.dirname(__file__), "golden", "hand_2x2.json")
+    h = json.load(open(f))
+    obj = np.array(h["obj_re"], dtype=complex)
+    probe = np.array(h["probe_re"]) + 1j * np.array(h["probe_im"])
+    pos = np.array(h["pos"], dtype=np.int32)
+    data = np.array(h["data"], dtype=float)
+    go = np.array(h["grad_obj_re"]) + 1j * np.array(h["grad_obj_im"])
+    gp = np.array(h["grad_probe_re"]) + 1j * np.array(h["grad_probe_im"])
+    return obj, probe, pos, data, go, gp
+
+
+def _phi_bruteforce(obj, probe, pos, data):
+    total = 0.0
+    for k, (r, c) in enumerate(pos):
+        e = [[probe[u][v] * obj[r + u][c + v] for v in range(2)] for u in range(2)]
+        for a in range(2):
+            for b in range(2):
+                g = 0.5 * sum(e[u][v] * (-1) ** (a * u + b * v) for u in range(2) for v in range(2))
+                x = abs(g) ** 2
+                d = data[k][a][b]
+                total += x if d == 0 else x - d - d * math.log(x / d)
+    return total
+
+
+def test_joint_first_iteration_bruteforce():
+    obj, probe, pos, data, go, gp = _hand()
+    phi0 = _phi_bruteforce(obj, probe, pos, data)
+    assert phi0 == pytest.approx(4 * (10 - 5 - 5 * math.log(2)), rel=1e-14)
+    # Algorithm 1 order: gamma <- tau gamma, evaluate, accept the first pass
+    j, gamma = 0, 1.0
+    while True:
+        j += 1
+        gamma *= 0.5
+        phi1 = _phi_bruteforce(obj - gamma * go, probe - gamma * gp, pos, data)
+        if phi1 <= phi0:
+            break
+    o, p, tr = O.cg_solve(obj, probe, pos, data, iters=2, update_probe=True)
+    assert tr[0]["restarted"] and tr[0]["beta"] == 0.0
+    assert tr[0]["gamma"] == gamma and tr[0]["halvings"] == j
+    assert tr[0]["phi"] == pytest.approx(phi0, rel=1e-12)
+    assert tr[1]["phi"] == pytest.approx(phi1, rel=1e-12)
+    step = gamma * math.sqrt(np.sum(np.abs(go) ** 2) + np.sum(np.abs(gp) ** 2))
+    assert tr[0]["step_norm"] == pytest.approx(step, rel=1e-12)
+    # object-only mode from the same start takes a different step: the probe
+    # block is what changes the search
+    _, _, tro = O.cg_solve(obj, probe, pos, data, iters=1)
+    jo, go_ = 0, 1.0
+    while True:
+        jo += 1
+        go_ *= 0.5
+        if _phi_bruteforce(obj - go_ * go, probe, pos, data) <= phi0:
+            break
+    assert tro[0]["gamma"] == go_ and tro[0]["halvings"] == jo
+
+
+def test_target_stop_bruteforce():
+    obj, probe, pos, data, go, gp = _hand()
+    _, _, tr = O.cg_solve(obj, probe, pos, data, iters=3, update_probe=True)
+    phi1 = tr[1]["phi"]
+    assert phi1 == pytest.approx(_phi_bruteforce(obj - tr[0]["gamma"] * go, probe - tr[0]["gamma"] * gp, pos, data),
+                                 rel=1e-12)
+    # the stop is tested on Phi(psi_m) before the direction: at target = Phi_1
+    # the solve ends after one update, just below it it takes the next one
+    o1, p1, t1 = O.cg_solve(obj, probe, pos, data, iters=3, update_probe=True, target_phi=phi1 * (1 + 1e-12))
+    assert len(t1) == 1
+    assert np.allclose(o1, obj - tr[0]["gamma"] * go, rtol=0, atol=1e-15)
+    o2, _, t2 = O.cg_solve(obj, probe, pos, data, iters=3, update_probe=True, target_phi=phi1 * (1 - 1e-9))
+    assert len(t2) >= 2
+    _, _, t0 = O.cg_solve(obj, probe, pos, data, iters=3, update_probe=True, target_phi=tr[0]["phi"])
+    assert len(t0) == 0
