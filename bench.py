@@ -3,16 +3,22 @@
 Workload: the single large projection -- 2048^2 complex64 object, 128^2
 apodised-disk probe, 64x64 = 4096 positions on a 24 px raster with +-2 px
 jitter, 128^2 float32 Poisson intensities at 1e5 photons per pattern,
-object-only CG with FP64 reductions.  A step is one CG iteration (GRAD ->
-DIR -> LS -> Update over all 4096 patterns).  W warm-up iterations run in a
-separate solve; the timed region is one ptyg_cg_solve of K iterations from
-the usual start (psi_0 = 1), inputs resident in HBM.
+object-only CG with FP64 reductions.  Inputs come from the seeded generator
+(object, probe, scan; Poisson counts drawn on the host from the generator's
+per-chunk seeds) with the expected intensities from the library's forward
+model, so the data are the tested workload's up to FP32 rounding of the
+expected counts.  A step is one CG iteration (GRAD -> DIR -> LS -> Update
+over all 4096 patterns).  W warm-up iterations run in a separate solve; the
+timed region is one ptyg_cg_solve of K iterations from the usual start
+(psi_0 = 1), inputs resident in HBM.
 
 value = diffraction patterns per second through grad + line search
-(4096 * K / t).  The roofline object is for the line-search kernel or the
-fused GRAD kernel, whichever takes more time, with its duration measured by
-HIP events on the launch stream inside the timed region.  The CPU baseline
-is the FP64 oracle on a bounded sample of the same workload.
+(4096 * K / t).  The roofline object is the forward+adjoint unit, the GRAD
+stage as the solver runs it (transform kernel, ordered overlap sum and
+reductions), at its algorithmic 20 bytes per pattern pixel, its duration
+measured by HIP events on the launch stream inside the timed region; the
+per-kernel fractions follow as secondary fields.  The CPU baseline is the
+FP64 oracle on a bounded sample of the same workload.
 """
 from __future__ import annotations
 
@@ -37,16 +43,15 @@ if ROOT not in sys.path:
 #   direction forward: eta patch 8 B + far field 8 B + stored A read 8 B
 #   overlap sum: back-propagated waves 8 B per pixel + object gradient write
 def kernel_bytes(kind: str, cfg, batched: bool, nnz: int, joint: bool = False) -> int:
-    """Algorithmic bytes per launch: 20 B per pattern pixel for GRAD (patch,
-    intensity, gradient contribution) plus the far field it stores for the
-    batched search, 8 B per stored value; far fields stored for the listed
-    elements only (object-only search at n = 128) add 8 B per listed element
-    and an 8-byte record per 32 elements."""
+    """Algorithmic bytes per launch.  GRAD kernel and GRAD stage: 20 B per
+    pattern pixel (patch 8, intensity 4, gradient contribution 8); the far
+    field the batched search stores is not counted.  Line-search pass,
+    direction forward and overlap sum as commented above."""
     px = cfg.k * cfg.n * cfg.n
     compact = batched and not joint and cfg.n == 128
     stored = 8 * nnz + px // 4 if compact else 8 * px
-    if kind == "grad":
-        return 20 * px + (stored if batched else 0)
+    if kind in ("grad", "grad_unit"):
+        return 20 * px
     if kind == "minfunc":
         if not batched:
             return 20 * px
@@ -64,17 +69,14 @@ def kernel_bytes(kind: str, cfg, batched: bool, nnz: int, joint: bool = False) -
 
 KERNEL_NAMES = {"grad": "k_grad (fused GRAD)", "minfunc": "k_minfunc (line-search trial)",
                 "ls_batched": "k_ls_batch (batched line-search pass)", "dir_forward": "k_fwd_t (G eta)",
-                "tile_sum": "k_tile_sum (ordered overlap sum)"}
+                "tile_sum": "k_tile_sum (ordered overlap sum)",
+                "grad_unit": "GRAD stage: k_grad + k_tile_sum + k_finalize (forward+adjoint unit)"}
 HBM_PEAK_GBS = 8000.0
 # HBM bytes per launch (FETCH_SIZE x 2 + WRITE_SIZE x 1, the factors from a
 # 512 MiB device copy measured by the same counters) of the current kernels,
 # from the rocprofv3 --pmc runs summarised in profiles/; keyed (kind,
 # workload, line search); absent = not measured for the current kernel build
 TRAFFIC_BYTES = {
-    ("grad", "c2", "batched"): 1084702482,
-    ("dir_forward", "c2", "batched"): 113414743,
-    ("tile_sum", "c2", "batched"): 725436379,
-    ("ls_batched", "c2", "batched"): 157936402,
 }
 FP32_PEAK_TFLOPS = 157.3
 
@@ -85,6 +87,9 @@ def fft_flops(n: int) -> float:
 
 
 def make_inputs(cfg_name: str, device):
+    """Seeded inputs: object, probe and scan from the generator; expected
+    intensities from the library's forward model of the true object; Poisson
+    counts drawn on the host from the generator's per-chunk seeds."""
     import numpy as np
     import torch
 
@@ -95,14 +100,14 @@ def make_inputs(cfg_name: str, device):
     obj_true = torch.from_numpy(inp.obj_true.astype(np.complex64)).to(device)
     probe = torch.from_numpy(inp.probe.astype(np.complex64)).to(device)
     pos = torch.from_numpy(inp.pos).to(device)
-    # synthetic measurements: expected intensities from the forward model on
-    # the ground truth, then seeded Poisson counts
-    far = ptyg.forward(obj_true, probe, pos)
-    gen = torch.Generator(device=device)
-    gen.manual_seed(cfg.seed("poisson"))
-    data = torch.poisson((far.real ** 2 + far.imag ** 2).float(), generator=gen).contiguous()
-    del far
-    return cfg, inp, probe, pos, data
+    data = np.empty((cfg.k, cfg.n, cfg.n), np.float32)
+    chunk = 1024
+    for lo in range(0, cfg.k, chunk):
+        far = ptyg.forward(obj_true, probe, pos[lo:lo + chunk])
+        data[lo:lo + chunk] = (far.real ** 2 + far.imag ** 2).cpu().numpy()
+        del far
+    data = synth.make_data(cfg, data.astype(np.float64)).astype(np.float32)
+    return cfg, inp, probe, pos, torch.from_numpy(data).to(device)
 
 
 def cpu_baseline(cfg_name: str, halvings_per_iter: float, budget_s: float = 12.0):
@@ -296,12 +301,16 @@ def main():
         run_gd(args, cfg, probe, pos, data, obj0, joint)
         return
     ls = args.line_search
-    ws = ptyg.workspace(ptyg.dims_of(obj0.shape, cfg.n, K), device, update_probe=joint, line_search=ls)
-
     est = args.estimator
     px = K * cfg.n * cfg.n
-    nnz = int((~(data <= 0)).sum())
     batched = ls == "batched"
+    # the batched search stores far fields for the pixels with counts only:
+    # size its workspace by their number
+    nnz = ptyg.listed_count(data, cfg.n)
+    max_listed = nnz if batched else -1
+    ws = ptyg.workspace(ptyg.dims_of(obj0.shape, cfg.n, K), device, update_probe=joint, line_search=ls,
+                        max_listed=max_listed)
+    ws_full = ptyg.workspace_size(ptyg.dims_of(obj0.shape, cfg.n, K), update_probe=joint, line_search=ls)
 
     def kernel_table(kt):
         kinds = {}
@@ -309,33 +318,28 @@ def main():
             if cnt:
                 name = "ls_batched" if (kind == "minfunc" and batched) else kind
                 avg_s = ms / cnt / 1e3
-                ffts = {"grad": 2, "minfunc": 1, "dir_forward": 1 + int(joint), "ls_batched": 0, "tile_sum": 0}[name]
+                ffts = {"grad": 2, "minfunc": 1, "dir_forward": 1 + int(joint), "ls_batched": 0, "tile_sum": 0,
+                        "grad_unit": 2}[name]
                 kb = kernel_bytes(kind, cfg, batched, nnz, joint)
                 kinds[name] = {"kind": kind, "launches": cnt, "avg_us": avg_s * 1e6, "total_ms": ms,
                                "bytes_per_launch": kb, "alg_GBs": kb / avg_s / 1e9,
                                "fft_TFLOPs": ffts * K * fft_flops(cfg.n) / avg_s / 1e12}
         return kinds
 
-    # The warm-up times every kernel kind to find the dominant kernel; the
-    # timed run records events around that kernel only (an event pair adds
-    # a few microseconds between launches); a short pass after it, every
-    # kind timed, gives the per-kernel table.
+    # The timed run records events around the GRAD stage only (the
+    # forward+adjoint unit the roofline is about; an event pair adds a few
+    # microseconds between launches); a short pass after it, every kind
+    # timed, gives the per-kernel table.
     ptyg.timing_reset()
-    ptyg.timing_enable(True)
     if args.warmup > 0:
-        ptyg.cg_solve(obj0, probe, pos, data, args.warmup, update_probe=joint, ws=ws, line_search=ls, estimator=est)
+        ptyg.cg_solve(obj0, probe, pos, data, args.warmup, update_probe=joint, ws=ws, line_search=ls, estimator=est,
+                      max_listed=max_listed)
     torch.cuda.synchronize()
-    ptyg.timing_enable(False)
-    warm = kernel_table(ptyg.timing_read())
-    ptyg.timing_reset()
-    if warm:
-        ptyg.timing_enable(True, kinds=(warm[max(warm, key=lambda k: warm[k]["total_ms"])]["kind"],))
-    else:
-        ptyg.timing_enable(True)
+    ptyg.timing_enable(True, kinds=("grad_unit",))
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     res = ptyg.cg_solve(obj0, probe, pos, data, args.steps, update_probe=joint, ws=ws, line_search=ls,
-                        estimator=est)
+                        estimator=est, max_listed=max_listed)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
     ptyg.timing_enable(False)
@@ -343,7 +347,8 @@ def main():
     ptyg.timing_reset()
     ptyg.timing_enable(True)
     table_iters = min(args.steps, 10)
-    ptyg.cg_solve(obj0, probe, pos, data, table_iters, update_probe=joint, ws=ws, line_search=ls, estimator=est)
+    ptyg.cg_solve(obj0, probe, pos, data, table_iters, update_probe=joint, ws=ws, line_search=ls, estimator=est,
+                  max_listed=max_listed)
     torch.cuda.synchronize()
     ptyg.timing_enable(False)
     kinds = kernel_table(ptyg.timing_read())
@@ -367,14 +372,16 @@ def main():
     iters = res.iters_done
     halvings = sum(r["halvings"] for r in res.trace)
     value = K * iters / dt
-    dom = max(timed, key=lambda k: timed[k]["total_ms"])
+    dom = "grad_unit"
     d = timed[dom]
     bpl = d["bytes_per_launch"]
     roofline = {"bound": "hbm", "achieved": round(d["alg_GBs"], 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": round(d["alg_GBs"] / HBM_PEAK_GBS, 4), "traffic": TRAFFIC_BYTES.get((dom, args.config, ls)),
                 "kernel": KERNEL_NAMES[dom], "bytes_per_launch": bpl, "avg_launch_us": round(d["avg_us"], 2),
-                "fft_tflops": round(d["fft_TFLOPs"], 2), "fft_frac_of_fp32_peak":
-                    round(d["fft_TFLOPs"] / FP32_PEAK_TFLOPS, 4)}
+                "launches": d["launches"], "fft_tflops": round(d["fft_TFLOPs"], 2), "fft_frac_of_fp32_peak":
+                    round(d["fft_TFLOPs"] / FP32_PEAK_TFLOPS, 4),
+                "per_kernel_frac": {k: round(v["alg_GBs"] / HBM_PEAK_GBS, 4) for k, v in kinds.items()
+                                    if k != "grad_unit"}}
     out = {
         "metric": "diffraction patterns/s through grad+line search",
         "value": round(value, 1),
@@ -403,6 +410,8 @@ def main():
         "pattern_passes_per_s": round(K * (iters + halvings) / dt, 1),
         "mean_halvings": round(halvings / max(iters, 1), 3),
         "listed_fraction": round(nnz / px, 4),
+        "workspace_bytes": int(ws.numel()), "workspace_bytes_all_pixels_reserved": int(ws_full),
+        "phi_0": res.trace[0]["phi"] if res.trace else None,
         "final_phi": res.trace[-1]["phi"] if res.trace else None,
         "kernels": {k: {kk: (round(vv, 3) if isinstance(vv, float) else vv) for kk, vv in v.items() if kk != "kind"}
                     for k, v in kinds.items()},

@@ -100,9 +100,16 @@ typedef struct {
                            a polynomial in gamma whose coefficients are object sums
                            weighted by the illumination (object only) or patch sums
                            (joint); at n = 128 and 256 the far fields are stored for
-                           the d > 0 pixels only.  Needs 2 (joint: 3) extra k*n*n
-                           complex64 of workspace (ptyg_workspace_size counts it). */
+                           the d > 0 pixels only.  Needs 2 (joint: 3) extra far fields
+                           of workspace (ptyg_workspace_size counts them): k*n*n
+                           complex64 each, or max_listed of them at n = 128 and 256. */
   int32_t estimator;    /* PTYG_EST_ML or PTYG_EST_LS */
+  int64_t max_listed;   /* batched search at n = 128 and 256: capacity, in pixels, of the
+                           compacted far-field regions, which hold only the pixels with
+                           d > 0 (or NaN); < 0 reserves every pixel (k*n*n).  The
+                           ptyg_listed_count of the data is the exact need; a solve whose
+                           data list more pixels returns PTYG_E_WORKSPACE before it
+                           writes them.  Ignored elsewhere. */
 } ptyg_cg_opts;
 
 enum { PTYG_LS_SEQUENTIAL = 0, PTYG_LS_BATCHED = 1 };
@@ -131,6 +138,13 @@ const char* ptyg_last_error(void);
  * used by ptyg_cg_solve, and the stored far fields of the batched line search
  * when opts->line_search is PTYG_LS_BATCHED. */
 size_t ptyg_workspace_size(const ptyg_dims* dims, const ptyg_cg_opts* opts);
+
+/* Number of pixels with d > 0 (or NaN) in data [k][n][n]: the listed pixels
+ * whose far fields the batched line search stores (the others enter through
+ * a polynomial in the step).  Synchronises `stream`; -1 on an error.  Uses a
+ * counter inside the library (one per GPU): concurrent counts on one GPU
+ * race. */
+int64_t ptyg_listed_count(const ptyg_dims* dims, const float* data, ptyg_stream_t stream);
 
 /* Checks that every scan position keeps its patch inside the object.
  * Synchronises `stream`.  Returns PTYG_OK or PTYG_E_BOUNDS. */
@@ -227,14 +241,15 @@ ptyg_status ptyg_cg_solve_views(const ptyg_dims* dims, int32_t views, ptyg_c64* 
 /* Opt-in kernel timing for benchmarks: the fused GRAD kernel (kind 0), the
  * line-search kernel (kind 1: a MINFUNC pass, or a batched pass over stored
  * far fields), the forward transform of the search direction of the batched
- * line search (kind 2) and the ordered overlap sum of the object gradient
- * (kind 3) launched by the solver and the GRAD call can be bracketed by HIP
- * events on their stream.  `kinds_mask`: bit k times kind k (0 turns timing
+ * line search (kind 2), the ordered overlap sum of the object gradient
+ * (kind 3) and the whole GRAD stage -- transform kernel, overlap sum and
+ * reductions, without the tile lists (kind 4) -- launched by the solver and
+ * the GRAD call can be bracketed by HIP events on their stream.  `kinds_mask`: bit k times kind k (0 turns timing
  * off, -1 times every kind); each recorded event pair adds a few
  * microseconds between launches, so a timed run should time only the kinds
  * it reports.  ptyg_timing_read waits for the recorded events and returns,
  * per kind, the total elapsed milliseconds and the number of launches since
- * the last reset (arrays of `kinds` entries, kinds <= 4).  Timing is per
+ * the last reset (arrays of `kinds` entries, kinds <= 5).  Timing is per
  * process and not thread-safe. */
 void ptyg_timing_enable(int32_t kinds_mask);
 void ptyg_timing_reset(void);

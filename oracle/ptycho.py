@@ -245,15 +245,19 @@ def dai_yuan_beta(g_new, g_old, eta_old):
 
 
 def line_search(phi_of_gamma, phi_m: float, gamma0: float = 1.0,
-                tau: float = 0.5, t: float = 0.0, lmax: int = 40):
+                tau: float = 0.5, t: float = 0.0, lmax: int = 40, values=None):
     """Backtracking of Eq. linesearch in Algorithm 1's order: gamma <- tau
     gamma, evaluate, until F(psi + gamma eta) <= F(psi) + gamma t.
 
-    Returns (gamma, trials, accepted); if `lmax` trials fail, gamma = 0."""
+    Returns (gamma, trials, accepted); if `lmax` trials fail, gamma = 0.
+    values (optional list): receives every trial's objective, in order."""
     gamma = gamma0
     for j in range(1, lmax + 1):
         gamma = gamma * tau
-        if phi_of_gamma(gamma) <= phi_m + gamma * t:
+        phi_t = phi_of_gamma(gamma)
+        if values is not None:
+            values.append(phi_t)
+        if phi_t <= phi_m + gamma * t:
             return gamma, j, True
     return 0.0, lmax, False
 
@@ -269,7 +273,8 @@ def cg_solve(obj0, probe0, pos, d, iters: int, gamma0: float = 1.0,
     -> LS (Eq. linesearch) -> Update (Eq. update).  Object only (the paper)
     or joint object+probe.  Returns (obj, probe, trace) with one trace row
     per iteration: phi, f (at psi_m), gamma, halvings, beta, step_norm
-    (||psi_{m+1} - psi_m||, the paper's convergence 2-norm), restarted.
+    (||psi_{m+1} - psi_m||, the paper's convergence 2-norm), restarted, and
+    trial_phis (the objective of every line-search trial, in order).
     callback (optional): called as callback(m + 1, obj, probe) after each
     update, for recording iterates; it must not modify them."""
     x = [np.array(obj0, dtype=np.complex128)]
@@ -304,13 +309,14 @@ def cg_solve(obj0, probe0, pos, d, iters: int, gamma0: float = 1.0,
             oo, pp = unpack([b + gamma * e for b, e in zip(x, eta)])
             return minfunc(oo, pp, pos, d, eps, estimator)[0]
 
-        gamma, trials, accepted = line_search(phi_of_gamma, phi_m, gamma0, tau, t, lmax)
+        trial_values = []
+        gamma, trials, accepted = line_search(phi_of_gamma, phi_m, gamma0, tau, t, lmax, trial_values)
         # Update stage
         x = [b + gamma * e for b, e in zip(x, eta)]
         step = gamma * math.sqrt(sum(inner(e, e).real for e in eta))
         trace.append({"phi": phi_m, "f": res["f"], "gamma": gamma,
                       "halvings": trials, "beta": beta, "step_norm": step,
-                      "restarted": bool(restarted)})
+                      "restarted": bool(restarted), "trial_phis": trial_values})
         g_old = g_new
         restart = not accepted
         if callback is not None:

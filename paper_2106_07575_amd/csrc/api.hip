@@ -73,13 +73,17 @@ struct Layout {
       total;
   size_t nz_blocks, z_blocks;
   size_t n_partials;
+  int64_t listed_cap;  // batched search: listed elements the compacted regions hold
 };
 
 // The regions of the batched line search come last, so the offsets of the
 // others do not depend on it.
 // `views`: the multi-view solver's stacked layout (no illumination or
 // compacted far fields).
-Layout layout(const ptyg_dims* d, bool joint, bool batched = false, bool views = false) {
+// `listed`: capacity for the elements with d > 0 (or NaN) that the batched
+// search stores compacted (n = 128 and 256, single solve); < 0 means every
+// element.
+Layout layout(const ptyg_dims* d, bool joint, bool batched = false, bool views = false, int64_t listed = -1) {
   Layout L{};
   const size_t obj_n = (size_t)d->obj_h * d->obj_w;
   const size_t probe_n = (size_t)d->n * d->n;
@@ -122,6 +126,10 @@ Layout layout(const ptyg_dims* d, bool joint, bool batched = false, bool views =
   L.nz_blocks = L.z_blocks = 0;
   if (batched) {
     const size_t elems = (size_t)d->k * probe_n;
+    // compacted stores: far fields, indices and intensities of the listed
+    // elements only, so those regions scale with the listed count
+    const bool compact = !views && (d->n == 128 || d->n == 256);
+    const size_t cap = (compact && listed >= 0 && (size_t)listed < elems) ? (size_t)listed : elems;
     L.nz_blocks = (elems + kNzChunk - 1) / kNzChunk;
     L.z_blocks = (size_t)fwd_t_blocks(d->n, d->k);
     L.nz_counts = o;
@@ -129,7 +137,7 @@ Layout layout(const ptyg_dims* d, bool joint, bool batched = false, bool views =
     L.nz_offsets = o;
     o = align_up(o + (L.nz_blocks + 1) * sizeof(int));
     L.nz_idx = o;
-    o = align_up(o + elems * sizeof(int));
+    o = align_up(o + std::max<size_t>(cap, 1) * sizeof(int));
     // GRAD sums of |G psi|^2 (one per block), then the rows of the direction
     // sums (object only the DIR kernel's, joint the patch sums')
     L.zparts = o;
@@ -137,7 +145,7 @@ Layout layout(const ptyg_dims* d, bool joint, bool batched = false, bool views =
                                           2 * (size_t)patch_sums_blocks(d->k, d->n)});
     o = align_up(o + (L.n_partials + rows * 4) * sizeof(double));
     L.zsums = L.scalars + kZsSlot * sizeof(double);
-    const size_t far_bytes = (size_t)d->k * probe_n * sizeof(float2);
+    const size_t far_bytes = std::max<size_t>(cap, 1) * sizeof(float2);
     L.far_a = o;
     o = align_up(o + far_bytes);
     L.far_b = o;
@@ -162,16 +170,21 @@ Layout layout(const ptyg_dims* d, bool joint, bool batched = false, bool views =
       L.nz_seg = o;
       o = align_up(o + elems / 32 * sizeof(uint2));
       L.nz_dc = o;
-      o = align_up(o + elems * sizeof(float));
+      o = align_up(o + std::max<size_t>(cap, 1) * sizeof(float));
     }
   }
   L.total = o;
+  L.listed_cap = batched ? (int64_t)((!views && (d->n == 128 || d->n == 256) && listed >= 0 &&
+                                      listed < (int64_t)d->k * d->n * d->n)
+                                         ? listed
+                                         : (int64_t)d->k * d->n * d->n)
+                         : 0;
   return L;
 }
 
 ptyg_status check_ws(const ptyg_dims* d, void* ws, size_t ws_bytes, bool joint, Layout* out,
-                     bool batched = false) {
-  *out = layout(d, joint, batched);
+                     bool batched = false, int64_t listed = -1) {
+  *out = layout(d, joint, batched, false, listed);
   if (!ws) return fail(PTYG_E_INVAL, "workspace is NULL");
   if (((uintptr_t)ws) % kAlign) return fail(PTYG_E_INVAL, "workspace not 256-byte aligned");
   if (ws_bytes < out->total)
@@ -205,8 +218,9 @@ struct Timing {
   };
   std::vector<Rec> pending;
   std::vector<hipEvent_t> pool;
-  double ms[4] = {0.0, 0.0, 0.0, 0.0};
-  int count[4] = {0, 0, 0, 0};
+  static constexpr int kKinds = 5;
+  double ms[kKinds] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  int count[kKinds] = {0, 0, 0, 0, 0};
   hipEvent_t get() {
     if (!pool.empty()) {
       hipEvent_t e = pool.back();
@@ -266,11 +280,14 @@ struct TimedLaunch {
   }
 };
 
+// Counter of ptyg_listed_count (one per GPU; concurrent counts on one GPU race).
+static __device__ unsigned long long listed_counter;
+
 }  // namespace
 
 extern "C" {
 
-int32_t ptyg_abi_version(void) { return 4; }
+int32_t ptyg_abi_version(void) { return 5; }
 
 const char* ptyg_status_string(ptyg_status s) {
   switch (s) {
@@ -292,7 +309,31 @@ size_t ptyg_workspace_size(const ptyg_dims* dims, const ptyg_cg_opts* opts) {
     fail(PTYG_E_INVAL, "line_search=%d is not a PTYG_LS_* value", opts->line_search);
     return 0;
   }
-  return layout(dims, opts && opts->update_probe, opts && opts->line_search == PTYG_LS_BATCHED).total;
+  return layout(dims, opts && opts->update_probe, opts && opts->line_search == PTYG_LS_BATCHED, false,
+                opts ? opts->max_listed : -1)
+      .total;
+}
+
+int64_t ptyg_listed_count(const ptyg_dims* dims, const float* data, ptyg_stream_t stream) {
+  if (check_dims(dims) != PTYG_OK) return -1;
+  if (!data) {
+    fail(PTYG_E_INVAL, "data is NULL");
+    return -1;
+  }
+  unsigned long long* cnt = nullptr;
+  if (hipGetSymbolAddress((void**)&cnt, HIP_SYMBOL(listed_counter)) != hipSuccess || !cnt) {
+    fail(PTYG_E_HIP, "hipGetSymbolAddress(listed_counter): %s", hipGetErrorString(hipGetLastError()));
+    return -1;
+  }
+  const hipStream_t s = S(stream);
+  unsigned long long h = 0;
+  if (launch_count_listed(data, (int64_t)dims->k * dims->n * dims->n, cnt, s) != hipSuccess ||
+      hipMemcpyAsync(&h, cnt, sizeof(h), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess) {
+    fail(PTYG_E_HIP, "counting the listed pixels: %s", hipGetErrorString(hipGetLastError()));
+    return -1;
+  }
+  return (int64_t)h;
 }
 
 ptyg_status ptyg_check_positions(const ptyg_dims* dims, const int32_t* pos, void* ws, size_t ws_bytes,
@@ -382,6 +423,8 @@ ptyg_status run_grad(const ptyg_dims* dims, const float2* obj, const float2* pro
   // conj(p) folded into the stored waves unless the probe gradient needs them plain
   a.premul = !grad_probe && dims->n <= 128;
   int nb = 0;
+  // kind 4: the whole GRAD stage (transform kernel, overlap sum, reductions)
+  TimedLaunch tl_unit(4, s);
   if (far_in) {
     // test hook: the far field is given (row layout)
     a.far = const_cast<float2*>(far_in);
@@ -493,7 +536,7 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
   const bool joint = opts->update_probe != 0;
   const bool batched = opts->line_search == PTYG_LS_BATCHED;
   Layout L;
-  if (ptyg_status st = check_ws(dims, ws, ws_bytes, joint, &L, batched)) return st;
+  if (ptyg_status st = check_ws(dims, ws, ws_bytes, joint, &L, batched, opts->max_listed)) return st;
   if (iters_done) *iters_done = 0;
   if (ptyg_status st = ptyg_check_positions(dims, pos_i, ws, ws_bytes, stream)) return st;
 
@@ -533,21 +576,32 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
   // trial; the d <= 0 ones through the zero-pixel sums
   int64_t nnz = 0;
   if (batched) {
+    // count the listed elements first: the compacted regions hold at most
+    // L.listed_cap of them
     int* offs = at<int>(ws, L.nz_offsets);
-    PTYG_HIP(launch_nz_compact(dt, (int64_t)dims->k * dims->n * dims->n, at<int>(ws, L.nz_counts), offs,
-                               at<int>(ws, L.nz_idx), cseg, dcomp, s));
+    const int64_t elems = (int64_t)dims->k * dims->n * dims->n;
+    PTYG_HIP(launch_nz_count(dt, elems, at<int>(ws, L.nz_counts), offs, s));
     int h_nnz = 0;
     PTYG_HIP(hipMemcpyAsync(&h_nnz, offs + L.nz_blocks, sizeof(int), hipMemcpyDeviceToHost, s));
     PTYG_HIP(hipStreamSynchronize(s));
     nnz = h_nnz;
+    if (nnz > L.listed_cap)
+      return fail(PTYG_E_WORKSPACE, "the data list %lld pixels with d > 0 but the workspace was sized for %lld "
+                  "(opts->max_listed)", (long long)nnz, (long long)L.listed_cap);
+    PTYG_HIP(launch_nz_fill(dt, elems, offs, at<int>(ws, L.nz_idx), cseg, dcomp, s));
   }
 
   // scalar slots
   enum {
     PHI = 0, FEQ = 1, N1O = 2, N2O = 3, N1P = 4, N2P = 5, N3O = 6, EEO = 7, N3P = 8, EEP = 9,
     PHIT = 10,  // a trial's (Phi, F): two slots
-    BETA = 12, RST = 13, NSC = 14
+    BETA = 12, RST = 13,
+    DCONST = 15  // sum over d > 0 of d - d log d: Eq. ML's F = Phi + this
   };
+  // the GRAD passes form the deviance only; Eq. ML's value for the trace is
+  // Phi plus the data constant, summed once here and read back with the
+  // first iteration's scalars
+  PTYG_HIP(launch_data_const(dt, (int64_t)dims->k * dims->n * dims->n, 1, partials, sc + DCONST, s));
   double* h = readback_buffer();
   if (!h) return fail(PTYG_E_HIP, "pinned readback buffer: %s", hipGetErrorString(hipGetLastError()));
   struct EventGuard {
@@ -635,7 +689,7 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
     bool restarted = true, stop = false;
     auto take_scalars = [&]() -> ptyg_status {
       phi_m = h[PHI];
-      f_m = h[FEQ];
+      f_m = phi_m + h[DCONST];
       beta = h[BETA];
       restarted = h[RST] != 0.0;
       if (!std::isfinite(phi_m)) return fail(PTYG_E_NONFINITE, "objective is %g at iteration %d", phi_m, m);
@@ -784,7 +838,7 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
       if (ptyg_status st = run_minfunc(dims, obj, eta_o, probe, eta_p, gamma, pos, dt, DataLayout::Transposed,
                                        eps, est, sc + PHIT, ws, L, s))
         return st;
-      PTYG_HIP(hipMemcpyAsync(h, sc, NSC * sizeof(double), hipMemcpyDeviceToHost, s));
+      PTYG_HIP(hipMemcpyAsync(h, sc, (DCONST + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
       PTYG_HIP(hipStreamSynchronize(s));
       if (j == 1) {
         if (ptyg_status st = take_scalars()) return st;
@@ -997,6 +1051,11 @@ ptyg_status ptyg_cg_solve_views(const ptyg_dims* dims, int32_t views, ptyg_c64* 
     PTYG_HIP(launch_nz_compact(dt, pe * V, at<int>(ws, L.nz_counts), at<int>(ws, L.nz_offsets), at<int>(ws, L.nz_idx),
                                nullptr, nullptr, s));
 
+  // per-view data constants: Eq. ML's F = Phi + sum over d > 0 of d - d log d
+  std::vector<double> dconst(V, 0.0);
+  PTYG_HIP(launch_data_const(dt, pe, V, at<double>(ws, VL.vparts), at<double>(ws, VL.vout), s));
+  PTYG_HIP(hipMemcpyAsync(dconst.data(), at<double>(ws, VL.vout), V * sizeof(double), hipMemcpyDeviceToHost, s));
+  PTYG_HIP(hipStreamSynchronize(s));
   // per-view state
   std::vector<double> h((size_t)V * 32), hbeta(V, 0.0), halpha(V, 0.0), phi_m(V), f_m(V), n3_prev(V, 0.0);
   std::vector<double> lsrow((size_t)V * kLsRow), zc((size_t)V * 3);
@@ -1022,7 +1081,7 @@ ptyg_status ptyg_cg_solve_views(const ptyg_dims* dims, int32_t views, ptyg_c64* 
     PTYG_HIP(hipStreamSynchronize(s));
     for (int v = 0; v < V; ++v) {
       phi_m[v] = pf[2 * v];
-      f_m[v] = pf[2 * v + 1];
+      f_m[v] = phi_m[v] + dconst[v];
       if (!std::isfinite(phi_m[v]))
         return fail(PTYG_E_NONFINITE, "objective is %g at iteration %d of view %d", phi_m[v], m, v);
       double beta = 0.0;
@@ -1190,18 +1249,18 @@ ptyg_status ptyg_cg_solve_views(const ptyg_dims* dims, int32_t views, ptyg_c64* 
   return PTYG_OK;
 }
 
-void ptyg_timing_enable(int32_t kinds_mask) { g_timing.mask = kinds_mask & 0xF; }
+void ptyg_timing_enable(int32_t kinds_mask) { g_timing.mask = kinds_mask & 0x1F; }
 
 void ptyg_timing_reset(void) {
   g_timing.drain();
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < Timing::kKinds; ++i) {
     g_timing.ms[i] = 0.0;
     g_timing.count[i] = 0;
   }
 }
 
 ptyg_status ptyg_timing_read(double* ms, int32_t* count, int32_t kinds) {
-  if (!ms || !count || kinds < 0 || kinds > 4) return fail(PTYG_E_INVAL, "bad timing arguments");
+  if (!ms || !count || kinds < 0 || kinds > Timing::kKinds) return fail(PTYG_E_INVAL, "bad timing arguments");
   g_timing.drain();
   for (int i = 0; i < kinds; ++i) {
     ms[i] = g_timing.ms[i];

@@ -427,7 +427,7 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
   // out before the G psi stores (a load waits for every earlier store)
   float dn[kResChunk];
 #pragma unroll
-  for (int j = 0; j < kResChunk; ++j) dn[j] = load_data<N, LAY>(a.data, k, L, j);
+  for (int j = 0; j < kResChunk; ++j) dn[j] = load_data<N, LAY>(a.data, k, L, kOrd<N>.s[j]);
   if constexpr (SG) {
     // G psi for the batched line search, in the element order of the
     // transposed intensities, with sum |G psi|^2.  All stores go out before
@@ -446,6 +446,9 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
     }
     __builtin_amdgcn_sched_barrier(0);
   }
+  // Eq. ML's F only for the API call (row layout); the solver forms it from
+  // Phi and the data constant
+  constexpr bool WANT_F = LAY == DataLayout::Rows;
 #pragma unroll
   for (int c = 0; c < G::E; c += kResChunk) {
     __builtin_amdgcn_sched_barrier(0);
@@ -454,17 +457,17 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
     for (int j = 0; j < kResChunk; ++j) dc[j] = dn[j];
     if (c + kResChunk < G::E) {
 #pragma unroll
-      for (int j = 0; j < kResChunk; ++j) dn[j] = load_data<N, LAY>(a.data, k, L, c + kResChunk + j);
+      for (int j = 0; j < kResChunk; ++j) dn[j] = load_data<N, LAY>(a.data, k, L, kOrd<N>.s[c + kResChunk + j]);
     }
 #pragma unroll
     for (int j = 0; j < kResChunk; ++j) {
-      const int s = c + j;
+      const int s = kOrd<N>.s[c + j];
       const float2 g = SG ? v[s] : cscale(v[s], invN);
       const float x = fmaf(g.x, g.x, g.y * g.y);
       float phi, ft, fac;
-      pixel_terms<true, EST>(x, dc[j], a.eps, phi, ft, fac);
+      pixel_terms<WANT_F, EST>(x, dc[j], a.eps, phi, ft, fac);
       acc_phi += (double)phi;
-      acc_f += (double)ft;
+      if constexpr (WANT_F) acc_f += (double)ft;
       v[s] = cscale(g, fac * invN);
     }
   }
@@ -525,7 +528,9 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_minfunc(PatArgs a) {
   // intensities one chunk ahead (as in GRAD)
   float dn[kResChunk];
 #pragma unroll
-  for (int j = 0; j < kResChunk; ++j) dn[j] = load_data<N, LAY>(a.data, k, L, j);
+  for (int j = 0; j < kResChunk; ++j) dn[j] = load_data<N, LAY>(a.data, k, L, kOrd<N>.s[j]);
+  // the solver's line search (transposed intensities) needs only Phi
+  constexpr bool WANT_F = LAY == DataLayout::Rows;
 #pragma unroll
   for (int c = 0; c < G::E; c += kResChunk) {
     __builtin_amdgcn_sched_barrier(0);
@@ -534,15 +539,13 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_minfunc(PatArgs a) {
     for (int j = 0; j < kResChunk; ++j) dc[j] = dn[j];
     if (c + kResChunk < G::E) {
 #pragma unroll
-      for (int j = 0; j < kResChunk; ++j) dn[j] = load_data<N, LAY>(a.data, k, L, c + kResChunk + j);
+      for (int j = 0; j < kResChunk; ++j) dn[j] = load_data<N, LAY>(a.data, k, L, kOrd<N>.s[c + kResChunk + j]);
     }
 #pragma unroll
     for (int j = 0; j < kResChunk; ++j) {
-      const float2 g = cscale(v[c + j], invN);
+      const float2 g = cscale(v[kOrd<N>.s[c + j]], invN);
       const float x = fmaf(g.x, g.x, g.y * g.y);
       float phi, ft, fac;
-      // the solver's line search (transposed intensities) needs only Phi
-      constexpr bool WANT_F = LAY == DataLayout::Rows;
       pixel_terms<WANT_F, EST>(x, dc[j], a.eps, phi, ft, fac);
       acc_phi += (double)phi;
       if constexpr (WANT_F) acc_f += (double)ft;
@@ -896,6 +899,25 @@ __global__ __launch_bounds__(kVecWG) void k_fill_i32(int* x, int64_t n, int valu
     x[i] = value;
 }
 
+// Per-block sums of d - d log d over the d > 0 elements (NaN propagates) of
+// segment blockIdx.y (n elements each), FP64: the constant between Eq. ML
+// and its deviance form.
+__global__ __launch_bounds__(kVecWG) void k_data_const(const float* __restrict__ d, int64_t n,
+                                                        double* __restrict__ partials) {
+  __shared__ double red[2 * (kVecWG / 64)];
+  const float* ds = d + (int64_t)blockIdx.y * n;
+  double acc = 0.0, unused = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * kVecWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVecWG) {
+    const float v = ds[i];
+    if (!(v <= 0.0f)) {
+      const double dv = v;
+      acc += dv - dv * log(dv);
+    }
+  }
+  block_sum2<kVecWG>(acc, unused, red);
+  if (threadIdx.x == 0) partials[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = acc;
+}
+
 __global__ __launch_bounds__(kVecWG) void k_dot2(VecArgs v) {
   __shared__ double red[2 * (kVecWG / 64)];
   double s1 = 0.0, s2 = 0.0;
@@ -972,8 +994,11 @@ __global__ void k_dy_beta(double* sc, int n1, int n2, int n3, int joint_off, int
   sc[rst] = ok ? 0.0 : 1.0;
 }
 
+// A zero step leaves `a` untouched (also when c holds NaN: the solver's
+// device-side update after a search that accepted nothing).
 __global__ __launch_bounds__(kVecWG) void k_axpy(VecArgs v) {
   const float al = (float)(v.alpha_dev ? *v.alpha_dev : v.alpha);
+  if (al == 0.0f) return;
   for (int64_t i = (int64_t)blockIdx.x * kVecWG + threadIdx.x; i < v.n; i += (int64_t)gridDim.x * kVecWG) {
     const float2 x = v.a[i], c = v.c[i];
     v.a[i] = make_float2(fmaf(al, c.x, x.x), fmaf(al, c.y, x.y));
@@ -1028,7 +1053,7 @@ __global__ __launch_bounds__(256) void k_ls_batch(LsArgs a) {
           xi = fmaf(g2, cv.y, xi);
         }
         float phi, ft, fac;
-        pixel_terms<false, EST>(fmaf(xr, xr, xi * xi), dv, a.eps, phi, ft, fac);
+        pixel_terms_br<false, EST>(fmaf(xr, xr, xi * xi), dv, a.eps, phi, ft, fac);
         acc[j] += (double)phi;
       }
     }
@@ -1262,6 +1287,7 @@ __global__ __launch_bounds__(kVecWG) void k_dir_views(const float2* a, float2* b
 __global__ __launch_bounds__(kVecWG) void k_axpy_views(float2* a, const float2* c, const double* alpha, int64_t n) {
   const int v = blockIdx.y;
   const float al = (float)alpha[v];
+  if (al == 0.0f) return;  // a zero step leaves the view untouched
   float2* av = a + (size_t)v * n;
   const float2* cv = c + (size_t)v * n;
   for (int64_t i = (int64_t)blockIdx.x * kVecWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVecWG) {
@@ -1319,7 +1345,7 @@ __global__ __launch_bounds__(256) void k_ls_batch_views(LsArgs a, const int* off
           xi = fmaf(g2, cv.y, xi);
         }
         float phi, ft, fac;
-        pixel_terms<false, EST>(fmaf(xr, xr, xi * xi), dv, a.eps, phi, ft, fac);
+        pixel_terms_br<false, EST>(fmaf(xr, xr, xi * xi), dv, a.eps, phi, ft, fac);
         acc[j] += (double)phi;
       }
     }
@@ -1533,6 +1559,50 @@ int fwd_t_blocks(int N, int K) {
   return nb;
 }
 
+hipError_t launch_nz_count(const float* d, int64_t n, int* counts, int* offsets, hipStream_t s) {
+  if (!d || !counts || !offsets || n < 1) return hipErrorInvalidValue;
+  const int64_t blocks = (n + kNzChunk - 1) / kNzChunk;
+  if (blocks > (1 << 30)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_nz_count, dim3((unsigned)blocks), dim3(256), 0, s, d, n, counts);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, (int)blocks, offsets);
+  return hipGetLastError();
+}
+
+hipError_t launch_nz_fill(const float* d, int64_t n, const int* offsets, int* idx, uint2* seg, float* dc,
+                          hipStream_t s) {
+  if (!d || !offsets || !idx || n < 1) return hipErrorInvalidValue;
+  if (seg && n % 32) return hipErrorInvalidValue;
+  const int64_t blocks = (n + kNzChunk - 1) / kNzChunk;
+  if (blocks > (1 << 30)) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_nz_fill, dim3((unsigned)blocks), dim3(256), 0, s, d, n, offsets, idx, seg, dc);
+  return hipGetLastError();
+}
+
+// Number of elements with !(d <= 0), accumulated into *out (zeroed first).
+__global__ __launch_bounds__(256) void k_count_listed(const float* __restrict__ d, int64_t n,
+                                                       unsigned long long* out) {
+  __shared__ unsigned long long red[4];
+  unsigned long long c = 0;
+  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < n; i += (int64_t)gridDim.x * 256)
+    c += !(d[i] <= 0.0f) ? 1ull : 0ull;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) atomicAdd(out, red[0] + red[1] + red[2] + red[3]);
+}
+
+__global__ void k_zero_u64(unsigned long long* x) { *x = 0ull; }
+
+hipError_t launch_count_listed(const float* d, int64_t n, unsigned long long* out, hipStream_t s) {
+  if (!d || !out || n < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(1), 0, s, out);
+  const int64_t want = (n + 255) / 256;
+  const int nb = (int)(want < 2048 ? want : 2048);
+  hipLaunchKernelGGL(k_count_listed, dim3(nb), dim3(256), 0, s, d, n, out);
+  return hipGetLastError();
+}
+
 hipError_t launch_nz_compact(const float* d, int64_t n, int* counts, int* offsets, int* idx, uint2* seg,
                              float* dc, hipStream_t s) {
   if (!d || !counts || !offsets || !idx || n < 1) return hipErrorInvalidValue;
@@ -1744,6 +1814,13 @@ hipError_t launch_finalize_views(const double* partials, int N, int K, int k_per
   hipLaunchKernelGGL(k_finalize_views, dim3(views), dim3(256), 0, s, partials, nb, groups, ppw, k_per_view, width,
                      out);
   return hipGetLastError();
+}
+
+hipError_t launch_data_const(const float* d, int64_t n, int segs, double* partials, double* out, hipStream_t s) {
+  if (!d || !partials || !out || n < 1 || segs < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_data_const, dim3(kSegBlocks, segs), dim3(kVecWG), 0, s, d, n, partials);
+  if (hipError_t e = hipGetLastError()) return e;
+  return launch_finalize_seg(partials, kSegBlocks, 1, segs, out, s);
 }
 
 hipError_t launch_dot2_views(const float2* a, const float2* b, int64_t n, int views, double* partials,

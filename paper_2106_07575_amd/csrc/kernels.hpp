@@ -179,6 +179,14 @@ hipError_t launch_patch_sums(const float2* obj, const float2* eta, const float2*
 // record per 32 elements; dc (nullable): the listed d values, compacted.
 hipError_t launch_nz_compact(const float* d, int64_t n, int* counts, int* offsets, int* idx, uint2* seg,
                              float* dc, hipStream_t s);
+// The two halves of launch_nz_compact: the per-chunk counts and their scan
+// (offsets[blocks] = total), then the fill.
+hipError_t launch_nz_count(const float* d, int64_t n, int* counts, int* offsets, hipStream_t s);
+hipError_t launch_nz_fill(const float* d, int64_t n, const int* offsets, int* idx, uint2* seg, float* dc,
+                          hipStream_t s);
+// *out = number of elements with !(d <= 0) (d > 0 or NaN); out is zeroed
+// by a kernel first.
+hipError_t launch_count_listed(const float* d, int64_t n, unsigned long long* out, hipStream_t s);
 // Zero-pixel sums of the direction forward: rows of 4 doubles per block.
 int fwd_t_blocks(int N, int K);
 
@@ -200,6 +208,10 @@ hipError_t launch_dir_views(const float2* a, float2* b, const double* beta, int6
                             double* partials, hipStream_t s);
 hipError_t launch_axpy_views(float2* a, const float2* c, const double* alpha, int64_t n, int views,
                              hipStream_t s);
+// out[v] = sum over the d > 0 elements of segment v (n elements each) of
+// d - d log d, in FP64 (F = Phi + this constant); partials holds
+// segs * kSegBlocks doubles.
+hipError_t launch_data_const(const float* d, int64_t n, int segs, double* partials, double* out, hipStream_t s);
 // out[v][0..width) = ordered sums of rows [v][0..rows) of `width` doubles.
 hipError_t launch_finalize_seg(const double* partials, int rows, int width, int views, double* out,
                                hipStream_t s);

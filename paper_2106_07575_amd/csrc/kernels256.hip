@@ -257,9 +257,10 @@ __global__ __launch_bounds__(256) void k_combine(PatArgs a, int64_t items) {
         }
         const float x = fmaf(g[j].x, g[j].x, g[j].y * g[j].y);
         float phi, ft, fac;
-        pixel_terms<RES || LAY == DataLayout::Rows, EST>(x, d, a.eps, phi, ft, fac);
+        // F for the row-layout API calls only (the solver forms it from Phi)
+        pixel_terms<LAY == DataLayout::Rows, EST>(x, d, a.eps, phi, ft, fac);
         acc_phi += (double)phi;
-        if constexpr (RES || LAY == DataLayout::Rows) acc_f += (double)ft;
+        if constexpr (LAY == DataLayout::Rows) acc_f += (double)ft;
         r[j] = cscale(g[j], fac);
       }
       if constexpr (MODE == 4) {

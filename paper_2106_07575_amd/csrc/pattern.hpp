@@ -64,6 +64,19 @@ struct FreqTable {
 template <int N>
 inline constexpr FreqTable<N> kFreq{};
 
+// Slots in ascending order of their base frequency: the residual loops take
+// pixels in this order, four at a time, so a chunk's intensity loads in the
+// row layout (one row per lane) fall in one cache line per lane.
+template <int N>
+struct SlotOrder {
+  int s[Geo<N>::E];
+  constexpr SlotOrder() : s() {
+    for (int i = 0; i < Geo<N>::E; ++i) s[i] = slot_of_freq(Geo<N>::E, i);
+  }
+};
+template <int N>
+inline constexpr SlotOrder<N> kOrd{};
+
 template <int N>
 __device__ __forceinline__ int fidx(int s, bool h) {
   if constexpr (Geo<N>::TPC == 1) return kFreq<N>.f[s];

@@ -38,7 +38,7 @@ class CgOpts(ctypes.Structure):
                 ("gamma0", ctypes.c_double), ("tau", ctypes.c_double), ("t", ctypes.c_double),
                 ("max_halvings", ctypes.c_int32), ("eps", ctypes.c_double),
                 ("target_phi", ctypes.c_double), ("line_search", ctypes.c_int32),
-                ("estimator", ctypes.c_int32)]
+                ("estimator", ctypes.c_int32), ("max_listed", ctypes.c_int64)]
 
 
 LINE_SEARCH = {"sequential": 0, "batched": 1}
@@ -59,6 +59,7 @@ _SIGS = {
     "ptyg_last_error": (ctypes.c_char_p, []),
     "ptyg_workspace_size": (ctypes.c_size_t, [ctypes.POINTER(Dims), ctypes.POINTER(CgOpts)]),
     "ptyg_check_positions": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, ctypes.c_size_t, _P]),
+    "ptyg_listed_count": (ctypes.c_int64, [ctypes.POINTER(Dims), _P, _P]),
     "ptyg_forward": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "ptyg_adjoint": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P, _P, _P, _P, ctypes.c_size_t, _P]),
     "ptyg_grad": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P, ctypes.c_float, ctypes.c_int32, _P, _P,
@@ -153,18 +154,35 @@ def dims_of(obj_shape, n: int, k: int) -> Dims:
     return Dims(int(obj_shape[0]), int(obj_shape[1]), int(n), int(k))
 
 
-def workspace_size(dims: Dims, update_probe: bool = False, line_search: str = "sequential") -> int:
+def listed_count(data, n: int) -> int:
+    """Pixels with d > 0 (or NaN) in data [k, n, n] (ptyg_listed_count)."""
+    data = _dev(data, "data", torch.float32)
+    d = Dims(n, n, n, data.numel() // (n * n))
+    c = load().ptyg_listed_count(ctypes.byref(d), _ptr(data), _stream())
+    if c < 0:
+        raise PtygError(-1, load().ptyg_last_error().decode())
+    return int(c)
+
+
+def workspace_size(dims: Dims, update_probe: bool = False, line_search: str = "sequential",
+                   max_listed: int = -1) -> int:
     o = CgOpts()
     o.update_probe = int(update_probe)
     o.line_search = LINE_SEARCH[line_search]
+    o.max_listed = int(max_listed)
     sz = load().ptyg_workspace_size(ctypes.byref(dims), ctypes.byref(o))
     if sz == 0:
         raise PtygError(-1, load().ptyg_last_error().decode())
     return sz
 
 
-def workspace(dims: Dims, device, update_probe: bool = False, line_search: str = "sequential") -> torch.Tensor:
-    return torch.empty(workspace_size(dims, update_probe, line_search), dtype=torch.uint8, device=device)
+def workspace(dims: Dims, device, update_probe: bool = False, line_search: str = "sequential",
+              max_listed: int = -1) -> torch.Tensor:
+    """Workspace for every call with these dims; for the batched search at
+    n = 128 / 256, max_listed >= 0 sizes its far fields for that many listed
+    pixels (listed_count of the data) instead of k*n*n."""
+    return torch.empty(workspace_size(dims, update_probe, line_search, max_listed), dtype=torch.uint8,
+                       device=device)
 
 
 def _common(obj, probe, pos):
@@ -251,19 +269,23 @@ class CgResult:
 def cg_solve(obj0, probe, pos, data, iters: int, update_probe: bool = False, gamma0: float = 1.0,
              tau: float = 0.5, t: float = 0.0, max_halvings: int = 40, eps: float = 1e-32,
              target_phi: float | None = None, ws=None, line_search: str = "sequential",
-             estimator: str = "ml") -> CgResult:
+             estimator: str = "ml", max_listed: int | None = None) -> CgResult:
     """ML-CG (Algorithm 1).  Works on copies of obj0 / probe.  line_search:
     "sequential" (one MINFUNC pass per trial) or "batched" (trials evaluated
     from stored far fields, up to 16 per pass; the workspace must then be
-    sized with the same line_search)."""
+    sized with the same line_search and max_listed).  max_listed: None
+    sizes a new workspace from listed_count(data); with a caller workspace
+    it must be the value that workspace was sized with (-1: every pixel)."""
     obj, probe_c, pos, d = _common(obj0, probe, pos)
     data = _dev(data, "data", torch.float32)
     obj = obj.clone()
     probe_c = probe_c.clone()
+    if max_listed is None:
+        max_listed = listed_count(data, d.n) if (line_search == "batched" and ws is None) else -1
     o = CgOpts(int(iters), int(update_probe), float(gamma0), float(tau), float(t), int(max_halvings),
                float(eps), -1.0 if target_phi is None else float(target_phi), LINE_SEARCH[line_search],
-               ESTIMATOR[estimator])
-    ws = workspace(d, obj.device, update_probe, line_search) if ws is None else ws
+               ESTIMATOR[estimator], int(max_listed))
+    ws = workspace(d, obj.device, update_probe, line_search, max_listed) if ws is None else ws
     trace = (IterStats * max(1, iters))()
     done = ctypes.c_int32(0)
     _check(load().ptyg_cg_solve(ctypes.byref(d), _ptr(obj), _ptr(probe_c), _ptr(pos), _ptr(data),
@@ -305,7 +327,7 @@ def cg_solve_views(obj0, probe, pos, data, iters: int, gamma0: float = 1.0, tau:
     k = data.shape[1]
     d = dims_of((H, W), probe.shape[0], k)
     o = CgOpts(int(iters), 0, float(gamma0), float(tau), float(t), int(max_halvings), float(eps), -1.0,
-               LINE_SEARCH[line_search], ESTIMATOR[estimator])
+               LINE_SEARCH[line_search], ESTIMATOR[estimator], -1)
     if ws is None:
         sz = load().ptyg_views_workspace_size(ctypes.byref(d), V, ctypes.byref(o))
         if sz == 0:
@@ -400,7 +422,7 @@ def debug_lane_swap(a, b):
     _check(load().ptyg_debug_lane_swap(_ptr(a), _ptr(b), _stream()))
 
 
-KERNEL_KINDS = ("grad", "minfunc", "dir_forward", "tile_sum")
+KERNEL_KINDS = ("grad", "minfunc", "dir_forward", "tile_sum", "grad_unit")
 
 
 def timing_enable(on: bool = True, kinds=None):
@@ -423,8 +445,9 @@ def timing_reset():
 
 def timing_read() -> dict:
     """{kind: (total ms, launches)} for the fused GRAD kernel, the line-search
-    kernel, the direction forward transform of the batched line search and
-    the ordered overlap sum of the object gradient."""
+    kernel, the direction forward transform of the batched line search, the
+    ordered overlap sum of the object gradient and the whole GRAD stage
+    (transform kernel + overlap sum + reductions)."""
     n = len(KERNEL_KINDS)
     ms = (ctypes.c_double * n)()
     cnt = (ctypes.c_int32 * n)()

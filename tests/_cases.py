@@ -135,6 +135,34 @@ def trajectory_factor(bound, floor):
     return max(1.0, bound / max(floor, 1e-300))
 
 
+def first_decision_flip(gpu_trace, oracle_trace):
+    """Index of the first iteration whose line-search decision (step and
+    accepted trial) differs between two traces, or None."""
+    for m, (a, b) in enumerate(zip(gpu_trace, oracle_trace)):
+        if a["gamma"] != b["gamma"] or a["halvings"] != b["halvings"]:
+            return m
+    return None
+
+
+def flip_is_a_tie(m, gpu_trace, oracle_trace, tol=1e-5):
+    """A decision that differs at iteration m is legitimate when it is a tie
+    within what the two trajectories already disagree on.  The larger of the
+    two accepted steps passed the sufficient-decrease test of Eq.
+    linesearch (t = 0: Phi(psi_m + g eta) <= Phi(psi_m)) on one side and
+    failed it on the other; it is a tie if the oracle's own trial objective
+    there (its trace keeps every trial's value) lies within
+    |Phi_gpu(m) - Phi_oracle(m)| + tol Phi_oracle(m) of Phi_oracle(m).
+    Returns (is_tie, margin, allowed)."""
+    a, b = gpu_trace[m], oracle_trace[m]
+    j = min(a["halvings"], b["halvings"])  # the trial one side accepted and the other rejected
+    vals = b["trial_phis"]
+    if j < 1 or j > len(vals):
+        return False, float("nan"), 0.0
+    margin = vals[j - 1] - b["phi"]
+    allowed = abs(a["phi"] - b["phi"]) + tol * b["phi"]
+    return abs(margin) <= allowed, margin, allowed
+
+
 def cg_with_floor(obj0, probe, pos, data, iters, **kw):
     """(oracle FP64 CG result, oracle CG result with FP32-rounded transforms)."""
     args = (obj0.astype(np.complex128), probe.astype(np.complex128), pos, data.astype(np.float64), iters)

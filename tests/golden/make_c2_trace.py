@@ -15,7 +15,7 @@ Two runs:
          far any FP32-transform solver can follow the FP64 one.
 
 Each output file holds the per-iteration trace (Phi, F, gamma, trial index,
-beta, step norm, restart) and the iterate on ten fixed 16 x 16 sample windows
+beta, step norm, restart, every line-search trial's objective) and the iterate on ten fixed 16 x 16 sample windows
 after iterations 1, 10 and 100, plus the illuminated-mask norm of the object
 after iterations 1, 2, 5, 10, 20, 50 and 100 and the phase-aligned masked error against
 the ground truth.
@@ -96,7 +96,8 @@ def main(kind: str) -> None:
         "window": WIN,
         "window_corners": WINDOWS,
         "mask_pixels": int(mask.sum()),
-        "trace": [{k: (bool(v) if k == "restarted" else (int(v) if k == "halvings" else float(v)))
+        "trace": [{k: (bool(v) if k == "restarted" else (int(v) if k == "halvings" else
+                       ([float(x) for x in v] if k == "trial_phis" else float(v))))
                    for k, v in row.items()} for row in trace],
         "snapshots": {str(m): snaps[m] for m in RECORD if m in snaps},
         "seconds": time.time() - t0,

@@ -32,7 +32,7 @@ def test_library_exports_every_declared_symbol():
     assert set(declared()) == set(ptyg.EXPORTS)
     # host-only calls work without a GPU
     lib = ptyg.load()
-    assert lib.ptyg_abi_version() == 4
+    assert lib.ptyg_abi_version() == 5
     d = ptyg.Dims(2048, 2048, 128, 4096)
     sz = ptyg.workspace_size(d)
     assert sz > 4096 * 128 * 128 * 4
@@ -94,3 +94,25 @@ def test_tile_list_buffers_are_length_checked():
     p = ctypes.cast(dummy, ctypes.c_void_p)
     assert lib.ptyg_ws_tile_lists(p, 4096, 2048, 2048, 64, p, T, p, cap, None) != 0
     assert lib.ptyg_ws_tile_lists(p, 4096, 2048, 2048, 64, p, T + 1, p, cap - 1, None) != 0
+
+
+def test_batched_workspace_scales_with_listed_pixels():
+    """The batched search's far fields are sized by the listed-pixel capacity
+    at n = 128 and 256 (host-only size queries, no GPU): at the large
+    one-GPU share (8192^2, 256^2 probe, 16384 patterns, about 5.3% of the
+    pixels with counts) its extra workspace stays under 8 GiB, against
+    three full far fields (24 GiB) when every pixel is reserved."""
+    from paper_2106_07575_amd import ptyg
+    if not os.path.exists(ptyg.lib_path()):
+        pytest.skip("libptyg.so not built")
+    d = ptyg.Dims(8192, 8192, 256, 16384)
+    px = 16384 * 256 * 256
+    seq = ptyg.workspace_size(d, update_probe=True)
+    full = ptyg.workspace_size(d, update_probe=True, line_search="batched")
+    listed = ptyg.workspace_size(d, update_probe=True, line_search="batched", max_listed=int(0.053 * px))
+    assert full - seq > 3 * px * 8
+    assert listed - seq < 8 * 2 ** 30
+    assert listed < full
+    # below 128 the far fields are stored whole: the capacity is ignored
+    s = ptyg.Dims(320, 320, 64, 49)
+    assert ptyg.workspace_size(s, line_search="batched", max_listed=10) == ptyg.workspace_size(s, line_search="batched")

@@ -8,11 +8,13 @@ object directions supported on four 192 x 192 windows (only the patterns
 touching a window change, so the oracle evaluates those alone) and probe
 directions -- against 2 Re <grad_W, v> = Re <torch grad, v>.  For Gaussian
 random directions the projections of the gradient and of its error have
-the same spread, so over the set of directions the relative L2 mismatch is
-the gradient's relative error: it must stay within 1.5x the gradient bound
-of _cases.grad_bound (1.5: the spread of a 16-sample ratio of norms) plus
-the finite differences' own truncation error, estimated per direction by
-the difference between steps h and 2h.  The gradient is also compared with
+the same spread (each Re <x, v> is normal with variance ||x||^2), so over
+M directions the relative L2 mismatch estimates the gradient's relative
+error up to a ratio of two chi-distributed norms: it must stay within the
+gradient bound of _cases.grad_bound times the 99.9% range of that ratio
+(3 for the 16 object directions, 4.5 for the 8 probe directions) plus the
+finite differences' own truncation error, estimated per direction from the
+difference between steps h and 2h.  The gradient is also compared with
 2x the oracle's Wirtinger gradient directly."""
 import numpy as np
 import pytest
@@ -80,7 +82,7 @@ def test_ml_loss_finite_differences_oracle(env):
             fds.append(c1)
             ans.append(np.vdot(gv, v).real)
             trunc.append(abs(c2 - c1) / 3.0)
-    for _ in range(4):
+    for _ in range(8):
         v = rng.standard_normal(p.shape) + 1j * rng.standard_normal(p.shape)
         h = 1e-6 * np.linalg.norm(p64) / np.linalg.norm(v)
         f = lambda t: O.minfunc(psi64, p64 + t * v, inp.pos, d64)[0]
@@ -98,8 +100,8 @@ def test_ml_loss_finite_differences_oracle(env):
     tp = np.linalg.norm(trunc[16:]) / np.linalg.norm(fds[16:])
     print(f"oracle FD vs autograd over random directions: object {eo:.2e} (gradient bound {bo:.2e}, FD "
           f"truncation {to:.1e}), probe {ep:.2e} (bound {bp:.2e}, truncation {tp:.1e})")
-    assert eo <= 1.5 * bo + to
-    assert ep <= 1.5 * bp + tp
+    assert eo <= 3.0 * bo + to
+    assert ep <= 4.5 * bp + tp
 
 
 def test_ml_loss_gradient_matches_oracle(env):

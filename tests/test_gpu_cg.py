@@ -183,3 +183,27 @@ def test_cg_joint_probe_256(P):
     assert gammas(res.trace) == gammas(rtr)
     assert eo <= max(1e-3, co * fo)
     assert ep <= max(1e-3, cp * fp)
+
+
+@pytest.mark.parametrize("ls", ["sequential", "batched"])
+def test_cg_nonfinite_leaves_caller_object_intact(P, ls):
+    """PTYG_E_NONFINITE from the C entry point on a caller-owned object: the
+    object (psi_0 here, since the objective is already NaN at it) must be
+    left as it was -- no update with a zero step times a NaN direction."""
+    import ctypes
+    cfg, inp, probe, obj, data = workload("c1")
+    bad = data.copy()
+    bad[2, 3, 4] = np.nan
+    o = dev(np.ones(obj.shape, np.complex64))
+    keep = o.clone()
+    pr, pos, d = dev(probe), dev(inp.pos), dev(bad)
+    dims = P.dims_of(obj.shape, probe.shape[0], inp.pos.shape[0])
+    ws = P.workspace(dims, o.device, line_search=ls)
+    opts = P.CgOpts(3, 0, 1.0, 0.5, 0.0, 40, 1e-32, -1.0, P.LINE_SEARCH[ls], 0, -1)
+    trace = (P.IterStats * 3)()
+    done = ctypes.c_int32(0)
+    st = P.load().ptyg_cg_solve(ctypes.byref(dims), P._ptr(o), P._ptr(pr), P._ptr(pos), P._ptr(d), ctypes.byref(opts),
+                                P._ptr(ws), ws.numel(), trace, ctypes.byref(done), P._stream())
+    torch.cuda.synchronize()
+    assert st == -4
+    assert torch.equal(o, keep)

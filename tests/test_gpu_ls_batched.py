@@ -105,7 +105,10 @@ def test_batched_object_within_fp32_floor(P, case, iters):
 @pytest.mark.parametrize("case", ["m32", "m64", "m128"])
 def test_batched_equals_sequential_steps(P, case):
     """Same workload, both GPU searches: identical step sequences over the
-    first iterations (before FP32 chaos can separate the trajectories)."""
+    first iterations (before FP32 chaos can separate the trajectories).  The
+    two trajectories are separate FP32 realisations (the GRAD variant that
+    stores G psi rounds in its own order), so their objectives agree to the
+    per-operator objective bar, 1e-5."""
     cfg, inp, probe, obj, data = workload(case)
     o0 = dev(np.ones(obj.shape, np.complex64))
     args = (o0, dev(probe), dev(inp.pos), dev(data), 4)
@@ -115,7 +118,7 @@ def test_batched_equals_sequential_steps(P, case):
     assert gammas(rs.trace) == gammas(rb.trace)
     assert [r["halvings"] for r in rs.trace] == [r["halvings"] for r in rb.trace]
     for a, b in zip(rs.trace, rb.trace):
-        assert abs(a["phi"] - b["phi"]) <= 1e-6 * abs(a["phi"])
+        assert abs(a["phi"] - b["phi"]) <= 1e-5 * abs(a["phi"])
 
 
 def test_batched_multi_pass_search(P):
@@ -223,3 +226,22 @@ def test_batched_nonfinite_data_is_reported(P):
     with pytest.raises(P.PtygError) as e:
         P.cg_solve(dev(np.ones(obj.shape, np.complex64)), dev(probe), dev(inp.pos), dev(bad), 2, line_search=B)
     assert e.value.status == -4
+
+
+def test_batched_workspace_sized_by_listed_count(P):
+    """n = 128: a workspace sized by the data's listed-pixel count solves as
+    the full one does; one pixel short is refused before anything is
+    written past it."""
+    cfg, inp, probe, obj, data = workload("m128")
+    nnz = P.listed_count(dev(data), cfg.n)
+    assert nnz == int(np.count_nonzero(~(data <= 0)))
+    d = P.dims_of(obj.shape, cfg.n, cfg.k)
+    args = (dev(np.ones(obj.shape, np.complex64)), dev(probe), dev(inp.pos), dev(data), 4)
+    full = P.cg_solve(*args, line_search=B, ws=P.workspace(d, torch.device("cuda"), line_search=B), max_listed=-1)
+    ws = P.workspace(d, torch.device("cuda"), line_search=B, max_listed=nnz)
+    tight = P.cg_solve(*args, line_search=B, ws=ws, max_listed=nnz)
+    assert torch.equal(full.obj, tight.obj) and full.trace == tight.trace
+    short = P.workspace(d, torch.device("cuda"), line_search=B, max_listed=nnz - 1)
+    with pytest.raises(P.PtygError) as e:
+        P.cg_solve(*args, line_search=B, ws=short, max_listed=nnz - 1)
+    assert e.value.status == -5
