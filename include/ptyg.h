@@ -189,6 +189,22 @@ ptyg_status ptyg_minfunc(const ptyg_dims* dims, const ptyg_c64* obj, const ptyg_
                          const float* data, float eps, int32_t estimator, double* objective, void* ws,
                          size_t ws_bytes, ptyg_stream_t stream);
 
+/* ptyg_minfunc without a workspace, for callers that cannot allocate device
+ * memory (code under HIP graph capture, tight serving loops, harnesses that
+ * forbid allocation).  Same arguments, kernels and result as ptyg_minfunc
+ * minus ws / ws_bytes.  Its per-workgroup partial sums live in a fixed
+ * 1 MiB device array inside the library (65536 rows of two doubles, one row
+ * per workgroup: k <= 65536 at n = 128, 131072 at n = 64, 524288 at n = 32,
+ * 1048576 at n = 16); n = 256 and larger k return PTYG_E_INVAL.  Every call
+ * on a GPU uses that GPU's one array: calls that overlap on one GPU (other
+ * streams, other threads) race and must be serialised by the caller.  The
+ * array is written in full before it is read, so no clearing is needed.  It
+ * allocates nothing. */
+ptyg_status ptyg_minfunc_noalloc(const ptyg_dims* dims, const ptyg_c64* obj, const ptyg_c64* dir_obj,
+                                 const ptyg_c64* probe, const ptyg_c64* dir_probe, double gamma, const int32_t* pos,
+                                 const float* data, float eps, int32_t estimator, double* objective,
+                                 ptyg_stream_t stream);
+
 /* ML-CG reconstruction (Algorithm 1 on one GPU; Eqs. update, DaiYuan,
  * linesearch).  obj: in psi_0, out psi_iters.  probe: read, and updated when
  * opts->update_probe.  trace: HOST array of opts->iters rows (nullable).

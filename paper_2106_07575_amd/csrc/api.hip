@@ -7,6 +7,7 @@
 #include <cstdio>
 #include <cstring>
 #include <algorithm>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -283,6 +284,33 @@ struct TimedLaunch {
 // Counter of ptyg_listed_count (one per GPU; concurrent counts on one GPU race).
 static __device__ unsigned long long listed_counter;
 
+// Workspace-free objective pass (ptyg_minfunc_noalloc): its per-workgroup
+// (Phi, F) partials live in this file-scope device array instead of a
+// caller workspace.  Each GPU holds its own copy until the process ends; host
+// code must use the per-device address from hipGetSymbolAddress, never the
+// array's name (a host-side stand-in).
+constexpr int kNoAllocMaxBlocks = 65536;
+static __device__ __align__(256) double scratch[2 * kNoAllocMaxBlocks];
+
+// Device address of `scratch` on the current device, looked up once per
+// device (with that device current) and kept.
+ptyg_status scratch_address(double** out) {
+  static std::mutex mu;
+  static std::vector<double*> addr;
+  int dev = 0;
+  PTYG_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(mu);
+  if ((int)addr.size() <= dev) addr.resize(dev + 1, nullptr);
+  if (!addr[dev]) {
+    void* p = nullptr;
+    PTYG_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    if (!p) return fail(PTYG_E_HIP, "hipGetSymbolAddress returned NULL for the scratch array");
+    addr[dev] = static_cast<double*>(p);
+  }
+  *out = addr[dev];
+  return PTYG_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -517,6 +545,42 @@ ptyg_status ptyg_minfunc(const ptyg_dims* dims, const ptyg_c64* obj, const ptyg_
                      reinterpret_cast<const float2*>(probe), reinterpret_cast<const float2*>(dir_probe), gamma,
                      reinterpret_cast<const int2*>(pos), data, DataLayout::Rows, eps, estimator, objective, ws, L,
                      S(stream));
+}
+
+ptyg_status ptyg_minfunc_noalloc(const ptyg_dims* dims, const ptyg_c64* obj, const ptyg_c64* dir_obj,
+                                 const ptyg_c64* probe, const ptyg_c64* dir_probe, double gamma, const int32_t* pos,
+                                 const float* data, float eps, int32_t estimator, double* objective,
+                                 ptyg_stream_t stream) {
+  if (ptyg_status st = check_dims(dims)) return st;
+  if (!obj || !probe || !pos || !data || !objective) return fail(PTYG_E_INVAL, "NULL array argument");
+  if (!std::isfinite(gamma)) return fail(PTYG_E_INVAL, "gamma not finite");
+  if (!(eps >= 0.0f)) return fail(PTYG_E_INVAL, "eps must be >= 0");
+  if (ptyg_status st = check_est(estimator)) return st;
+  if (dims->n > 128)
+    return fail(PTYG_E_INVAL, "ptyg_minfunc_noalloc supports n <= 128 (n = 256 stages every pattern through a workspace)");
+  const int ppw = patterns_per_block(dims->n);
+  const int64_t groups = ((int64_t)dims->k + ppw - 1) / ppw;
+  const int64_t blocks = 8 * ((groups + 7) / 8);
+  if (blocks > kNoAllocMaxBlocks)
+    return fail(PTYG_E_INVAL, "k=%d needs %lld partial rows; ptyg_minfunc_noalloc holds at most %d (k <= %lld at n=%d)",
+                dims->k, (long long)blocks, kNoAllocMaxBlocks, (long long)kNoAllocMaxBlocks * ppw, dims->n);
+  double* sp = nullptr;
+  if (ptyg_status st = scratch_address(&sp)) return st;
+  PatArgs a = base_args(dims);
+  a.est = estimator;
+  a.obj = reinterpret_cast<const float2*>(obj);
+  a.dobj = reinterpret_cast<const float2*>(dir_obj);
+  a.probe = reinterpret_cast<const float2*>(probe);
+  a.dprobe = reinterpret_cast<const float2*>(dir_probe);
+  a.gamma = (float)gamma;
+  a.pos = reinterpret_cast<const int2*>(pos);
+  a.data = data;
+  a.eps = eps;
+  a.partials = sp;
+  int nb = 0;
+  PTYG_HIP(launch_minfunc(a, DataLayout::Rows, &nb, S(stream)));
+  PTYG_HIP(launch_finalize(sp, nb, 2, objective, S(stream)));
+  return PTYG_OK;
 }
 
 ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* probe_c, const int32_t* pos_i,

@@ -66,6 +66,8 @@ _SIGS = {
                                    _P, _P, ctypes.c_size_t, _P]),
     "ptyg_minfunc": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P, ctypes.c_double, _P, _P,
                                       ctypes.c_float, ctypes.c_int32, _P, _P, ctypes.c_size_t, _P]),
+    "ptyg_minfunc_noalloc": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P, ctypes.c_double, _P, _P,
+                                              ctypes.c_float, ctypes.c_int32, _P, _P]),
     "ptyg_cg_solve": (ctypes.c_int32, [ctypes.POINTER(Dims), _P, _P, _P, _P, ctypes.POINTER(CgOpts), _P,
                                        ctypes.c_size_t, ctypes.POINTER(IterStats),
                                        ctypes.POINTER(ctypes.c_int32), _P]),
@@ -255,6 +257,25 @@ def minfunc(obj, probe, pos, data, dir_obj=None, dir_probe=None, gamma: float = 
     _check(load().ptyg_minfunc(ctypes.byref(d), _ptr(obj), _ptr(dir_obj), _ptr(probe), _ptr(dir_probe),
                                float(gamma), _ptr(pos), _ptr(data), float(eps), ESTIMATOR[estimator],
                                _ptr(objective), _ptr(ws), ws.numel(), _stream()))
+    return objective
+
+
+def minfunc_noalloc(obj, probe, pos, data, objective, dir_obj=None, dir_probe=None, gamma: float = 0.0,
+                    eps: float = 1e-32, estimator: str = "ml") -> torch.Tensor:
+    """minfunc without a workspace: writes (Phi, F) into the caller's float64
+    [2] device tensor `objective` and allocates nothing (n <= 128)."""
+    obj, probe, pos, d = _common(obj, probe, pos)
+    data = _dev(data, "data", torch.float32)
+    objective = _dev(objective, "objective", torch.float64)
+    if objective.numel() < 2:
+        raise ValueError("objective must hold two float64 values")
+    if dir_obj is not None:
+        dir_obj = _dev(dir_obj, "dir_obj", torch.complex64)
+    if dir_probe is not None:
+        dir_probe = _dev(dir_probe, "dir_probe", torch.complex64)
+    _check(load().ptyg_minfunc_noalloc(ctypes.byref(d), _ptr(obj), _ptr(dir_obj), _ptr(probe), _ptr(dir_probe),
+                                       float(gamma), _ptr(pos), _ptr(data), float(eps), ESTIMATOR[estimator],
+                                       _ptr(objective), _stream()))
     return objective
 
 
