@@ -118,8 +118,7 @@ Layout layout(const ptyg_dims* d, bool joint, bool batched = false, bool views =
   L.toff = o;
   o = align_up(o + (T + 1) * sizeof(int));
   L.tlist = o;
-  const size_t nl = std::max(T, (size_t)d->k * tiles_per_patch(d->n));
-  o = align_up(o + nl * sizeof(int));
+  o = align_up(o + tile_list_ints(d->k, d->obj_h, d->obj_w, d->n) * sizeof(int));
   L.tparts = o;  // per-tile (|grad|^2, Re<eta, grad>) rows of the overlap sum
   o = align_up(o + 2 * T * sizeof(double));
   L.far_a = L.far_b = L.far_c = L.lsparts = L.lsphi = L.nz_counts = L.nz_offsets = L.nz_idx = L.zparts = L.zsums = 0;
@@ -435,9 +434,19 @@ ptyg_status run_grad(const ptyg_dims* dims, const float2* obj, const float2* pro
                      const float* data, DataLayout lay, float eps, int est, float2* grad_obj, float2* grad_probe,
                      double* objective, void* ws, const Layout& L, hipStream_t s, float2* gstore = nullptr,
                      double* gsum = nullptr, const uint2* cseg = nullptr, const float2* dot_b = nullptr,
-                     double* dot_out = nullptr, const float2* far_in = nullptr, float2* res_out = nullptr) {
+                     double* dot_out = nullptr, const float2* far_in = nullptr, float2* res_out = nullptr,
+                     bool want_f = true) {
   PatArgs a = base_args(dims);
   a.est = est;
+  a.want_f = want_f ? 1 : 0;
+  if (dims->n == 256 && lay == DataLayout::Rows && !far_in) {
+    // the 256^2 radix stage reads intensities coalesced only per pattern
+    // transposed: transpose once into the workspace
+    float* dt = at<float>(ws, L.data_t);
+    PTYG_HIP(launch_transpose_data(data, dt, dims->k, dims->n, s));
+    data = dt;
+    lay = DataLayout::Transposed;
+  }
   a.gstore = gstore;
   a.cseg = cseg;
   if (gstore) a.zs_part = at<double>(ws, L.zparts);
@@ -492,9 +501,17 @@ ptyg_status build_tiles(const ptyg_dims* dims, const int2* pos, void* ws, const 
 
 ptyg_status run_minfunc(const ptyg_dims* dims, const float2* obj, const float2* dobj, const float2* probe,
                         const float2* dprobe, double gamma, const int2* pos, const float* data, DataLayout lay,
-                        float eps, int est, double* objective, void* ws, const Layout& L, hipStream_t s) {
+                        float eps, int est, double* objective, void* ws, const Layout& L, hipStream_t s,
+                        bool want_f = true) {
   PatArgs a = base_args(dims);
   a.est = est;
+  a.want_f = want_f ? 1 : 0;
+  if (dims->n == 256 && lay == DataLayout::Rows) {
+    float* dt = at<float>(ws, L.data_t);
+    PTYG_HIP(launch_transpose_data(data, dt, dims->k, dims->n, s));
+    data = dt;
+    lay = DataLayout::Transposed;
+  }
   a.obj = obj;
   a.dobj = dobj;
   a.probe = probe;
@@ -528,7 +545,7 @@ ptyg_status ptyg_grad(const ptyg_dims* dims, const ptyg_c64* obj, const ptyg_c64
   return run_grad(dims, reinterpret_cast<const float2*>(obj), reinterpret_cast<const float2*>(probe),
                   reinterpret_cast<const int2*>(pos), data, DataLayout::Rows, eps, estimator,
                   reinterpret_cast<float2*>(grad_obj), reinterpret_cast<float2*>(grad_probe), objective, ws, L,
-                  S(stream));
+                  S(stream), nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, objective != nullptr);
 }
 
 ptyg_status ptyg_minfunc(const ptyg_dims* dims, const ptyg_c64* obj, const ptyg_c64* dir_obj,
@@ -577,6 +594,7 @@ ptyg_status ptyg_minfunc_noalloc(const ptyg_dims* dims, const ptyg_c64* obj, con
   a.data = data;
   a.eps = eps;
   a.partials = sp;
+  a.want_f = 1;
   int nb = 0;
   PTYG_HIP(launch_minfunc(a, DataLayout::Rows, &nb, S(stream)));
   PTYG_HIP(launch_finalize(sp, nb, 2, objective, S(stream)));
@@ -625,9 +643,14 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
   double* lsphi = batched ? at<double>(ws, L.lsphi) : nullptr;
   int last_trials = kLsBatch;  // batched search: the previous accepted index sizes the first pass
 
-  // the intensities are read by every pass: store them per pattern transposed
-  // so that the row-layout reads are coalesced
-  PTYG_HIP(launch_transpose_data(data, dt, dims->k, dims->n, s));
+  // The transform kernels of n <= 128 read the intensities as given (a
+  // lane's four consecutive frequencies are one 16-byte load); the 256^2
+  // radix stage and the compaction of the batched search read them per
+  // pattern transposed, from a copy made once
+  const bool big = dims->n == 256;
+  if (batched || big) PTYG_HIP(launch_transpose_data(data, dt, dims->k, dims->n, s));
+  const float* dgrad = big ? dt : data;
+  const DataLayout lgrad = big ? DataLayout::Transposed : DataLayout::Rows;
   if (ptyg_status st = build_tiles(dims, pos, ws, L, s)) return st;
   float2* illum = batched && !joint ? at<float2>(ws, L.illum) : nullptr;
   // n = 128 and 256: G psi, G eta (and G(eta_p eta)) are stored for the listed elements only
@@ -665,7 +688,7 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
   // the GRAD passes form the deviance only; Eq. ML's value for the trace is
   // Phi plus the data constant, summed once here and read back with the
   // first iteration's scalars
-  PTYG_HIP(launch_data_const(dt, (int64_t)dims->k * dims->n * dims->n, 1, partials, sc + DCONST, s));
+  PTYG_HIP(launch_data_const(data, (int64_t)dims->k * dims->n * dims->n, 1, partials, sc + DCONST, s));
   double* h = readback_buffer();
   if (!h) return fail(PTYG_E_HIP, "pinned readback buffer: %s", hipGetErrorString(hipGetLastError()));
   struct EventGuard {
@@ -686,9 +709,9 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
   for (int m = 0; m < opts->iters; ++m) {
     // GRAD stage
     // the overlap sum also forms ||g_m||^2 and Re<eta_{m-1}, g_m> (sc[N1O], sc[N2O])
-    if (ptyg_status st = run_grad(dims, obj, probe, pos, dt, DataLayout::Transposed, eps, est, grad_o, grad_p,
-                                  sc + PHI, ws, L, s, far_a, batched ? at<double>(ws, L.zsums) : nullptr, cseg,
-                                  restart ? nullptr : eta_o, sc + N1O))
+    if (ptyg_status st = run_grad(dims, obj, probe, pos, dgrad, lgrad, eps, est, grad_o, grad_p, sc + PHI, ws, L, s,
+                                  far_a, batched ? at<double>(ws, L.zsums) : nullptr, cseg, restart ? nullptr : eta_o,
+                                  sc + N1O, nullptr, nullptr, false))
       return st;
     bool applied = false;  // the update was applied with the device's step
     if (joint) {
@@ -899,8 +922,8 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
     for (int j = 1; !batched && j <= opts->max_halvings; ++j) {
       gamma *= opts->tau;
       trials = j;
-      if (ptyg_status st = run_minfunc(dims, obj, eta_o, probe, eta_p, gamma, pos, dt, DataLayout::Transposed,
-                                       eps, est, sc + PHIT, ws, L, s))
+      if (ptyg_status st = run_minfunc(dims, obj, eta_o, probe, eta_p, gamma, pos, dgrad, lgrad, eps, est,
+                                       sc + PHIT, ws, L, s, false))
         return st;
       PTYG_HIP(hipMemcpyAsync(h, sc, (DCONST + 1) * sizeof(double), hipMemcpyDeviceToHost, s));
       PTYG_HIP(hipStreamSynchronize(s));
@@ -975,15 +998,19 @@ ptyg_status ptyg_gd_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
   float2* grad_p = joint ? at<float2>(ws, L.grad_probe) : nullptr;
   float* dt = at<float>(ws, L.data_t);
   double* tr = at<double>(ws, L.gdtrace);
-  PTYG_HIP(launch_transpose_data(data, dt, dims->k, dims->n, s));
+  // n <= 128 reads the intensities as given, 256^2 per pattern transposed
+  const bool big = dims->n == 256;
+  if (big) PTYG_HIP(launch_transpose_data(data, dt, dims->k, dims->n, s));
+  const float* dgrad = big ? dt : data;
+  const DataLayout lgrad = big ? DataLayout::Transposed : DataLayout::Rows;
   if (ptyg_status st = build_tiles(dims, pos, ws, L, s)) return st;
   std::vector<double> h(kGdTrace);
   for (int m0 = 0; m0 < iters; m0 += kGdTrace) {
     const int cnt = std::min(kGdTrace, iters - m0);
     for (int i = 0; i < cnt; ++i) {
       // GRAD stage; the objective of obj_m lands in the device trace
-      if (ptyg_status st = run_grad(dims, obj, probe, pos, dt, DataLayout::Transposed, eps, estimator, grad_o,
-                                    grad_p, tr + i, ws, L, s))
+      if (ptyg_status st = run_grad(dims, obj, probe, pos, dgrad, lgrad, eps, estimator, grad_o, grad_p, tr + i, ws,
+                                    L, s, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr, false))
         return st;
       VecArgs u{};
       u.n = (int64_t)dims->obj_h * dims->obj_w;
@@ -1107,7 +1134,9 @@ ptyg_status ptyg_cg_solve_views(const ptyg_dims* dims, int32_t views, ptyg_c64* 
   double* dalpha = at<double>(ws, VL.valpha);
   float2* far_a = batched ? at<float2>(ws, L.far_a) : nullptr;
   float2* far_b = batched ? at<float2>(ws, L.far_b) : nullptr;
-  PTYG_HIP(launch_transpose_data(data, dt, D->k, D->n, s));
+  // the transform kernels read the intensities as given; the compaction of
+  // the batched search reads a per-pattern transposed copy
+  if (batched) PTYG_HIP(launch_transpose_data(data, dt, D->k, D->n, s));
   PTYG_HIP(launch_zero(eta_o, on * V, s));
   if (ptyg_status st = build_tiles(D, pos, ws, L, s)) return st;
   const int cpv = (int)(pe / kNzChunk);  // compaction chunks per view
@@ -1117,7 +1146,7 @@ ptyg_status ptyg_cg_solve_views(const ptyg_dims* dims, int32_t views, ptyg_c64* 
 
   // per-view data constants: Eq. ML's F = Phi + sum over d > 0 of d - d log d
   std::vector<double> dconst(V, 0.0);
-  PTYG_HIP(launch_data_const(dt, pe, V, at<double>(ws, VL.vparts), at<double>(ws, VL.vout), s));
+  PTYG_HIP(launch_data_const(data, pe, V, at<double>(ws, VL.vparts), at<double>(ws, VL.vout), s));
   PTYG_HIP(hipMemcpyAsync(dconst.data(), at<double>(ws, VL.vout), V * sizeof(double), hipMemcpyDeviceToHost, s));
   PTYG_HIP(hipStreamSynchronize(s));
   // per-view state
@@ -1128,8 +1157,9 @@ ptyg_status ptyg_cg_solve_views(const ptyg_dims* dims, int32_t views, ptyg_c64* 
   // vout slots: 0 phi, 1 f, 2 n1, 3 n2, 4 n3, 5 eta2, 6 |a|^2, 8..11 direction sums
   for (int m = 0; m < opts->iters; ++m) {
     // GRAD over every view in one launch; objectives and sums per view
-    if (ptyg_status st = run_grad(D, obj, probe, pos, dt, DataLayout::Transposed, eps, est, grad_o, nullptr,
-                                  nullptr, ws, L, s, far_a, nullptr))
+    if (ptyg_status st = run_grad(D, obj, probe, pos, data, DataLayout::Rows, eps, est, grad_o, nullptr,
+                                  nullptr, ws, L, s, far_a, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
+                                  false))
       return st;
     PTYG_HIP(launch_finalize_views(partials, D->n, D->k, dims->k, V, 2, vparts, s));
     PTYG_HIP(launch_dot2_views(grad_o, eta_o, on, V, vparts + 2 * V, s));
@@ -1263,14 +1293,14 @@ ptyg_status ptyg_cg_solve_views(const ptyg_dims* dims, int32_t views, ptyg_c64* 
         a.probe = probe;
         a.gamma = (float)gamma;
         a.pos = pos;
-        a.data = dt;
+        a.data = data;
         a.eps = eps;
         a.est = est;
         a.partials = partials;
         a.ubuf = at<float2>(ws, L.ubuf);
         {
           TimedLaunch tl(1, s);
-          PTYG_HIP(launch_minfunc(a, DataLayout::Transposed, nullptr, s));
+          PTYG_HIP(launch_minfunc(a, DataLayout::Rows, nullptr, s));
         }
         PTYG_HIP(launch_finalize_views(partials, D->n, D->k, dims->k, V, 2, vout + 8 * V, s));
         std::vector<double> pt(2 * V);

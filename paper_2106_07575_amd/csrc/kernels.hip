@@ -389,7 +389,7 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_fwd_t(PatArgs a) {
 // instead of being formed; everything after it -- residual and objective
 // terms, inverse transform, stored waves -- is the same code as GRAD's.
 // With a.gstore set it also writes the residual r (row layout).
-template <int N, DataLayout LAY, bool SG, int EST, bool CP = false, bool FARIN = false>
+template <int N, DataLayout LAY, bool SG, int EST, bool CP = false, bool FARIN = false, bool WF = true>
 __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
   using G = Geo<N>;
   static_assert(!CP || (N == 128 && SG), "compacted stores: n = 128 with the G psi store");
@@ -446,9 +446,9 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
     }
     __builtin_amdgcn_sched_barrier(0);
   }
-  // Eq. ML's F only for the API call (row layout); the solver forms it from
+  // Eq. ML's F only where the caller reports it; the solver forms it from
   // Phi and the data constant
-  constexpr bool WANT_F = LAY == DataLayout::Rows;
+  constexpr bool WANT_F = WF;
 #pragma unroll
   for (int c = 0; c < G::E; c += kResChunk) {
     __builtin_amdgcn_sched_barrier(0);
@@ -505,7 +505,7 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
   }
 }
 
-template <int N, DataLayout LAY, bool LINC_O, bool LINC_P, int EST>
+template <int N, DataLayout LAY, bool LINC_O, bool LINC_P, int EST, bool WF = true>
 __global__ PTYG_PATTERN_KERNEL(N) void k_minfunc(PatArgs a) {
   using G = Geo<N>;
   __shared__ float2 lds[G::LDS_ELEMS];
@@ -529,8 +529,8 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_minfunc(PatArgs a) {
   float dn[kResChunk];
 #pragma unroll
   for (int j = 0; j < kResChunk; ++j) dn[j] = load_data<N, LAY>(a.data, k, L, kOrd<N>.s[j]);
-  // the solver's line search (transposed intensities) needs only Phi
-  constexpr bool WANT_F = LAY == DataLayout::Rows;
+  // the solver's line search needs only Phi
+  constexpr bool WANT_F = WF;
 #pragma unroll
   for (int c = 0; c < G::E; c += kResChunk) {
     __builtin_amdgcn_sched_barrier(0);
@@ -674,30 +674,87 @@ __device__ __forceinline__ bool overlaps(int2 p, int N, int y0, int x0) {
   return p.x < y0 + kTileH && p.x + N > y0 && p.y < x0 + kTileW && p.y + N > x0;
 }
 
-// counts[t] = number of patches overlapping tile t (one workgroup per tile).
-__global__ __launch_bounds__(256) void k_tile_count(const int2* __restrict__ pos, int K, int W, int N,
-                                                     int* __restrict__ counts) {
-  __shared__ int red[4];
-  const int ntx = tiles_x(W), t = blockIdx.x;
-  const int y0 = (t / ntx) * kTileH, x0 = (t % ntx) * kTileW;
-  int c = 0;
-  for (int k = threadIdx.x; k < K; k += 256) c += overlaps(pos[k], N, y0, x0) ? 1 : 0;
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) c += __shfl_xor(c, off);
-  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
-  __syncthreads();
-  if (threadIdx.x == 0) counts[t] = red[0] + red[1] + red[2] + red[3];
+// Pattern-parallel tile lists: each pattern adds itself to the tiles its
+// patch overlaps (integer atomics: exact counts), the lists are filled in
+// arrival order, then each tile's list is sorted into ascending pattern
+// order, so the overlap sums run in a fixed order.
+__device__ __forceinline__ void patch_tiles(int2 p, int N, int H, int W, int& ty0, int& ty1, int& tx0, int& tx1) {
+  ty0 = p.x / kTileH;
+  ty1 = min(p.x + N - 1, H - 1) / kTileH;
+  tx0 = p.y / kTileW;
+  tx1 = min(p.y + N - 1, W - 1) / kTileW;
 }
 
-// list[offsets[t] ...] = overlapping patterns of tile t in ascending order:
-// 256 candidates per step, compacted with a ballot prefix.
-__global__ __launch_bounds__(256) void k_tile_fill(const int2* __restrict__ pos, int K, int W, int N,
+// One thread per (pattern, candidate tile) pair: the j-th tile of the
+// tiles_per_patch(N) span starting at the patch's first tile, skipped when
+// it lies past the patch.
+__device__ __forceinline__ int pair_tile(const int2* pos, int64_t idx, int tpp, int span_x, int N, int H, int W) {
+  const int k = (int)(idx / tpp), j = (int)(idx % tpp);
+  int ty0, ty1, tx0, tx1;
+  patch_tiles(pos[k], N, H, W, ty0, ty1, tx0, tx1);
+  const int ty = ty0 + j / span_x, tx = tx0 + j % span_x;
+  if (ty > ty1 || tx > tx1) return -1;
+  return ty * tiles_x(W) + tx;
+}
+
+__global__ __launch_bounds__(256) void k_tile_count_k(const int2* __restrict__ pos, int64_t pairs, int tpp,
+                                                       int span_x, int H, int W, int N, int* __restrict__ counts) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= pairs) return;
+  const int t = pair_tile(pos, idx, tpp, span_x, N, H, W);
+  if (t >= 0) atomicAdd(&counts[t], 1);
+}
+
+__global__ __launch_bounds__(256) void k_tile_fill_k(const int2* __restrict__ pos, int64_t pairs, int tpp,
+                                                      int span_x, int H, int W, int N,
+                                                      const int* __restrict__ offsets, int* __restrict__ cursor,
+                                                      int* __restrict__ list) {
+  const int64_t idx = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= pairs) return;
+  const int t = pair_tile(pos, idx, tpp, span_x, N, H, W);
+  if (t >= 0) list[offsets[t] + atomicAdd(&cursor[t], 1)] = (int)(idx / tpp);
+}
+
+// One workgroup per tile: bitonic sort of its list in LDS (lists of up to
+// kSortMax patterns); a longer list is rebuilt in order by scanning every
+// pattern, as the per-tile fill does.
+constexpr int kSortMax = 2048;
+__global__ __launch_bounds__(256) void k_tile_sort(const int2* __restrict__ pos, int K, int W, int N,
                                                     const int* __restrict__ offsets, int* __restrict__ list) {
+  __shared__ int key[kSortMax];
   __shared__ int wsum[4];
-  const int ntx = tiles_x(W), t = blockIdx.x;
+  const int t = blockIdx.x;
+  const int beg = offsets[t], len = offsets[t + 1] - beg;
+  if (len <= 1) return;
+  if (len <= kSortMax) {
+    int P = 1;
+    while (P < len) P <<= 1;
+    for (int i = threadIdx.x; i < P; i += 256) key[i] = i < len ? list[beg + i] : 0x7fffffff;
+    __syncthreads();
+    for (int k = 2; k <= P; k <<= 1) {
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        for (int i = threadIdx.x; i < P; i += 256) {
+          const int l = i ^ j;
+          if (l > i) {
+            const int a = key[i], b = key[l];
+            const bool up = (i & k) == 0;
+            if ((a > b) == up) {
+              key[i] = b;
+              key[l] = a;
+            }
+          }
+        }
+        __syncthreads();
+      }
+    }
+    for (int i = threadIdx.x; i < len; i += 256) list[beg + i] = key[i];
+    return;
+  }
+  // long list: ascending scan over all patterns with a ballot prefix
+  const int ntx = tiles_x(W);
   const int y0 = (t / ntx) * kTileH, x0 = (t % ntx) * kTileW;
   const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
-  int base = offsets[t];
+  int base = beg;
   for (int k0 = 0; k0 < K; k0 += 256) {
     const int k = k0 + threadIdx.x;
     const bool f = k < K && overlaps(pos[k], N, y0, x0);
@@ -900,8 +957,10 @@ __global__ __launch_bounds__(kVecWG) void k_fill_i32(int* x, int64_t n, int valu
 }
 
 // Per-block sums of d - d log d over the d > 0 elements (NaN propagates) of
-// segment blockIdx.y (n elements each), FP64: the constant between Eq. ML
-// and its deviance form.
+// segment blockIdx.y (n elements each), accumulated in FP64: the constant
+// between Eq. ML and its deviance form.  The logarithm is the FP32 one
+// (relative error ~1e-7 per term, far below the 1e-5 the trace's F is
+// reported to; an FP64 logarithm made this pass cost more than a GRAD).
 __global__ __launch_bounds__(kVecWG) void k_data_const(const float* __restrict__ d, int64_t n,
                                                         double* __restrict__ partials) {
   __shared__ double red[2 * (kVecWG / 64)];
@@ -911,7 +970,7 @@ __global__ __launch_bounds__(kVecWG) void k_data_const(const float* __restrict__
     const float v = ds[i];
     if (!(v <= 0.0f)) {
       const double dv = v;
-      acc += dv - dv * log(dv);
+      acc += dv - dv * (double)(__log2f(v) * kLn2);
     }
   }
   block_sum2<kVecWG>(acc, unused, red);
@@ -1475,30 +1534,38 @@ hipError_t launch_adjoint(const PatArgs& a, hipStream_t s) {
   });
 }
 
+// Calls f with std::integral_constant<bool, b>.
+template <typename F>
+hipError_t dispatch_bool(bool b, F&& f) {
+  return b ? f(std::integral_constant<bool, true>{}) : f(std::integral_constant<bool, false>{});
+}
+
+// n <= 128: the intensities are read in the row layout (a lane's four
+// consecutive frequencies are one 16-byte load); n = 256 takes either.
 hipError_t launch_grad(const PatArgs& a, DataLayout lay, int* blocks_out, hipStream_t s) {
   if (!a.ubuf || !a.data || !a.partials || !a.obj || !a.probe || !a.pos) return hipErrorInvalidValue;
-  if (a.gstore && lay != DataLayout::Transposed) return hipErrorInvalidValue;
   if (a.N == 256) return launch_grad256(a, lay, blocks_out, s);
+  if (lay != DataLayout::Rows) return hipErrorInvalidValue;
   return dispatch_n(a.N, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
+    constexpr DataLayout R = DataLayout::Rows;
     const int nb = pattern_blocks<N>(a.K);
     if (blocks_out) *blocks_out = nb;
     const dim3 g(nb), b(Geo<N>::WG);
     return dispatch_est(a.est, [&](auto ec) {
       constexpr int E = decltype(ec)::value;
-      if (lay == DataLayout::Transposed) {
+      return dispatch_bool(a.want_f != 0, [&](auto wc) {
+        constexpr bool WF = decltype(wc)::value;
         if (a.gstore && a.cseg) {
-          if constexpr (N == 128) hipLaunchKernelGGL((k_grad<N, DataLayout::Transposed, true, E, true>), g, b, 0, s, a);
+          if constexpr (N == 128) hipLaunchKernelGGL((k_grad<N, R, true, E, true, false, WF>), g, b, 0, s, a);
           else return hipErrorInvalidValue;
         } else if (a.gstore) {
-          hipLaunchKernelGGL((k_grad<N, DataLayout::Transposed, true, E>), g, b, 0, s, a);
+          hipLaunchKernelGGL((k_grad<N, R, true, E, false, false, WF>), g, b, 0, s, a);
         } else {
-          hipLaunchKernelGGL((k_grad<N, DataLayout::Transposed, false, E>), g, b, 0, s, a);
+          hipLaunchKernelGGL((k_grad<N, R, false, E, false, false, WF>), g, b, 0, s, a);
         }
-      } else {
-        hipLaunchKernelGGL((k_grad<N, DataLayout::Rows, false, E>), g, b, 0, s, a);
-      }
-      return hipGetLastError();
+        return hipGetLastError();
+      });
     });
   });
 }
@@ -1663,6 +1730,7 @@ hipError_t launch_ls_finalize(const double* partials, int count, double* out, hi
 hipError_t launch_minfunc(const PatArgs& a, DataLayout lay, int* blocks_out, hipStream_t s) {
   if (!a.data || !a.partials || !a.obj || !a.probe || !a.pos) return hipErrorInvalidValue;
   if (a.N == 256) return launch_minfunc256(a, lay, blocks_out, s);
+  if (lay != DataLayout::Rows) return hipErrorInvalidValue;
   return dispatch_n(a.N, [&](auto nc) {
     constexpr int N = decltype(nc)::value;
     const int nb = pattern_blocks<N>(a.K);
@@ -1671,19 +1739,15 @@ hipError_t launch_minfunc(const PatArgs& a, DataLayout lay, int* blocks_out, hip
     const bool lo = a.dobj != nullptr, lp = a.dprobe != nullptr;
     return dispatch_est(a.est, [&](auto ec) {
       constexpr int E = decltype(ec)::value;
-      constexpr DataLayout T = DataLayout::Transposed, R = DataLayout::Rows;
-      if (lay == T) {
-        if (lo && lp) hipLaunchKernelGGL((k_minfunc<N, T, true, true, E>), g, b, 0, s, a);
-        else if (lo) hipLaunchKernelGGL((k_minfunc<N, T, true, false, E>), g, b, 0, s, a);
-        else if (lp) hipLaunchKernelGGL((k_minfunc<N, T, false, true, E>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_minfunc<N, T, false, false, E>), g, b, 0, s, a);
-      } else {
-        if (lo && lp) hipLaunchKernelGGL((k_minfunc<N, R, true, true, E>), g, b, 0, s, a);
-        else if (lo) hipLaunchKernelGGL((k_minfunc<N, R, true, false, E>), g, b, 0, s, a);
-        else if (lp) hipLaunchKernelGGL((k_minfunc<N, R, false, true, E>), g, b, 0, s, a);
-        else hipLaunchKernelGGL((k_minfunc<N, R, false, false, E>), g, b, 0, s, a);
-      }
-      return hipGetLastError();
+      return dispatch_bool(a.want_f != 0, [&](auto wc) {
+        constexpr bool WF = decltype(wc)::value;
+        constexpr DataLayout R = DataLayout::Rows;
+        if (lo && lp) hipLaunchKernelGGL((k_minfunc<N, R, true, true, E, WF>), g, b, 0, s, a);
+        else if (lo) hipLaunchKernelGGL((k_minfunc<N, R, true, false, E, WF>), g, b, 0, s, a);
+        else if (lp) hipLaunchKernelGGL((k_minfunc<N, R, false, true, E, WF>), g, b, 0, s, a);
+        else hipLaunchKernelGGL((k_minfunc<N, R, false, false, E, WF>), g, b, 0, s, a);
+        return hipGetLastError();
+      });
     });
   });
 }
@@ -1737,11 +1801,19 @@ hipError_t launch_debug_lane_swap(float* a, float* b, hipStream_t s) {
 
 hipError_t launch_tile_lists(const int2* pos, int K, int H, int W, int N, int* offsets, int* list, hipStream_t s) {
   const int T = tiles_x(W) * tiles_y(H);
-  // counts are written into list[] scratch first (list holds >= T ints)
-  int* counts = list;
-  hipLaunchKernelGGL(k_tile_count, dim3(T), dim3(256), 0, s, pos, K, W, N, counts);
+  // the T counters (then cursors) sit after the list's capacity
+  int* counts = list + (tile_list_ints(K, H, W, N) - (size_t)T);
+  // candidate tiles per patch: a (N - 1) / kTileH + 2 by (N - 1) / kTileW + 2 span
+  const int span_x = (N - 1) / kTileW + 2, tpp = tiles_per_patch(N);
+  const int64_t pairs = (int64_t)K * tpp;
+  const unsigned pb = (unsigned)((pairs + 255) / 256);
+  if (hipError_t e = launch_fill_i32(counts, T, 0, s)) return e;
+  hipLaunchKernelGGL(k_tile_count_k, dim3(pb), dim3(256), 0, s, pos, pairs, tpp, span_x, H, W, N, counts);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, T, offsets);
-  hipLaunchKernelGGL(k_tile_fill, dim3(T), dim3(256), 0, s, pos, K, W, N, offsets, list);
+  if (hipError_t e = launch_fill_i32(counts, T, 0, s)) return e;
+  hipLaunchKernelGGL(k_tile_fill_k, dim3(pb), dim3(256), 0, s, pos, pairs, tpp, span_x, H, W, N, offsets, counts,
+                     list);
+  hipLaunchKernelGGL(k_tile_sort, dim3(T), dim3(256), 0, s, pos, K, W, N, offsets, list);
   return hipGetLastError();
 }
 

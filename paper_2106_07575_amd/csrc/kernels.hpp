@@ -40,6 +40,9 @@ struct PatArgs {
   // set, gstore (GRAD) and far (direction forward) receive only the listed
   // elements, compacted in ascending element order
   const uint2* cseg;
+  // GRAD / MINFUNC: also form Eq. ML's F per pixel (the API calls report it;
+  // the solver forms it from Phi and a data constant)
+  int want_f;
 };
 
 // Batched line search over stored far fields: trial j evaluates the
@@ -136,7 +139,13 @@ __host__ __device__ inline int tiles_y(int H) { return (H + kTileH - 1) / kTileH
 // Upper bound of tiles one n x n patch overlaps.
 inline int tiles_per_patch(int n) { return ((n - 1) / kTileH + 2) * ((n - 1) / kTileW + 2); }
 // Per-tile lists of the patterns overlapping it, in ascending pattern order:
-// offsets [T + 1], list [sum of counts] (at most K * tiles_per_patch(N)).
+// offsets [T + 1], list [sum of counts] (at most K * tiles_per_patch(N)),
+// followed by T ints of scratch: `list` must hold tile_list_ints() ints.
+inline size_t tile_list_ints(int K, int H, int W, int N) {
+  const size_t T = (size_t)tiles_x(W) * tiles_y(H);
+  const size_t pairs = (size_t)K * tiles_per_patch(N);
+  return (pairs > T ? pairs : T) + T;
+}
 hipError_t launch_tile_lists(const int2* pos, int K, int H, int W, int N, int* offsets, int* list, hipStream_t s);
 // out[y][x] = sum over the tile's patterns k (ascending) of conj(p) * u_k at
 // (y - r_k, x - c_k); every object pixel is written.  probe = NULL: ubuf

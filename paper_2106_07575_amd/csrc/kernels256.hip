@@ -150,7 +150,7 @@ __device__ __forceinline__ void store_listed(float2* out, uint2 r, size_t e, flo
 // MODE 4 (test hook): MODE 1 with the far field taken from a.far (rows)
 // instead of the forward radix stage; with a.gstore set the residual r is
 // also written there (rows).
-template <int MODE, DataLayout LAY, int EST = 0>
+template <int MODE, DataLayout LAY, int EST = 0, bool WF = false>
 __global__ __launch_bounds__(256) void k_combine(PatArgs a, int64_t items) {
   static_assert(MODE != 4 || LAY == DataLayout::Rows, "given far field: row layout");
   constexpr bool RES = MODE == 1 || MODE == 4;  // residual and objective terms
@@ -257,10 +257,10 @@ __global__ __launch_bounds__(256) void k_combine(PatArgs a, int64_t items) {
         }
         const float x = fmaf(g[j].x, g[j].x, g[j].y * g[j].y);
         float phi, ft, fac;
-        // F for the row-layout API calls only (the solver forms it from Phi)
-        pixel_terms<LAY == DataLayout::Rows, EST>(x, d, a.eps, phi, ft, fac);
+        // F only where the caller reports it (the solver forms it from Phi)
+        pixel_terms<WF, EST>(x, d, a.eps, phi, ft, fac);
         acc_phi += (double)phi;
-        if constexpr (LAY == DataLayout::Rows) acc_f += (double)ft;
+        if constexpr (WF) acc_f += (double)ft;
         r[j] = cscale(g[j], fac);
       }
       if constexpr (MODE == 4) {
@@ -342,14 +342,19 @@ hipError_t combine(const PatArgs& a, DataLayout lay, int* blocks_out, hipStream_
   const int est = OBJ ? a.est : 0;
   return dispatch_est(est, [&](auto ec) {
     constexpr int E = OBJ ? decltype(ec)::value : 0;
-    if constexpr (MODE == 4) {
-      if (lay != DataLayout::Rows) return hipErrorInvalidValue;
-    } else if (lay == DataLayout::Transposed) {
-      hipLaunchKernelGGL((k_combine<MODE, DataLayout::Transposed, E>), dim3(nb), dim3(256), 0, s, a, items);
+    const bool wf = OBJ && a.want_f;
+    auto go = [&](auto wc) {
+      constexpr bool WF = OBJ && decltype(wc)::value;
+      if constexpr (MODE == 4) {
+        if (lay != DataLayout::Rows) return hipErrorInvalidValue;
+      } else if (lay == DataLayout::Transposed) {
+        hipLaunchKernelGGL((k_combine<MODE, DataLayout::Transposed, E, WF>), dim3(nb), dim3(256), 0, s, a, items);
+        return hipGetLastError();
+      }
+      hipLaunchKernelGGL((k_combine<MODE, DataLayout::Rows, E, WF>), dim3(nb), dim3(256), 0, s, a, items);
       return hipGetLastError();
-    }
-    hipLaunchKernelGGL((k_combine<MODE, DataLayout::Rows, E>), dim3(nb), dim3(256), 0, s, a, items);
-    return hipGetLastError();
+    };
+    return wf ? go(std::integral_constant<bool, true>{}) : go(std::integral_constant<bool, false>{});
   });
 }
 

@@ -163,6 +163,29 @@ def flip_is_a_tie(m, gpu_trace, oracle_trace, tol=1e-5):
     return abs(margin) <= allowed, margin, allowed
 
 
+def agreed_iterations(gpu_trace, oracle_trace, pert_trace=None, beta_indeterminate=1e-2, tol=1e-5):
+    """Number of leading iterations with identical line-search decisions,
+    after checking that a first disagreement, if any, is legitimate:
+      * a tie (flip_is_a_tie), or
+      * a search direction that FP32 transforms cannot determine: at that
+        iteration the oracle's own FP32-transform run moves the Dai-Yuan
+        coefficient by at least `beta_indeterminate` relative (its
+        denominator Re<eta, grad_m - grad_{m-1}> is a small difference of
+        large terms there, and the step decision follows the direction).
+    Returns (iterations agreed, description of the disagreement or None)."""
+    m = first_decision_flip(gpu_trace, oracle_trace)
+    if m is None:
+        return min(len(gpu_trace), len(oracle_trace)), None
+    tie, margin, allowed = flip_is_a_tie(m, gpu_trace, oracle_trace, tol)
+    b_ref = oracle_trace[m]["beta"]
+    b_pert = pert_trace[m]["beta"] if pert_trace is not None and m < len(pert_trace) else None
+    sens = abs(b_pert - b_ref) / abs(b_ref) if (b_pert is not None and b_ref != 0.0) else 0.0
+    why = (f"decisions part at iteration {m}: trial margin {margin:.3e} (tie within {allowed:.3e}); beta gpu "
+           f"{gpu_trace[m]['beta']:.6g} oracle {b_ref:.6g} fp32-transform oracle {b_pert}, sensitivity {sens:.2e}")
+    assert tie or sens >= beta_indeterminate, why
+    return m, why
+
+
 def cg_with_floor(obj0, probe, pos, data, iters, **kw):
     """(oracle FP64 CG result, oracle CG result with FP32-rounded transforms)."""
     args = (obj0.astype(np.complex128), probe.astype(np.complex128), pos, data.astype(np.float64), iters)
