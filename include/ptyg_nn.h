@@ -78,9 +78,11 @@ int32_t ptyg_nn_adam(float* w, const float* g, float* m, float* v, int64_t n, fl
  * entries) of the overlap matrix c_kj = sum_overlap conj(P_k) P_j. */
 /* Per-tile lists (the solver's object tiles, ascending window order) of the
  * q x q windows at wpos: offsets int32[ptyg_ws_tile_count(H, W) + 1], list
- * int32[ptyg_ws_tile_list_capacity(K, H, W, q)]; offsets_len and list_len
- * give the caller's buffer lengths in elements, and buffers shorter than
- * those sizes are rejected (nothing is written).  Host functions, no GPU. */
+ * int32[ptyg_ws_tile_list_capacity(K, H, W, q)] (the lists, followed by
+ * one counter per tile that the build uses as scratch); offsets_len and
+ * list_len give the caller's buffer lengths in elements, and buffers shorter
+ * than those sizes are rejected (nothing is written).  The two size queries
+ * are host functions (no GPU); they return 0 for a non-positive size. */
 int64_t ptyg_ws_tile_count(int32_t H, int32_t W);
 int64_t ptyg_ws_tile_list_capacity(int32_t K, int32_t H, int32_t W, int32_t q);
 int32_t ptyg_ws_tile_lists(const int32_t* wpos, int32_t K, int32_t H, int32_t W, int32_t q, int32_t* offsets,

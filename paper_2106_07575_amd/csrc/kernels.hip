@@ -796,9 +796,11 @@ __global__ __launch_bounds__(1024) void k_scan(const int* __restrict__ counts, i
 
 // grad[y][x] = sum over the tile's patterns (ascending k) of conj(p) * u_k,
 // or of the stored values themselves when they already carry conj(p).
-// 256 threads: lane column x = x0 + (t & 63), rows y0 + (t >> 6) + 4 i.
-// The tile's pattern list and positions are staged in LDS (kTileStage at a
-// time) so the loop issues its loads without waiting on scalar loads.
+// 256 threads on a 16 x 64 tile: lane l of wave w holds the column pair
+// x = x0 + 2 (l mod 32), x + 1 in the rows y0 + 2 w + l / 32 + 8 i, so each
+// row of the tile is one 512-byte run of 16-byte accesses.  The tile's pattern list
+// and positions are staged in LDS (kTileStage at a time) so the loop issues
+// its loads without waiting on scalar loads.
 constexpr int kTileStage = 512;
 
 // Offset of u_k[yy][xx] inside pattern k's block of U: natural row-major, or
@@ -809,11 +811,29 @@ __device__ __forceinline__ int u_off(int yy, int xx, int N) {
   else return yy * N + xx;
 }
 
-// The loads of kTileDepth patterns are issued before their adds: every lane
-// loads from a clamped in-patch address (valid memory) and an out-of-patch
-// value is dropped by a select, so no load sits behind a branch and the adds
-// still run in ascending pattern order.
-constexpr int kTileDepth = 4;
+// The loads of kTileDepth patterns (half as many when the probe is loaded
+// too) are issued before their adds, and no
+// load sits behind a branch, so the adds still run in ascending pattern
+// order.  Natural layout: one 16-byte buffer load per (pattern, row) reads
+// the pair's two values (pattern columns xc, xc + 1 with xc clamped to
+// [0, N - 2]; the lanes at the patch's left and right edge shift the pair);
+// a row or pair outside the patch gets an offset past the buffer's range,
+// which the hardware answers with zeros and no memory access.  Polyphase
+// layout (always with the probe): the pair's columns lie in different
+// planes, two 8-byte loads with the same out-of-range offset outside the
+// patch; the probe's pair is one 16-byte load as in the natural layout.
+constexpr int kTileDepth = 8;
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+constexpr int kBufDword3 = 0x00020000;  // raw (untyped) buffer, 32-bit data format
+
+__device__ __forceinline__ void pair_of(u32x4 w, int xx, int N, float2& v0, float2& v1) {
+  const float4 f = __builtin_bit_cast(float4, w);
+  const float2 lo = make_float2(f.x, f.y), hi = make_float2(f.z, f.w);
+  const bool left = xx == -1, right = xx == N - 1;
+  v0 = left ? make_float2(0.f, 0.f) : (right ? hi : lo);
+  v1 = left ? lo : (right ? make_float2(0.f, 0.f) : hi);
+}
 
 // dot_parts (nullable): per tile (sum |out|^2, sum Re(conj(dot_b) out)) over
 // the tile's pixels (the second 0 when dot_b is null), as written.
@@ -823,25 +843,25 @@ __global__ __launch_bounds__(256) void k_tile_sum(const float2* __restrict__ U, 
                                                    const int* __restrict__ list, int H, int W, int N,
                                                    int64_t ustride, float2* __restrict__ out,
                                                    const float2* __restrict__ dot_b, double* __restrict__ dot_parts) {
+  static_assert(kTileW == 64 && kTileH == 16, "32 column pairs per row, two rows per wave and step");
+  static_assert(PROBE || !POLY, "polyphase waves are stored without conj(p)");
   __shared__ int sk[kTileStage];
   __shared__ int2 sp[kTileStage];
   __shared__ double red[2 * 4];
   const int ntx = tiles_x(W);
   const int t = blockIdx.x;
-  const int x = (t % ntx) * kTileW + (threadIdx.x & 63);
-  const int yb = (t / ntx) * kTileH + (threadIdx.x >> 6);
-  constexpr int R = kTileH / 4;
-  constexpr int D = kTileDepth;
-  float2 acc[R];
+  const int lane = threadIdx.x & 63;
+  const int x = (t % ntx) * kTileW + 2 * (lane & 31);
+  const int yb = (t / ntx) * kTileH + 2 * (threadIdx.x >> 6) + (lane >> 5);
+  constexpr int RS = 8;  // row step
+  constexpr int R = kTileH / RS;
+  constexpr int D = PROBE ? kTileDepth / 2 : kTileDepth;  // the probe's loads double the registers
+  const int nrec = N * N * (int)sizeof(float2);
+  float2 a0[R], a1[R];
 #pragma unroll
-  for (int i = 0; i < R; ++i) acc[i] = make_float2(0.f, 0.f);
-  // the dot products' other operand, loaded ahead of the sum
-  float2 eb[R];
-#pragma unroll
-  for (int i = 0; i < R; ++i) {
-    const int y = yb + 4 * i;
-    eb[i] = (dot_b && x < W && y < H) ? dot_b[(size_t)y * W + x] : make_float2(0.f, 0.f);
-  }
+  for (int i = 0; i < R; ++i) a0[i] = a1[i] = make_float2(0.f, 0.f);
+  const __amdgpu_buffer_rsrc_t prs =
+      __builtin_amdgcn_make_buffer_rsrc((void*)probe, (short)0, PROBE ? nrec : 0, kBufDword3);
   const int beg = offsets[t], end = offsets[t + 1];
   for (int s0 = beg; s0 < end; s0 += kTileStage) {
     const int n = min(kTileStage, end - s0);
@@ -853,49 +873,118 @@ __global__ __launch_bounds__(256) void k_tile_sum(const float2* __restrict__ U, 
     }
     __syncthreads();
     for (int j = 0; j < n; j += D) {
-      float2 uv[D][R], pv[D][R];
-      bool ok[D][R];
+      if constexpr (!POLY) {
+        u32x4 uv[D][R], pv[D][R];
+        int xs[D];
 #pragma unroll
-      for (int q = 0; q < D; ++q) {
-        const bool live = j + q < n;
-        const int jj = live ? j + q : j;
-        const int2 rc = sp[jj];
-        const int xx = x - rc.y;
-        const bool cv = live && (unsigned)xx < (unsigned)N;
-        const int xc = min(max(xx, 0), N - 1);
-        const float2* uk = U + sk[jj] * ustride;
+        for (int q = 0; q < D; ++q) {
+          const bool live = j + q < n;
+          const int jj = live ? j + q : j;
+          const int2 rc = sp[jj];
+          const int k = __builtin_amdgcn_readfirstlane(sk[jj]);
+          const int xx = x - rc.y;
+          xs[q] = xx;
+          const bool cv = live && xx >= -1 && xx < N;
+          const int xc = min(max(xx, 0), N - 2);
+          const __amdgpu_buffer_rsrc_t rs =
+              __builtin_amdgcn_make_buffer_rsrc((void*)(U + (int64_t)k * ustride), (short)0, nrec, kBufDword3);
 #pragma unroll
-        for (int i = 0; i < R; ++i) {
-          const int yy = yb + 4 * i - rc.x;
-          ok[q][i] = cv && (unsigned)yy < (unsigned)N;
-          const int yc = min(max(yy, 0), N - 1);
-          uv[q][i] = uk[u_off<POLY>(yc, xc, N)];
-          if constexpr (PROBE) pv[q][i] = probe[yc * N + xc];
+          for (int i = 0; i < R; ++i) {
+            const int yy = yb + RS * i - rc.x;
+            const int off = (cv && (unsigned)yy < (unsigned)N) ? (yy * N + xc) * (int)sizeof(float2) : 0x7fffffff;
+            uv[q][i] = __builtin_amdgcn_raw_buffer_load_b128(rs, off, 0, 0);
+            if constexpr (PROBE) pv[q][i] = __builtin_amdgcn_raw_buffer_load_b128(prs, off, 0, 0);
+          }
         }
-      }
-      // keep every load of the group ahead of the first add
-      __builtin_amdgcn_sched_barrier(0);
+        // keep every load of the group ahead of the first add
+        __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-      for (int q = 0; q < D; ++q) {
+        for (int q = 0; q < D; ++q) {
 #pragma unroll
-        for (int i = 0; i < R; ++i) {
-          const float2 v = cadd(acc[i], PROBE ? cmulc(pv[q][i], uv[q][i]) : uv[q][i]);
-          acc[i] = ok[q][i] ? v : acc[i];
+          for (int i = 0; i < R; ++i) {
+            float2 v0, v1;
+            pair_of(uv[q][i], xs[q], N, v0, v1);
+            if constexpr (PROBE) {
+              float2 p0, p1;
+              pair_of(pv[q][i], xs[q], N, p0, p1);
+              v0 = cmulc(p0, v0);
+              v1 = cmulc(p1, v1);
+            }
+            a0[i] = cadd(a0[i], v0);
+            a1[i] = cadd(a1[i], v1);
+          }
+        }
+      } else {
+        u32x2 u0[D][R], u1[D][R];
+        u32x4 pv[D][R];
+        int xs[D];
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+          const bool live = j + q < n;
+          const int jj = live ? j + q : j;
+          const int2 rc = sp[jj];
+          const int k = __builtin_amdgcn_readfirstlane(sk[jj]);
+          const int xx = x - rc.y;
+          xs[q] = xx;
+          const bool c0 = live && (unsigned)xx < (unsigned)N, c1 = live && (unsigned)(xx + 1) < (unsigned)N;
+          const bool cv = live && xx >= -1 && xx < N;
+          const int xc = min(max(xx, 0), N - 2);
+          const __amdgpu_buffer_rsrc_t rs =
+              __builtin_amdgcn_make_buffer_rsrc((void*)(U + (int64_t)k * ustride), (short)0, nrec, kBufDword3);
+#pragma unroll
+          for (int i = 0; i < R; ++i) {
+            const int yy = yb + RS * i - rc.x;
+            const bool r = (unsigned)yy < (unsigned)N;
+            const int o0 = (c0 && r) ? u_off<true>(yy, xx, N) * (int)sizeof(float2) : 0x7fffffff;
+            const int o1 = (c1 && r) ? u_off<true>(yy, xx + 1, N) * (int)sizeof(float2) : 0x7fffffff;
+            u0[q][i] = __builtin_amdgcn_raw_buffer_load_b64(rs, o0, 0, 0);
+            u1[q][i] = __builtin_amdgcn_raw_buffer_load_b64(rs, o1, 0, 0);
+            // the probe is stored naturally: its pair is one 16-byte load
+            const int op = (cv && r) ? (yy * N + xc) * (int)sizeof(float2) : 0x7fffffff;
+            pv[q][i] = __builtin_amdgcn_raw_buffer_load_b128(prs, op, 0, 0);
+          }
+        }
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int q = 0; q < D; ++q) {
+#pragma unroll
+          for (int i = 0; i < R; ++i) {
+            float2 p0, p1;
+            pair_of(pv[q][i], xs[q], N, p0, p1);
+            a0[i] = cadd(a0[i], cmulc(p0, __builtin_bit_cast(float2, u0[q][i])));
+            a1[i] = cadd(a1[i], cmulc(p1, __builtin_bit_cast(float2, u1[q][i])));
+          }
         }
       }
     }
   }
-  double s1 = 0.0, s2 = 0.0;
-  if (x < W) {
+  // the dot products' other operand (loaded after the sum: held across the
+  // loop it cost the kernel a third of its occupancy)
+  float2 e0[R], e1[R];
 #pragma unroll
-    for (int i = 0; i < R; ++i) {
-      const int y = yb + 4 * i;
-      if (y < H) {
-        out[(size_t)y * W + x] = acc[i];
-        if (dot_parts) {
-          s1 += (double)acc[i].x * acc[i].x + (double)acc[i].y * acc[i].y;
-          if (dot_b) s2 += (double)eb[i].x * acc[i].x + (double)eb[i].y * acc[i].y;
-        }
+  for (int i = 0; i < R; ++i) {
+    const int y = yb + RS * i;
+    const bool row = dot_b && y < H;
+    e0[i] = (row && x < W) ? dot_b[(size_t)y * W + x] : make_float2(0.f, 0.f);
+    e1[i] = (row && x + 1 < W) ? dot_b[(size_t)y * W + x + 1] : make_float2(0.f, 0.f);
+  }
+  double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+  for (int i = 0; i < R; ++i) {
+    const int y = yb + RS * i;
+    if (y >= H) continue;
+    if (x < W) {
+      out[(size_t)y * W + x] = a0[i];
+      if (dot_parts) {
+        s1 += (double)a0[i].x * a0[i].x + (double)a0[i].y * a0[i].y;
+        if (dot_b) s2 += (double)e0[i].x * a0[i].x + (double)e0[i].y * a0[i].y;
+      }
+    }
+    if (x + 1 < W) {
+      out[(size_t)y * W + x + 1] = a1[i];
+      if (dot_parts) {
+        s1 += (double)a1[i].x * a1[i].x + (double)a1[i].y * a1[i].y;
+        if (dot_b) s2 += (double)e1[i].x * a1[i].x + (double)e1[i].y * a1[i].y;
       }
     }
   }

@@ -540,40 +540,42 @@ __global__ void k_sync_step(const double2* c, const int* cnt, const int* nb, int
 __global__ __launch_bounds__(256) void k_stitch(const float2* P, const double2* z, const int2* wpos,
                                                 const int* offsets, const int* list, int H, int W, int q,
                                                 float2* psi0) {
-  // object tiles of the solver's tile lists: kTileH x kTileW, lane column x,
-  // rows yb + 4 i
+  // object tiles of the solver's tile lists: kTileH x kTileW, lane column x
+  // in each 64-column part of the tile, rows yb + 4 i
   constexpr int R = kTileH / 4;
   const int ntx = tiles_x(W);
   const int t = blockIdx.x;
-  const int x = (t % ntx) * kTileW + (threadIdx.x & 63);
   const int yb = (t / ntx) * kTileH + (threadIdx.x >> 6);
-  float2 acc[R];
-  int n[R];
-#pragma unroll
-  for (int i = 0; i < R; ++i) {
-    acc[i] = make_float2(0.f, 0.f);
-    n[i] = 0;
-  }
-  for (int e = offsets[t]; e < offsets[t + 1]; ++e) {
-    const int k = list[e];
-    const int2 rc = wpos[k];
-    const int xx = x - rc.y;
-    if ((unsigned)xx >= (unsigned)q) continue;
-    const float2 zk = make_float2((float)z[k].x, (float)z[k].y);
+  for (int part = 0; part < kTileW / 64; ++part) {
+    const int x = (t % ntx) * kTileW + 64 * part + (threadIdx.x & 63);
+    float2 acc[R];
+    int n[R];
 #pragma unroll
     for (int i = 0; i < R; ++i) {
-      const int yy = yb + 4 * i - rc.x;
-      if ((unsigned)yy < (unsigned)q) {
-        acc[i] = cadd(acc[i], cmul(zk, P[(size_t)k * q * q + yy * q + xx]));
-        n[i] += 1;
+      acc[i] = make_float2(0.f, 0.f);
+      n[i] = 0;
+    }
+    for (int e = offsets[t]; e < offsets[t + 1]; ++e) {
+      const int k = list[e];
+      const int2 rc = wpos[k];
+      const int xx = x - rc.y;
+      if ((unsigned)xx >= (unsigned)q) continue;
+      const float2 zk = make_float2((float)z[k].x, (float)z[k].y);
+#pragma unroll
+      for (int i = 0; i < R; ++i) {
+        const int yy = yb + 4 * i - rc.x;
+        if ((unsigned)yy < (unsigned)q) {
+          acc[i] = cadd(acc[i], cmul(zk, P[(size_t)k * q * q + yy * q + xx]));
+          n[i] += 1;
+        }
       }
     }
-  }
-  if (x >= W) return;
+    if (x >= W) continue;
 #pragma unroll
-  for (int i = 0; i < R; ++i) {
-    const int y = yb + 4 * i;
-    if (y < H) psi0[(size_t)y * W + x] = n[i] ? cscale(acc[i], 1.0f / n[i]) : make_float2(1.f, 0.f);
+    for (int i = 0; i < R; ++i) {
+      const int y = yb + 4 * i;
+      if (y < H) psi0[(size_t)y * W + x] = n[i] ? cscale(acc[i], 1.0f / n[i]) : make_float2(1.f, 0.f);
+    }
   }
 }
 
@@ -612,21 +614,23 @@ __global__ void k_cover_count(const int2* wpos, int K, int H, int W, int q, cons
   constexpr int R = kTileH / 4;
   const int ntx = tiles_x(W);
   const int t = blockIdx.x;
-  const int x = (t % ntx) * kTileW + (threadIdx.x & 63);
   const int yb = (t / ntx) * kTileH + (threadIdx.x >> 6);
-  int n[R];
+  for (int part = 0; part < kTileW / 64; ++part) {
+    const int x = (t % ntx) * kTileW + 64 * part + (threadIdx.x & 63);
+    int n[R];
 #pragma unroll
-  for (int i = 0; i < R; ++i) n[i] = 0;
-  for (int e = offsets[t]; e < offsets[t + 1]; ++e) {
-    const int2 rc = wpos[list[e]];
-    if ((unsigned)(x - rc.y) >= (unsigned)q) continue;
+    for (int i = 0; i < R; ++i) n[i] = 0;
+    for (int e = offsets[t]; e < offsets[t + 1]; ++e) {
+      const int2 rc = wpos[list[e]];
+      if ((unsigned)(x - rc.y) >= (unsigned)q) continue;
 #pragma unroll
-    for (int i = 0; i < R; ++i) n[i] += ((unsigned)(yb + 4 * i - rc.x) < (unsigned)q) ? 1 : 0;
+      for (int i = 0; i < R; ++i) n[i] += ((unsigned)(yb + 4 * i - rc.x) < (unsigned)q) ? 1 : 0;
+    }
+    if (x >= W) continue;
+#pragma unroll
+    for (int i = 0; i < R; ++i)
+      if (yb + 4 * i < H) count[(size_t)(yb + 4 * i) * W + x] = n[i];
   }
-  if (x >= W) return;
-#pragma unroll
-  for (int i = 0; i < R; ++i)
-    if (yb + 4 * i < H) count[(size_t)(yb + 4 * i) * W + x] = n[i];
 }
 
 __global__ void k_fill_one(double2* z, int K) {
@@ -823,9 +827,9 @@ int64_t ptyg_ws_tile_count(int32_t H, int32_t W) {
 }
 
 int64_t ptyg_ws_tile_list_capacity(int32_t K, int32_t H, int32_t W, int32_t q) {
-  const int64_t T = (int64_t)tiles_x(W) * tiles_y(H);
-  const int64_t per = (int64_t)((q - 1) / kTileH + 2) * ((q - 1) / kTileW + 2);
-  return T > (int64_t)K * per ? T : (int64_t)K * per;
+  if (K < 1 || H < 1 || W < 1 || q < 1) return 0;
+  // the lists, then the build's per-tile counters
+  return (int64_t)tile_list_ints(K, H, W, q);
 }
 
 int32_t ptyg_ws_tile_lists(const int32_t* wpos, int32_t K, int32_t H, int32_t W, int32_t q, int32_t* offsets,

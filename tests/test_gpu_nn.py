@@ -8,6 +8,8 @@ a bf16 output (relative 2^-9).  Tolerances: bf16 outputs |e| <= 2^-8 |ref| +
 1e-4 max|ref|, FP32 outputs |e| <= 1e-4 max|ref|.  Elementwise kernels whose
 result is one rounding of an exactly computed value are compared bit for bit.
 """
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -262,6 +264,36 @@ def test_stitch_tile_lists_at_object_scale(NN):
     count = torch.empty((H, W), dtype=torch.int32, device="cuda")
     NN.cover_count(wposd, H, W, q, offsets, lst, count)
     assert np.array_equal(count.cpu().numpy(), cnt)
+
+
+def test_tile_lists_stay_inside_the_reported_capacity(NN):
+    """The build writes its lists and per-tile counters only inside the
+    capacity the library reports: a sentinel guard after it is untouched,
+    and the offsets end at the number of (window, tile) overlaps."""
+    wpos, H, W = _grid_positions(20, 48, 64)
+    q, K = 64, len(wpos)
+    T = int(NN.lib().ptyg_ws_tile_count(H, W))
+    cap = int(NN.lib().ptyg_ws_tile_list_capacity(K, H, W, q))
+    guard = 4096
+    buf = torch.full((cap + guard,), -7, dtype=torch.int32, device="cuda")
+    offsets = torch.empty(T + 1, dtype=torch.int32, device="cuda")
+    wposd = torch.from_numpy(wpos).cuda()
+    lib = NN.lib()
+    assert lib.ptyg_ws_tile_lists(ctypes.c_void_p(wposd.data_ptr()), K, H, W, q,
+                                  ctypes.c_void_p(offsets.data_ptr()), T + 1, ctypes.c_void_p(buf.data_ptr()),
+                                  cap, None) == 0
+    torch.cuda.synchronize()
+    assert torch.all(buf[cap:] == -7)
+    n = int(offsets[-1])
+    assert n <= cap
+    # each tile's list ascends and names only windows; every window is listed
+    lst = buf[:n].cpu().numpy()
+    off = offsets.cpu().numpy()
+    assert np.all(np.diff(off) >= 0)
+    for t in range(T):
+        seg = lst[off[t]:off[t + 1]]
+        assert np.all(np.diff(seg) > 0) and np.all((seg >= 0) & (seg < K))
+    assert set(np.unique(lst)) == set(range(K))
 
 
 @pytest.mark.parametrize("K_side,step,q", [(6, 20, 32), (9, 24, 64)])

@@ -58,7 +58,7 @@ def run(P, pos, shape, n, chunk=1024, with_probe=False):
     return out, ref.astype(np.complex64)
 
 
-@pytest.mark.parametrize("n,h,w,k", [(16, 40, 57, 13), (32, 90, 70, 9), (64, 130, 100, 5), (128, 300, 260, 11),
+@pytest.mark.parametrize("n,h,w,k", [(16, 40, 57, 13), (32, 90, 70, 9), (64, 130, 100, 5), (64, 70, 257, 8), (128, 300, 260, 11),
                                      (128, 417, 333, 40), (256, 400, 300, 3), (256, 611, 523, 12)])
 @pytest.mark.parametrize("with_probe", [False, True])
 def test_tile_sum_bit_exact_random_positions(P, n, h, w, k, with_probe):
