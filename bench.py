@@ -5,10 +5,10 @@ apodised-disk probe, 64x64 = 4096 positions on a 24 px raster with +-2 px
 jitter, 128^2 float32 Poisson intensities at 1e5 photons per pattern,
 object-only CG with FP64 reductions.  Inputs come from the seeded generator
 (object, probe, scan; Poisson counts drawn on the host from the generator's
-per-chunk seeds) with the expected intensities from the library's forward
-model, so the data are the tested workload's up to FP32 rounding of the
-expected counts.  A step is one CG iteration (GRAD -> DIR -> LS -> Update
-over all 4096 patterns).  W warm-up iterations run in a separate solve; the
+per-chunk seeds) with the expected intensities from a float64 host forward
+model of the complex64 object and probe: the data are the tested workload's.
+A step is one CG iteration (GRAD -> DIR -> LS -> Update over all 4096
+patterns).  W warm-up iterations run in a separate solve; the
 timed region is one ptyg_cg_solve of K iterations from the usual start
 (psi_0 = 1), inputs resident in HBM.
 
@@ -18,7 +18,10 @@ stage as the solver runs it (transform kernel, ordered overlap sum and
 reductions), at its algorithmic 20 bytes per pattern pixel, its duration
 measured by HIP events on the launch stream inside the timed region; the
 per-kernel fractions follow as secondary fields.  The CPU baseline is the
-FP64 oracle on a bounded sample of the same workload.
+FP64 oracle on a bounded sample of the same workload.  `warm_start` (c2)
+holds the metric's second half: wall time for the learned warm start
+(inference, stitch, CG to plain CG's final objective) against plain CG's
+100 iterations, with iteration counts and errors against the truth.
 """
 from __future__ import annotations
 
@@ -89,27 +92,80 @@ def fft_flops(n: int) -> float:
     return 5.0 * m * math.log2(m)
 
 
-def make_inputs(cfg_name: str, device):
-    """Seeded inputs: object, probe and scan from the generator; expected
-    intensities from the library's forward model of the true object; Poisson
-    counts drawn on the host from the generator's per-chunk seeds."""
+def warm_start(args, inp, probe, pos, data, device) -> dict:
+    """Second half of the metric: time to plain CG's final objective from
+    the learned warm start against plain CG from psi_0 = 1, on this run's
+    inputs.  The network is trained here (seeded: 500 synthetic 1024^2
+    objects, 200 k forward-model patterns, `--warm-start-epochs` epochs,
+    then 400 fine-tuning steps through the differentiable operator); the
+    timed comparison is warmstart.time_to_objective (plain CG for 100
+    iterations; inference on the patterns at least 40 px apart + stitch + CG
+    until plain CG's final objective; host wall times around synchronised
+    GPU work).  Errors are phase-aligned relative errors against the ground
+    truth on the illuminated region."""
     import numpy as np
     import torch
 
-    from paper_2106_07575_amd import ptyg, synth
+    from paper_2106_07575_amd import warmstart as W
+
+    t0 = time.perf_counter()
+    ts = W.make_training_set(probe)
+    net = W.Net(device)
+    hist = W.train(net, ts, epochs=args.warm_start_epochs)
+    del ts
+    ft = W.finetune(net, W.finetune_objects(probe), probe, steps=400, lr=3e-4)
+    torch.cuda.synchronize()
+    t_prep = time.perf_counter() - t0
+    obj_true = torch.from_numpy(inp.obj_true.astype(np.complex64)).to(device)
+    r = W.time_to_objective(net, probe, pos, data, tuple(obj_true.shape), obj_true, line_search=args.line_search,
+                            infer_sep=40)
+    ms = lambda s: round(s * 1e3, 2)
+    return {"t_plain_ms": ms(r["t_plain_s"]), "plain_iters": r["plain_iters"],
+            "t_warm_ms": ms(r["t_warm_total_s"]), "t_infer_ms": ms(r["t_infer_s"]), "t_stitch_ms": ms(r["t_stitch_s"]),
+            "t_cg_warm_ms": ms(r["t_cg_warm_s"]), "warm_iters": r["warm_iters"],
+            "warm_reached_target": r["warm_reached_target"], "warm_faster": r["warm_faster"],
+            "phi_target": r["phi_plain_final"], "phi_warm_final": r["phi_warm_final"],
+            "phi0_ones": r["phi0_ones"], "phi0_warm": r["phi0_warm"],
+            "err_plain": round(r["err_plain"], 5), "err_warm": round(r["err_warm"], 5),
+            "err_psi0_warm": round(r["err_psi0_warm"], 5), "break_even_iters": round(r["break_even_iters"], 1),
+            "inferred_patterns": r["infer_patterns"], "train_epochs": args.warm_start_epochs,
+            "train_loss_last": round(float(np.mean(hist[-5:])), 5), "finetune_phi_first_last": [ft[0], ft[-1]],
+            "t_train_and_finetune_s": round(t_prep, 1)}
+
+
+def expected_intensities(obj, probe, pos, chunk: int = 256):
+    """|F (p * psi[s_k])|^2 in float64 on the host (Eq. fwd_model with the
+    unitary 2-D DFT, scipy's), for input generation only: the counts then
+    follow from the same expected values as the tests' workloads."""
+    import numpy as np
+    import scipy.fft
+
+    n = probe.shape[0]
+    out = np.empty((len(pos), n, n))
+    for lo in range(0, len(pos), chunk):
+        ex = np.stack([probe * obj[r:r + n, c:c + n] for r, c in pos[lo:lo + chunk]])
+        out[lo:lo + chunk] = np.abs(scipy.fft.fft2(ex, norm="ortho", workers=-1)) ** 2
+    return out
+
+
+def make_inputs(cfg_name: str, device):
+    """Seeded inputs: object, probe and scan from the generator; expected
+    intensities |G psi_true|^2 in float64 on the host from the complex64
+    object and probe; Poisson counts from the generator's per-chunk seeds."""
+    import numpy as np
+    import torch
+
+    from paper_2106_07575_amd import synth
 
     cfg = synth.CONFIGS[cfg_name]
     inp = synth.make_inputs(cfg)
-    obj_true = torch.from_numpy(inp.obj_true.astype(np.complex64)).to(device)
-    probe = torch.from_numpy(inp.probe.astype(np.complex64)).to(device)
+    obj32 = inp.obj_true.astype(np.complex64)
+    probe32 = inp.probe.astype(np.complex64)
+    inten = expected_intensities(obj32.astype(np.complex128), probe32.astype(np.complex128), inp.pos)
+    data = synth.make_data(cfg, inten).astype(np.float32)
+    del inten
+    probe = torch.from_numpy(probe32).to(device)
     pos = torch.from_numpy(inp.pos).to(device)
-    data = np.empty((cfg.k, cfg.n, cfg.n), np.float32)
-    chunk = 1024
-    for lo in range(0, cfg.k, chunk):
-        far = ptyg.forward(obj_true, probe, pos[lo:lo + chunk])
-        data[lo:lo + chunk] = (far.real ** 2 + far.imag ** 2).cpu().numpy()
-        del far
-    data = synth.make_data(cfg, data.astype(np.float64)).astype(np.float32)
     return cfg, inp, probe, pos, torch.from_numpy(data).to(device)
 
 
@@ -276,6 +332,10 @@ def main():
                     help="multi-view batch: V independent 320^2 / 128^2 / 49-position projections solved in one set "
                          "of launches, against the same V solved one after another")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--warm-start-epochs", type=float, default=2.0,
+                    help="c2 only: train the warm-start network this many epochs on forward-model patterns "
+                         "(200 k), fine-tune it through the operator, and time NN start + CG to plain CG's final "
+                         "objective against plain CG (0: skip)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="after the timed run, copy a MIB-MiB device buffer 3 times (a reference kernel of known "
                          "traffic for the HBM byte counters)")
@@ -428,6 +488,9 @@ def main():
             dst.copy_(src)
         torch.cuda.synchronize()
         out["copy_calibration_bytes"] = src.numel()
+    if args.warm_start_epochs > 0 and args.config == "c2" and est == "ml":
+        del ws
+        out["warm_start"] = warm_start(args, inp, probe, pos, data, device)
     if not args.no_cpu_baseline and not joint and est == "ml":
         out["cpu_baseline"] = cpu_baseline(args.config, halvings / max(iters, 1))
     print(json.dumps(out))

@@ -1050,18 +1050,26 @@ __global__ __launch_bounds__(kVecWG) void k_fill_i32(int* x, int64_t n, int valu
 // between Eq. ML and its deviance form.  The logarithm is the FP32 one
 // (relative error ~1e-7 per term, far below the 1e-5 the trace's F is
 // reported to; an FP64 logarithm made this pass cost more than a GRAD).
+__device__ __forceinline__ double data_const_term(float v) {
+  const double dv = v;
+  return !(v <= 0.0f) ? dv - dv * (double)(__log2f(v) * kLn2) : 0.0;
+}
 __global__ __launch_bounds__(kVecWG) void k_data_const(const float* __restrict__ d, int64_t n,
                                                         double* __restrict__ partials) {
   __shared__ double red[2 * (kVecWG / 64)];
   const float* ds = d + (int64_t)blockIdx.y * n;
-  double acc = 0.0, unused = 0.0;
-  for (int64_t i = (int64_t)blockIdx.x * kVecWG + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVecWG) {
-    const float v = ds[i];
-    if (!(v <= 0.0f)) {
-      const double dv = v;
-      acc += dv - dv * (double)(__log2f(v) * kLn2);
-    }
+  const int64_t stride = (int64_t)gridDim.x * kVecWG;
+  double acc = 0.0, acc2 = 0.0;
+  int64_t i = (int64_t)blockIdx.x * kVecWG + threadIdx.x;
+  // four independent loads per step, two accumulators
+  for (; i + 3 * stride < n; i += 4 * stride) {
+    const float v0 = ds[i], v1 = ds[i + stride], v2 = ds[i + 2 * stride], v3 = ds[i + 3 * stride];
+    acc += data_const_term(v0) + data_const_term(v1);
+    acc2 += data_const_term(v2) + data_const_term(v3);
   }
+  for (; i < n; i += stride) acc += data_const_term(ds[i]);
+  acc += acc2;
+  double unused = 0.0;
   block_sum2<kVecWG>(acc, unused, red);
   if (threadIdx.x == 0) partials[(size_t)blockIdx.y * gridDim.x + blockIdx.x] = acc;
 }
@@ -1979,9 +1987,16 @@ hipError_t launch_finalize_views(const double* partials, int N, int K, int k_per
 
 hipError_t launch_data_const(const float* d, int64_t n, int segs, double* partials, double* out, hipStream_t s) {
   if (!d || !partials || !out || n < 1 || segs < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_data_const, dim3(kSegBlocks, segs), dim3(kVecWG), 0, s, d, n, partials);
+  // one segment (a whole solve's data): enough blocks to fill the chip, at
+  // most kVecMaxBlocks partials; several segments: kSegBlocks each
+  int nb = kSegBlocks;
+  if (segs == 1) {
+    const int64_t want = n / ((int64_t)kVecWG * 32);
+    nb = (int)(want < 1 ? 1 : (want > kVecMaxBlocks ? kVecMaxBlocks : want));
+  }
+  hipLaunchKernelGGL(k_data_const, dim3(nb, segs), dim3(kVecWG), 0, s, d, n, partials);
   if (hipError_t e = hipGetLastError()) return e;
-  return launch_finalize_seg(partials, kSegBlocks, 1, segs, out, s);
+  return launch_finalize_seg(partials, nb, 1, segs, out, s);
 }
 
 hipError_t launch_dot2_views(const float2* a, const float2* b, int64_t n, int views, double* partials,

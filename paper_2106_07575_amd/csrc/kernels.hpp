@@ -219,7 +219,7 @@ hipError_t launch_axpy_views(float2* a, const float2* c, const double* alpha, in
                              hipStream_t s);
 // out[v] = sum over the d > 0 elements of segment v (n elements each) of
 // d - d log d, in FP64 (F = Phi + this constant); partials holds
-// segs * kSegBlocks doubles.
+// segs * kSegBlocks doubles, or 2048 for a single segment.
 hipError_t launch_data_const(const float* d, int64_t n, int segs, double* partials, double* out, hipStream_t s);
 // out[v][0..width) = ordered sums of rows [v][0..rows) of `width` doubles.
 hipError_t launch_finalize_seg(const double* partials, int rows, int width, int views, double* out,

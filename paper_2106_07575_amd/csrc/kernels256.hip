@@ -150,142 +150,168 @@ __device__ __forceinline__ void store_listed(float2* out, uint2 r, size_t e, flo
 // MODE 4 (test hook): MODE 1 with the far field taken from a.far (rows)
 // instead of the forward radix stage; with a.gstore set the residual r is
 // also written there (rows).
+//
+// The item loop is software-pipelined: an item's loads are issued before
+// the previous item's stores (the wait for loaded data also waits for every
+// older store), so a wave keeps one item's loads in flight while it stores.
+
+// Element index of (A, B) in pattern k's far field / intensities.
+template <DataLayout LAY>
+__device__ __forceinline__ size_t far_index(int64_t k, int A, int B) {
+  return (size_t)k * NB * NB + ((LAY == DataLayout::Transposed) ? (size_t)B * NB + A : (size_t)A * NB + B);
+}
+
+// Everything one item loads: the four sub-grid values (MODE 0-2) or given
+// far-field values (MODE 3, 4), the intensities, the compacted-store records
+// and the direction-sum operands, index j = al * 2 + be.
+struct CombLoads {
+  float2 y[4];
+  float d[4];
+  uint2 rec[4];
+  float2 P[4], Q[4];
+};
+
+template <int MODE, DataLayout LAY>
+__device__ __forceinline__ void comb_load(const PatArgs& a, int64_t i, CombLoads& L) {
+  const int ai = (int)(i & 127), bi = (int)((i >> 7) & 127);
+  const int64_t k = i >> 14;
+  if constexpr (MODE == 3 || MODE == 4) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      L.y[j] = a.far[far_index<DataLayout::Rows>(k, ai + 128 * (j >> 1), bi + 128 * (j & 1))];
+  } else {
+    const float2* y = a.ubuf + (size_t)k * NB * NB + (size_t)bi * NS + ai;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) L.y[j] = y[j * SUB];
+  }
+  if constexpr (MODE == 1 || MODE == 2 || MODE == 4) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) L.d[j] = a.data[far_index<LAY>(k, ai + 128 * (j >> 1), bi + 128 * (j & 1))];
+  }
+  if constexpr (LAY == DataLayout::Transposed && (MODE == 0 || MODE == 1)) {
+    if (MODE == 0 && a.zs_part) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const size_t e = far_index<LAY>(k, ai + 128 * (j >> 1), bi + 128 * (j & 1));
+        L.P[j] = a.zs_p[e];
+        if (a.zs_q) L.Q[j] = a.zs_q[e];
+      }
+    }
+    if (a.cseg && (MODE == 0 || a.gstore)) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) L.rec[j] = a.cseg[far_index<LAY>(k, ai + 128 * (j >> 1), bi + 128 * (j & 1)) >> 5];
+    }
+  }
+}
+
+template <int MODE, DataLayout LAY, int EST, bool WF>
+__device__ __forceinline__ void comb_finish(const PatArgs& a, int64_t i, const CombLoads& L, double& acc_phi,
+                                            double& acc_f, double* z) {
+  constexpr bool RES = MODE == 1 || MODE == 4;  // residual and objective terms
+  const float inv = 1.0f / NB;
+  const int ai = (int)(i & 127), bi = (int)((i >> 7) & 127);
+  const int64_t k = i >> 14;
+  float2 g[4];  // index al * 2 + be
+  if constexpr (MODE == 4) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) g[j] = L.y[j];
+  } else if constexpr (MODE != 3) {
+    const float2 t00 = L.y[0];
+    const float2 t01 = cmul(w256(bi, -1), L.y[1]);
+    const float2 t10 = cmul(w256(ai, -1), L.y[2]);
+    const float2 t11 = cmul(w256(ai + bi, -1), L.y[3]);
+    const float2 s0 = cadd(t00, t10), s1 = csub(t00, t10);  // al = 0 / 1 over p
+    const float2 e0 = cadd(t01, t11), e1 = csub(t01, t11);
+    g[0] = cscale(cadd(s0, e0), inv);  // al 0 be 0
+    g[1] = cscale(csub(s0, e0), inv);  // al 0 be 1
+    g[2] = cscale(cadd(s1, e1), inv);  // al 1 be 0
+    g[3] = cscale(csub(s1, e1), inv);  // al 1 be 1
+  }
+  if constexpr (MODE == 0) {
+    // Rows: far [k][A][B]; Transposed: per pattern [B][A] (the order of
+    // the transposed intensities, for the batched line search)
+    if (LAY == DataLayout::Transposed && a.zs_part) {
+      // sums Re(P conj y), Re(Q conj y), |y|^2
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const float2 y = g[j];
+        z[0] += (double)L.P[j].x * y.x + (double)L.P[j].y * y.y;
+        if (a.zs_q) z[1] += (double)L.Q[j].x * y.x + (double)L.Q[j].y * y.y;
+        z[2] += (double)y.x * y.x + (double)y.y * y.y;
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      const size_t e = far_index<LAY>(k, ai + 128 * (j >> 1), bi + 128 * (j & 1));
+      if (LAY == DataLayout::Transposed && a.cseg) store_listed(a.far, L.rec[j], e, g[j]);
+      else a.far[e] = g[j];
+    }
+    return;
+  }
+  float2 r[4];
+  if constexpr (MODE == 3) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) r[j] = L.y[j];
+  } else {
+    const bool cp = MODE == 1 && LAY == DataLayout::Transposed && a.gstore && a.cseg;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      if constexpr (MODE == 1 && LAY == DataLayout::Transposed) {
+        if (a.gstore) {
+          const size_t e = far_index<LAY>(k, ai + 128 * (j >> 1), bi + 128 * (j & 1));
+          if (cp) store_listed(a.gstore, L.rec[j], e, g[j]);
+          else a.gstore[e] = g[j];
+          z[0] += (double)g[j].x * g[j].x + (double)g[j].y * g[j].y;
+        }
+      }
+      const float x = fmaf(g[j].x, g[j].x, g[j].y * g[j].y);
+      float phi, ft, fac;
+      // F only where the caller reports it (the solver forms it from Phi)
+      pixel_terms<WF, EST>(x, L.d[j], a.eps, phi, ft, fac);
+      acc_phi += (double)phi;
+      if constexpr (WF) acc_f += (double)ft;
+      r[j] = cscale(g[j], fac);
+    }
+    if constexpr (MODE == 4) {
+      if (a.gstore) {
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+          a.gstore[far_index<DataLayout::Rows>(k, ai + 128 * (j >> 1), bi + 128 * (j & 1))] = r[j];
+      }
+    }
+  }
+  if constexpr (RES || MODE == 3) {
+    // adjoint radix stage: R_pq = conj(W^(ap+bq)) sum (-1)^(al p + be q) r / 256
+    float2* y = a.ubuf + (size_t)k * NB * NB + (size_t)bi * NS + ai;
+    const float2 s0 = cadd(r[0], r[2]), s1 = csub(r[0], r[2]);  // over al
+    const float2 u0 = cadd(r[1], r[3]), u1 = csub(r[1], r[3]);
+    const float2 r00 = cadd(s0, u0);        // p 0 q 0
+    const float2 r01 = csub(s0, u0);        // p 0 q 1
+    const float2 r10 = cadd(s1, u1);        // p 1 q 0
+    const float2 r11 = csub(s1, u1);        // p 1 q 1
+    y[0] = cscale(r00, inv);
+    y[SUB] = cscale(cmul(w256(bi, +1), r01), inv);
+    y[2 * SUB] = cscale(cmul(w256(ai, +1), r10), inv);
+    y[3 * SUB] = cscale(cmul(w256(ai + bi, +1), r11), inv);
+  }
+}
+
 template <int MODE, DataLayout LAY, int EST = 0, bool WF = false>
 __global__ __launch_bounds__(256) void k_combine(PatArgs a, int64_t items) {
   static_assert(MODE != 4 || LAY == DataLayout::Rows, "given far field: row layout");
-  constexpr bool RES = MODE == 1 || MODE == 4;  // residual and objective terms
+  constexpr bool RES = MODE == 1 || MODE == 4;
   __shared__ double red[16];
   double acc_phi = 0.0, acc_f = 0.0;
   double z[4] = {0.0, 0.0, 0.0, 0.0};  // with a.zs_part: MODE 0 direction sums, MODE 1 sum |G psi|^2
-  const float inv = 1.0f / NB;
-  for (int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x; i < items; i += (int64_t)gridDim.x * 256) {
-    const int ai = (int)(i & 127), bi = (int)((i >> 7) & 127);
-    const int64_t k = i >> 14;
-    float2* y = a.ubuf + (size_t)k * NB * NB + (size_t)bi * NS + ai;
-    float2 g[4];  // index al * 2 + be
-    if constexpr (MODE == 4) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int A = ai + 128 * (j >> 1), B = bi + 128 * (j & 1);
-        g[j] = a.far[(size_t)k * NB * NB + (size_t)A * NB + B];
-      }
-    } else if constexpr (MODE != 3) {
-      const float2 y00 = y[0], y01 = y[SUB], y10 = y[2 * SUB], y11 = y[3 * SUB];
-      const float2 t00 = y00;
-      const float2 t01 = cmul(w256(bi, -1), y01);
-      const float2 t10 = cmul(w256(ai, -1), y10);
-      const float2 t11 = cmul(w256(ai + bi, -1), y11);
-      const float2 s0 = cadd(t00, t10), s1 = csub(t00, t10);  // al = 0 / 1 over p
-      const float2 e0 = cadd(t01, t11), e1 = csub(t01, t11);
-      g[0] = cscale(cadd(s0, e0), inv);  // al 0 be 0
-      g[1] = cscale(csub(s0, e0), inv);  // al 0 be 1
-      g[2] = cscale(cadd(s1, e1), inv);  // al 1 be 0
-      g[3] = cscale(csub(s1, e1), inv);  // al 1 be 1
-    }
-    if constexpr (MODE == 0) {
-      // Rows: far [k][A][B]; Transposed: per pattern [B][A] (the order of
-      // the transposed intensities, for the batched line search)
-      if (LAY == DataLayout::Transposed && a.zs_part) {
-        // sums Re(P conj y), Re(Q conj y), |y|^2, loaded before the stores
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int A = ai + 128 * (j >> 1), B = bi + 128 * (j & 1);
-          const size_t e = (size_t)k * NB * NB + (size_t)B * NB + A;
-          const float2 P = a.zs_p[e], y = g[j];
-          z[0] += (double)P.x * y.x + (double)P.y * y.y;
-          if (a.zs_q) {
-            const float2 Q = a.zs_q[e];
-            z[1] += (double)Q.x * y.x + (double)Q.y * y.y;
-          }
-          z[2] += (double)y.x * y.x + (double)y.y * y.y;
-        }
-      }
-      if (LAY == DataLayout::Transposed && a.cseg) {
-        // records first: a load waits for every earlier store
-        uint2 rec[4];
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int A = ai + 128 * (j >> 1), B = bi + 128 * (j & 1);
-          rec[j] = a.cseg[((size_t)k * NB * NB + (size_t)B * NB + A) >> 5];
-        }
-#pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          const int A = ai + 128 * (j >> 1), B = bi + 128 * (j & 1);
-          store_listed(a.far, rec[j], (size_t)k * NB * NB + (size_t)B * NB + A, g[j]);
-        }
-        continue;
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int A = ai + 128 * (j >> 1), B = bi + 128 * (j & 1);
-        const size_t e = (size_t)k * NB * NB +
-                         ((LAY == DataLayout::Transposed) ? (size_t)B * NB + A : (size_t)A * NB + B);
-        a.far[e] = g[j];
-      }
-      continue;
-    }
-    float2 r[4];
-    if constexpr (MODE == 3) {
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int A = ai + 128 * (j >> 1), B = bi + 128 * (j & 1);
-        r[j] = a.far[(size_t)k * NB * NB + (size_t)A * NB + B];
-      }
-    } else {
-      // the four intensities before any store (a load waits for every
-      // earlier store)
-      float dv[4];
-      uint2 rec[4];
-      const bool cp = MODE == 1 && LAY == DataLayout::Transposed && a.gstore && a.cseg;
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int A = ai + 128 * (j >> 1), B = bi + 128 * (j & 1);
-        dv[j] = (LAY == DataLayout::Transposed) ? a.data[(size_t)k * NB * NB + (size_t)B * NB + A]
-                                                : a.data[(size_t)k * NB * NB + (size_t)A * NB + B];
-        if (cp) rec[j] = a.cseg[((size_t)k * NB * NB + (size_t)B * NB + A) >> 5];
-      }
-#pragma unroll
-      for (int j = 0; j < 4; ++j) {
-        const int A = ai + 128 * (j >> 1), B = bi + 128 * (j & 1);
-        const float d = dv[j];
-        if constexpr (MODE == 1 && LAY == DataLayout::Transposed) {
-          if (a.gstore) {
-            if (cp) store_listed(a.gstore, rec[j], (size_t)k * NB * NB + (size_t)B * NB + A, g[j]);
-            else a.gstore[(size_t)k * NB * NB + (size_t)B * NB + A] = g[j];
-            z[0] += (double)g[j].x * g[j].x + (double)g[j].y * g[j].y;
-          }
-        }
-        const float x = fmaf(g[j].x, g[j].x, g[j].y * g[j].y);
-        float phi, ft, fac;
-        // F only where the caller reports it (the solver forms it from Phi)
-        pixel_terms<WF, EST>(x, d, a.eps, phi, ft, fac);
-        acc_phi += (double)phi;
-        if constexpr (WF) acc_f += (double)ft;
-        r[j] = cscale(g[j], fac);
-      }
-      if constexpr (MODE == 4) {
-        if (a.gstore) {
-#pragma unroll
-          for (int j = 0; j < 4; ++j) {
-            const int A = ai + 128 * (j >> 1), B = bi + 128 * (j & 1);
-            a.gstore[(size_t)k * NB * NB + (size_t)A * NB + B] = r[j];
-          }
-        }
-      }
-    }
-    if constexpr (RES || MODE == 3) {
-      // adjoint radix stage: R_pq = conj(W^(ap+bq)) sum (-1)^(al p + be q) r / 256
-      const float2 s0 = cadd(r[0], r[2]), s1 = csub(r[0], r[2]);  // over al
-      const float2 u0 = cadd(r[1], r[3]), u1 = csub(r[1], r[3]);
-      const float2 r00 = cadd(s0, u0);        // p 0 q 0
-      const float2 r01 = csub(s0, u0);        // p 0 q 1
-      const float2 r10 = cadd(s1, u1);        // p 1 q 0
-      const float2 r11 = csub(s1, u1);        // p 1 q 1
-      y[0] = cscale(r00, inv);
-      y[SUB] = cscale(cmul(w256(bi, +1), r01), inv);
-      y[2 * SUB] = cscale(cmul(w256(ai, +1), r10), inv);
-      y[3 * SUB] = cscale(cmul(w256(ai + bi, +1), r11), inv);
-    }
+  const int64_t stride = (int64_t)gridDim.x * 256;
+  int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  CombLoads cur;
+  if (i < items) comb_load<MODE, LAY>(a, i, cur);
+  for (; i < items; i += stride) {
+    CombLoads nxt;
+    if (i + stride < items) comb_load<MODE, LAY>(a, i + stride, nxt);
+    comb_finish<MODE, LAY, EST, WF>(a, i, cur, acc_phi, acc_f, z);
+    cur = nxt;
   }
   if constexpr ((MODE == 0 || MODE == 1) && LAY == DataLayout::Transposed) {
     if (a.zs_part && (MODE == 0 || a.gstore)) {
