@@ -1,6 +1,12 @@
 """Builds libptyg.so (HIP kernels + C ABI) for gfx950 with hipcc, in-tree.
 
-    python -m paper_2106_07575_amd.build        # or build() from Python
+    python -m paper_2106_07575_amd.build              # or build() from Python
+    python -m paper_2106_07575_amd.build --sanitize   # host-sanitizer variant
+
+The sanitizer variant (_build/sanitize/libptyg.so) instruments the host
+code only (AddressSanitizer and UndefinedBehaviorSanitizer on the host
+pass; device code is built as usual) for the CPU-side tests; a process
+loads it with the ASan runtime preloaded (asan_runtime()).
 """
 from __future__ import annotations
 
@@ -34,30 +40,63 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found (ROCm is required to build libptyg.so)")
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+SAN_BUILD = os.path.join(BUILD, "sanitize")
+SAN_LIB = os.path.join(SAN_BUILD, "libptyg.so")
+# host pass only: each -fsanitize= goes to the host compiler
+SAN_FLAGS = ["-O1", "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+             "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def _compile(src: str, sanitize: bool = False) -> str:
+    out = SAN_BUILD if sanitize else BUILD
+    obj = os.path.join(out, os.path.splitext(src)[0] + ".o")
+    flags = [f for f in FLAGS if f != "-O3"] + SAN_FLAGS if sanitize else FLAGS
+    cmd = [hipcc(), *flags, "-c", os.path.join(CSRC, src), "-o", obj]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{r.stderr}")
     return obj
 
 
-def build(verbose: bool = True) -> str:
-    """Compile every HIP source and link libptyg.so next to this file."""
-    os.makedirs(BUILD, exist_ok=True)
+def build(verbose: bool = True, sanitize: bool = False) -> str:
+    """Compile every HIP source and link libptyg.so next to this file (the
+    sanitizer variant: under _build/sanitize)."""
+    out, lib = (SAN_BUILD, SAN_LIB) if sanitize else (BUILD, LIB)
+    os.makedirs(out, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda src: _compile(src, sanitize), SOURCES))
+    tmp = lib + ".tmp"
     cmd = [hipcc(), "-shared", "-fPIC", f"--offload-arch={ARCH}", *objs, "-o", tmp]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError(f"link failed:\n{r.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, lib)
     if verbose:
-        print(f"built {LIB}", file=sys.stderr)
-    return LIB
+        print(f"built {lib}", file=sys.stderr)
+    return lib
+
+
+def sources_newer_than(path: str) -> bool:
+    """True when `path` is missing or older than a source or header."""
+    if not os.path.exists(path):
+        return True
+    t = os.path.getmtime(path)
+    inc = os.path.join(os.path.dirname(PKG), "include")
+    files = [os.path.join(CSRC, f) for f in os.listdir(CSRC)] + [os.path.join(inc, f) for f in os.listdir(inc)]
+    return any(os.path.getmtime(f) > t for f in files)
+
+
+def asan_runtime() -> str:
+    """The AddressSanitizer runtime of the compiler hipcc drives."""
+    clang = os.path.join(os.path.dirname(os.path.realpath(hipcc())), "..", "llvm", "bin", "clang++")
+    if not os.path.exists(clang):
+        clang = shutil.which("clang++") or "clang++"
+    r = subprocess.run([clang, "-print-file-name=libclang_rt.asan-x86_64.so"], capture_output=True, text=True)
+    path = r.stdout.strip()
+    if r.returncode != 0 or not os.path.isabs(path) or not os.path.exists(path):
+        raise RuntimeError("AddressSanitizer runtime not found")
+    return path
 
 
 if __name__ == "__main__":
-    build()
+    build(sanitize="--sanitize" in sys.argv[1:])

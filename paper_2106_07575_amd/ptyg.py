@@ -15,7 +15,9 @@ import os
 
 import torch
 
-_LIB_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "libptyg.so")
+# the in-tree build; PTYG_LIBRARY names another build of the same sources
+# (the host-sanitizer variant the CPU tests load)
+_LIB_PATH = os.environ.get("PTYG_LIBRARY") or os.path.join(os.path.dirname(os.path.abspath(__file__)), "libptyg.so")
 _lib = None
 
 PTYG_OK = 0
