@@ -204,22 +204,24 @@ __device__ __forceinline__ void comb_load(const PatArgs& a, int64_t i, CombLoads
   }
 }
 
+// One item's radix-stage work on its loaded operands (ly: sub-grid or given
+// far-field values, ld: intensities, rec: compacted-store records, P / Q:
+// direction-sum operands).  MODE 1, 3, 4 return the adjoint sub-grid values
+// in ynew for the caller to store.
 template <int MODE, DataLayout LAY, int EST, bool WF>
-__device__ __forceinline__ void comb_finish(const PatArgs& a, int64_t i, const CombLoads& L, double& acc_phi,
-                                            double& acc_f, double* z) {
-  constexpr bool RES = MODE == 1 || MODE == 4;  // residual and objective terms
+__device__ __forceinline__ void comb_item(const PatArgs& a, int ai, int bi, int64_t k, const float2* ly,
+                                          const float* ld, const uint2* rec, const float2* P, const float2* Q,
+                                          double& acc_phi, double& acc_f, double* z, float2* ynew) {
   const float inv = 1.0f / NB;
-  const int ai = (int)(i & 127), bi = (int)((i >> 7) & 127);
-  const int64_t k = i >> 14;
   float2 g[4];  // index al * 2 + be
   if constexpr (MODE == 4) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) g[j] = L.y[j];
+    for (int j = 0; j < 4; ++j) g[j] = ly[j];
   } else if constexpr (MODE != 3) {
-    const float2 t00 = L.y[0];
-    const float2 t01 = cmul(w256(bi, -1), L.y[1]);
-    const float2 t10 = cmul(w256(ai, -1), L.y[2]);
-    const float2 t11 = cmul(w256(ai + bi, -1), L.y[3]);
+    const float2 t00 = ly[0];
+    const float2 t01 = cmul(w256(bi, -1), ly[1]);
+    const float2 t10 = cmul(w256(ai, -1), ly[2]);
+    const float2 t11 = cmul(w256(ai + bi, -1), ly[3]);
     const float2 s0 = cadd(t00, t10), s1 = csub(t00, t10);  // al = 0 / 1 over p
     const float2 e0 = cadd(t01, t11), e1 = csub(t01, t11);
     g[0] = cscale(cadd(s0, e0), inv);  // al 0 be 0
@@ -235,15 +237,15 @@ __device__ __forceinline__ void comb_finish(const PatArgs& a, int64_t i, const C
 #pragma unroll
       for (int j = 0; j < 4; ++j) {
         const float2 y = g[j];
-        z[0] += (double)L.P[j].x * y.x + (double)L.P[j].y * y.y;
-        if (a.zs_q) z[1] += (double)L.Q[j].x * y.x + (double)L.Q[j].y * y.y;
+        z[0] += (double)P[j].x * y.x + (double)P[j].y * y.y;
+        if (a.zs_q) z[1] += (double)Q[j].x * y.x + (double)Q[j].y * y.y;
         z[2] += (double)y.x * y.x + (double)y.y * y.y;
       }
     }
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       const size_t e = far_index<LAY>(k, ai + 128 * (j >> 1), bi + 128 * (j & 1));
-      if (LAY == DataLayout::Transposed && a.cseg) store_listed(a.far, L.rec[j], e, g[j]);
+      if (LAY == DataLayout::Transposed && a.cseg) store_listed(a.far, rec[j], e, g[j]);
       else a.far[e] = g[j];
     }
     return;
@@ -251,7 +253,7 @@ __device__ __forceinline__ void comb_finish(const PatArgs& a, int64_t i, const C
   float2 r[4];
   if constexpr (MODE == 3) {
 #pragma unroll
-    for (int j = 0; j < 4; ++j) r[j] = L.y[j];
+    for (int j = 0; j < 4; ++j) r[j] = ly[j];
   } else {
     const bool cp = MODE == 1 && LAY == DataLayout::Transposed && a.gstore && a.cseg;
 #pragma unroll
@@ -259,7 +261,7 @@ __device__ __forceinline__ void comb_finish(const PatArgs& a, int64_t i, const C
       if constexpr (MODE == 1 && LAY == DataLayout::Transposed) {
         if (a.gstore) {
           const size_t e = far_index<LAY>(k, ai + 128 * (j >> 1), bi + 128 * (j & 1));
-          if (cp) store_listed(a.gstore, L.rec[j], e, g[j]);
+          if (cp) store_listed(a.gstore, rec[j], e, g[j]);
           else a.gstore[e] = g[j];
           z[0] += (double)g[j].x * g[j].x + (double)g[j].y * g[j].y;
         }
@@ -267,7 +269,7 @@ __device__ __forceinline__ void comb_finish(const PatArgs& a, int64_t i, const C
       const float x = fmaf(g[j].x, g[j].x, g[j].y * g[j].y);
       float phi, ft, fac;
       // F only where the caller reports it (the solver forms it from Phi)
-      pixel_terms<WF, EST>(x, L.d[j], a.eps, phi, ft, fac);
+      pixel_terms<WF, EST>(x, ld[j], a.eps, phi, ft, fac);
       acc_phi += (double)phi;
       if constexpr (WF) acc_f += (double)ft;
       r[j] = cscale(g[j], fac);
@@ -280,19 +282,105 @@ __device__ __forceinline__ void comb_finish(const PatArgs& a, int64_t i, const C
       }
     }
   }
-  if constexpr (RES || MODE == 3) {
+  if constexpr (MODE == 1 || MODE == 3 || MODE == 4) {
     // adjoint radix stage: R_pq = conj(W^(ap+bq)) sum (-1)^(al p + be q) r / 256
-    float2* y = a.ubuf + (size_t)k * NB * NB + (size_t)bi * NS + ai;
     const float2 s0 = cadd(r[0], r[2]), s1 = csub(r[0], r[2]);  // over al
     const float2 u0 = cadd(r[1], r[3]), u1 = csub(r[1], r[3]);
     const float2 r00 = cadd(s0, u0);        // p 0 q 0
     const float2 r01 = csub(s0, u0);        // p 0 q 1
     const float2 r10 = cadd(s1, u1);        // p 1 q 0
     const float2 r11 = csub(s1, u1);        // p 1 q 1
-    y[0] = cscale(r00, inv);
-    y[SUB] = cscale(cmul(w256(bi, +1), r01), inv);
-    y[2 * SUB] = cscale(cmul(w256(ai, +1), r10), inv);
-    y[3 * SUB] = cscale(cmul(w256(ai + bi, +1), r11), inv);
+    ynew[0] = cscale(r00, inv);
+    ynew[1] = cscale(cmul(w256(bi, +1), r01), inv);
+    ynew[2] = cscale(cmul(w256(ai, +1), r10), inv);
+    ynew[3] = cscale(cmul(w256(ai + bi, +1), r11), inv);
+  }
+}
+
+template <int MODE, DataLayout LAY, int EST, bool WF>
+__device__ __forceinline__ void comb_finish(const PatArgs& a, int64_t i, const CombLoads& L, double& acc_phi,
+                                            double& acc_f, double* z) {
+  const int ai = (int)(i & 127), bi = (int)((i >> 7) & 127);
+  const int64_t k = i >> 14;
+  float2 ynew[4];
+  comb_item<MODE, LAY, EST, WF>(a, ai, bi, k, L.y, L.d, L.rec, L.P, L.Q, acc_phi, acc_f, z, ynew);
+  if constexpr (MODE == 1 || MODE == 3 || MODE == 4) {
+    float2* y = a.ubuf + (size_t)k * NB * NB + (size_t)bi * NS + ai;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) y[j * SUB] = ynew[j];
+  }
+}
+
+// Transposed layout, MODE 0-2: two adjacent frequencies (a, a + 1) per
+// thread, so the sub-grid values move as 16-byte and the intensities as
+// 8-byte accesses.  Pair item i: a = 2 (i & 63), b = (i >> 6) & 127,
+// k = i >> 13.
+struct CombLoads2 {
+  float4 y[4];
+  float2 d[4];
+  uint2 rec[4];  // (a, a + 1) share one 32-element record: a is even
+  float4 P[4], Q[4];
+};
+
+template <int MODE>
+__device__ __forceinline__ void comb_load2(const PatArgs& a, int64_t i, CombLoads2& L) {
+  constexpr DataLayout T = DataLayout::Transposed;
+  const int ai = 2 * (int)(i & 63), bi = (int)((i >> 6) & 127);
+  const int64_t k = i >> 13;
+  const float4* y = reinterpret_cast<const float4*>(a.ubuf + (size_t)k * NB * NB + (size_t)bi * NS + ai);
+#pragma unroll
+  for (int j = 0; j < 4; ++j) L.y[j] = y[j * (SUB / 2)];
+  if constexpr (MODE == 1 || MODE == 2) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j)
+      L.d[j] = *reinterpret_cast<const float2*>(a.data + far_index<T>(k, ai + 128 * (j >> 1), bi + 128 * (j & 1)));
+  }
+  if constexpr (MODE == 0) {
+    if (a.zs_part) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) {
+        const size_t e = far_index<T>(k, ai + 128 * (j >> 1), bi + 128 * (j & 1));
+        L.P[j] = *reinterpret_cast<const float4*>(a.zs_p + e);
+        if (a.zs_q) L.Q[j] = *reinterpret_cast<const float4*>(a.zs_q + e);
+      }
+    }
+  }
+  if constexpr (MODE == 0 || MODE == 1) {
+    if (a.cseg && (MODE == 0 || a.gstore)) {
+#pragma unroll
+      for (int j = 0; j < 4; ++j) L.rec[j] = a.cseg[far_index<T>(k, ai + 128 * (j >> 1), bi + 128 * (j & 1)) >> 5];
+    }
+  }
+}
+
+__device__ __forceinline__ float2 half_of(float4 v, int h) {
+  return h ? make_float2(v.z, v.w) : make_float2(v.x, v.y);
+}
+
+template <int MODE, int EST, bool WF>
+__device__ __forceinline__ void comb_finish2(const PatArgs& a, int64_t i, const CombLoads2& L, double& acc_phi,
+                                             double& acc_f, double* z) {
+  const int ai = 2 * (int)(i & 63), bi = (int)((i >> 6) & 127);
+  const int64_t k = i >> 13;
+  float2 yn[2][4];
+#pragma unroll
+  for (int h = 0; h < 2; ++h) {
+    float2 ly[4], P[4], Q[4];
+    float ld[4];
+#pragma unroll
+    for (int j = 0; j < 4; ++j) {
+      ly[j] = half_of(L.y[j], h);
+      ld[j] = h ? L.d[j].y : L.d[j].x;
+      P[j] = half_of(L.P[j], h);
+      Q[j] = half_of(L.Q[j], h);
+    }
+    comb_item<MODE, DataLayout::Transposed, EST, WF>(a, ai + h, bi, k, ly, ld, L.rec, P, Q, acc_phi, acc_f, z,
+                                                     yn[h]);
+  }
+  if constexpr (MODE == 1) {
+    float4* y = reinterpret_cast<float4*>(a.ubuf + (size_t)k * NB * NB + (size_t)bi * NS + ai);
+#pragma unroll
+    for (int j = 0; j < 4; ++j) y[j * (SUB / 2)] = make_float4(yn[0][j].x, yn[0][j].y, yn[1][j].x, yn[1][j].y);
   }
 }
 
@@ -305,13 +393,25 @@ __global__ __launch_bounds__(256) void k_combine(PatArgs a, int64_t items) {
   double z[4] = {0.0, 0.0, 0.0, 0.0};  // with a.zs_part: MODE 0 direction sums, MODE 1 sum |G psi|^2
   const int64_t stride = (int64_t)gridDim.x * 256;
   int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  CombLoads cur;
-  if (i < items) comb_load<MODE, LAY>(a, i, cur);
-  for (; i < items; i += stride) {
-    CombLoads nxt;
-    if (i + stride < items) comb_load<MODE, LAY>(a, i + stride, nxt);
-    comb_finish<MODE, LAY, EST, WF>(a, i, cur, acc_phi, acc_f, z);
-    cur = nxt;
+  if constexpr (LAY == DataLayout::Transposed && MODE <= 2) {
+    const int64_t pairs = items >> 1;  // items = K * SUB is even
+    CombLoads2 cur;
+    if (i < pairs) comb_load2<MODE>(a, i, cur);
+    for (; i < pairs; i += stride) {
+      CombLoads2 nxt;
+      if (i + stride < pairs) comb_load2<MODE>(a, i + stride, nxt);
+      comb_finish2<MODE, EST, WF>(a, i, cur, acc_phi, acc_f, z);
+      cur = nxt;
+    }
+  } else {
+    CombLoads cur;
+    if (i < items) comb_load<MODE, LAY>(a, i, cur);
+    for (; i < items; i += stride) {
+      CombLoads nxt;
+      if (i + stride < items) comb_load<MODE, LAY>(a, i + stride, nxt);
+      comb_finish<MODE, LAY, EST, WF>(a, i, cur, acc_phi, acc_f, z);
+      cur = nxt;
+    }
   }
   if constexpr ((MODE == 0 || MODE == 1) && LAY == DataLayout::Transposed) {
     if (a.zs_part && (MODE == 0 || a.gstore)) {
