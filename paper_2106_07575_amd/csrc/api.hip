@@ -141,8 +141,11 @@ Layout layout(const ptyg_dims* d, bool joint, bool batched = false, bool views =
     // GRAD sums of |G psi|^2 (one per block), then the rows of the direction
     // sums (object only the DIR kernel's, joint the patch sums')
     L.zparts = o;
+    // (256^2 joint: the direction forward's per-block patch sums, 2 rows of
+    // its 4 k blocks)
     const size_t rows = std::max<size_t>({2 * L.z_blocks, (size_t)vec_blocks((int64_t)obj_n),
-                                          2 * (size_t)patch_sums_blocks(d->k, d->n)});
+                                          2 * (size_t)patch_sums_blocks(d->k, d->n),
+                                          d->n == 256 ? 8 * (size_t)d->k : 0});
     o = align_up(o + (L.n_partials + rows * 4) * sizeof(double));
     L.zsums = L.scalars + kZsSlot * sizeof(double);
     const size_t far_bytes = std::max<size_t>(cap, 1) * sizeof(float2);
@@ -810,8 +813,11 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
           fa.dobj = eta_o;
           fa.probe = probe;
           fa.dprobe = eta_p;
+          // 256^2: the first-order transform also forms the patch sums
+          if (dims->n == 256) fa.ps_part = zparts;
           PTYG_HIP(launch_fwd_t(fa, true, s));
           PatArgs fc = fa;
+          fc.ps_part = nullptr;
           fc.far = far_c;
           fc.obj = eta_o;
           fc.probe = eta_p;
@@ -822,12 +828,16 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
       }
       if (joint) {
         // the polynomial's coefficients over the patches (Parseval): rows
-        // (Re a b*, 0, |b|^2, 0) and (Re a c*, Re b c*, |c|^2, 0)
-        const int psb = patch_sums_blocks(dims->k, dims->n);
-        PTYG_HIP(launch_patch_sums(obj, eta_o, probe, eta_p, pos, dims->k, dims->obj_w, dims->n, zparts,
-                                   zparts + 4 * psb, s));
-        PTYG_HIP(launch_finalize2(FinJob{zparts, psb, 4, zsums + 4}, FinJob{zparts + 4 * psb, psb, 4, zsums + 8}, 2,
-                                  s));
+        // (Re a b*, 0, |b|^2, 0) and (Re a c*, Re b c*, |c|^2, 0); at 256^2
+        // the first-order transform above wrote them per block
+        int psb = 4 * dims->k;
+        if (dims->n != 256) {
+          psb = patch_sums_blocks(dims->k, dims->n);
+          PTYG_HIP(launch_patch_sums(obj, eta_o, probe, eta_p, pos, dims->k, dims->obj_w, dims->n, zparts,
+                                     zparts + 4 * (size_t)psb, s));
+        }
+        PTYG_HIP(launch_finalize2(FinJob{zparts, psb, 4, zsums + 4},
+                                  FinJob{zparts + 4 * (size_t)psb, psb, 4, zsums + 8}, 2, s));
       }
       LsArgs la{};
       la.A = far_a;

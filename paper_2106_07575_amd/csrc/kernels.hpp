@@ -43,6 +43,11 @@ struct PatArgs {
   // GRAD / MINFUNC: also form Eq. ML's F per pixel (the API calls report it;
   // the solver forms it from Phi and a data constant)
   int want_f;
+  // 256^2 joint direction forward (first-order term): when set, per-block
+  // patch sums of a = p psi, b = p eta + eta_p psi, c = eta_p eta, two rows
+  // of 4 per block: (Re a b*, 0, |b|^2, 0) at ps_part[4 blk], (Re a c*,
+  // Re b c*, |c|^2, 0) at ps_part[4 (blocks + blk)]
+  double* ps_part;
 };
 
 // Batched line search over stored far fields: trial j evaluates the

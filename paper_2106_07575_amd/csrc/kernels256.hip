@@ -36,9 +36,12 @@ __device__ __forceinline__ float2 w256(int e, int sign) {
 }
 
 // Gather the (p, q) sub-grid of (p + gamma dp) * (psi + gamma eta) patch k,
-// or with LIN of the first-order direction term p * eta + dp * psi.
-template <bool LINC_O, bool LINC_P, bool LIN = false>
-__device__ __forceinline__ void gather_sub(float2* v, const PatArgs& a, const Lane& L, int2 rc, int p, int q) {
+// or with LIN of the first-order direction term p * eta + dp * psi; with PS
+// also the lane's FP64 patch sums ps[5] = (Re a b*, |b|^2, Re a c*,
+// Re b c*, |c|^2) of a = p psi, b = p eta + dp psi, c = dp eta.
+template <bool LINC_O, bool LINC_P, bool LIN = false, bool PS = false>
+__device__ __forceinline__ void gather_sub(float2* v, const PatArgs& a, const Lane& L, int2 rc, int p, int q,
+                                           double* ps = nullptr) {
   // slot m -> sub-row u' = 2m + h, sub-col v' = line -> patch (2u' + p, 2v' + q)
   const uint32_t lo = (L.h ? 2u * (uint32_t)a.W : 0u) + 2u * (uint32_t)L.line;
   const size_t corner = (size_t)(rc.x + p) * a.W + rc.y + q;
@@ -54,7 +57,16 @@ __device__ __forceinline__ void gather_sub(float2* v, const PatArgs& a, const La
         const size_t row = corner + (size_t)(4 * m) * a.W;
         const float2 o = (a.obj + row)[lo], e = (a.dobj + row)[lo];
         const float2 pr = (pb + 4 * m * NB)[plo], dp = (dpb + 4 * m * NB)[plo];
-        v[m] = cadd(cmul(pr, e), cmul(dp, o));
+        const float2 bv = cadd(cmul(pr, e), cmul(dp, o));
+        v[m] = bv;
+        if constexpr (PS) {
+          const float2 av = cmul(pr, o), cv = cmul(dp, e);
+          ps[0] += (double)av.x * bv.x + (double)av.y * bv.y;
+          ps[1] += (double)bv.x * bv.x + (double)bv.y * bv.y;
+          ps[2] += (double)av.x * cv.x + (double)av.y * cv.y;
+          ps[3] += (double)bv.x * cv.x + (double)bv.y * cv.y;
+          ps[4] += (double)cv.x * cv.x + (double)cv.y * cv.y;
+        }
       }
     }
     __builtin_amdgcn_sched_barrier(0);
@@ -95,16 +107,41 @@ __device__ __forceinline__ void gather_sub(float2* v, const PatArgs& a, const La
 
 // U layout per pattern: [pq][b][a] for Y / R (transposed sub-grids, coalesced
 // for the row layout), [pq][u'][v'] for u (natural sub-grids).
-template <bool LINC_O, bool LINC_P, bool LIN = false>
+template <bool LINC_O, bool LINC_P, bool LIN = false, bool PS = false>
 __global__ PTYG_SUB_KERNEL void k_sub_fwd(PatArgs a) {
+  static_assert(!PS || LIN, "patch sums with the first-order term");
   __shared__ float2 lds[G::LDS_ELEMS];
+  __shared__ double psred[PS ? 5 * (G::WG / 64) : 1];
   const int blk = blockIdx.x;
   const int k = blk >> 2, pq = blk & 3, p = pq >> 1, q = pq & 1;
-  if (k >= a.K) return;
+  if (k >= a.K) return;  // the grid is exactly 4 K blocks
   const Lane L = lane_info<NS>();
   const int2 rc = a.pos[k];
   float2 v[G::E];
-  gather_sub<LINC_O, LINC_P, LIN>(v, a, L, rc, p, q);
+  double ps[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+  gather_sub<LINC_O, LINC_P, LIN, PS>(v, a, L, rc, p, q, ps);
+  if constexpr (PS) {
+    // block sums in a fixed order: lanes by shuffle, then the four waves
+#pragma unroll
+    for (int i = 0; i < 5; ++i)
+#pragma unroll
+      for (int off = 32; off > 0; off >>= 1) ps[i] += __shfl_xor(ps[i], off);
+    if ((threadIdx.x & 63) == 0)
+#pragma unroll
+      for (int i = 0; i < 5; ++i) psred[5 * (threadIdx.x >> 6) + i] = ps[i];
+    __syncthreads();
+    if (threadIdx.x < 8) {
+      // row 0 (Re a b*, 0, |b|^2, 0), row 1 (Re a c*, Re b c*, |c|^2, 0)
+      const int e = threadIdx.x & 3, r = threadIdx.x >> 2;
+      const int si = r == 0 ? (e == 0 ? 0 : (e == 2 ? 1 : -1)) : (e == 3 ? -1 : 2 + e);
+      double t = 0.0;
+      if (si >= 0) {
+#pragma unroll
+        for (int w = 0; w < G::WG / 64; ++w) t += psred[5 * w + si];
+      }
+      a.ps_part[4 * ((r ? (size_t)gridDim.x : 0) + blk) + e] = t;
+    }
+  }
   fwd_line<NS>(v, L.h);
   transpose_c2r<NS>(v, lds, L);
   fwd_line<NS>(v, L.h);
@@ -542,7 +579,8 @@ hipError_t launch_fwd_t256(const PatArgs& a, bool lin, hipStream_t s) {
   if (!staged_ok(a) || !a.far || !a.obj || !a.probe) return hipErrorInvalidValue;
   if (lin && (!a.dobj || !a.dprobe)) return hipErrorInvalidValue;
   const dim3 g(4 * a.K), b(G::WG);
-  if (lin) hipLaunchKernelGGL((k_sub_fwd<false, false, true>), g, b, 0, s, a);
+  if (lin && a.ps_part) hipLaunchKernelGGL((k_sub_fwd<false, false, true, true>), g, b, 0, s, a);
+  else if (lin) hipLaunchKernelGGL((k_sub_fwd<false, false, true>), g, b, 0, s, a);
   else hipLaunchKernelGGL((k_sub_fwd<false, false>), g, b, 0, s, a);
   if (hipError_t e = hipGetLastError()) return e;
   return combine<0>(a, DataLayout::Transposed, nullptr, s);
