@@ -31,7 +31,12 @@ def workload(name: str):
     inp = synth.make_inputs(cfg)
     probe32 = inp.probe.astype(np.complex64)
     obj32 = inp.obj_true.astype(np.complex64)
-    inten = np.abs(O.forward(obj32.astype(np.complex128), probe32.astype(np.complex128), inp.pos)) ** 2
+    # |G psi_true|^2 a chunk of patterns at a time (each transform is
+    # independent of the batch: the same values as one call, in less memory)
+    o64, p64 = obj32.astype(np.complex128), probe32.astype(np.complex128)
+    inten = np.empty((cfg.k, cfg.n, cfg.n))
+    for lo in range(0, cfg.k, 1024):
+        inten[lo:lo + 1024] = np.abs(O.forward(o64, p64, inp.pos[lo:lo + 1024])) ** 2
     data = synth.make_data(cfg, inten).astype(np.float32)
     return cfg, inp, probe32, obj32, data
 
@@ -117,7 +122,10 @@ def grad_bound(gpu_far, psi, probe, pos, data, want_probe=False, estimator="ml",
     fo = rel(pert["grad_obj"][reg], ref["grad_obj"][reg])
     bp = fp = None
     if want_probe:
-        lip_p = np.sqrt(np.max(np.sum(np.abs(O.gather(psi64, pos, n)) ** 2, axis=0)))
+        acc = np.zeros((n, n))
+        for lo in range(0, len(pos), 256):
+            acc += np.sum(np.abs(O.gather(psi64, pos[lo:lo + 256], n)) ** 2, axis=0)
+        lip_p = np.sqrt(np.max(acc))
         npg = np.linalg.norm(ref["grad_probe"])
         bp = (tol * npg + lip_p * dr) / npg
         fp = rel(pert["grad_probe"], ref["grad_probe"])

@@ -1,0 +1,99 @@
+"""Joint object+probe ML-CG at the large one-GPU share's full size (8192^2
+object, 256^2 probe, 16384 positions on a 48 px raster, Poisson at 1e6
+photons) from psi_0 = 1 and the probe's amplitude |p|, for the first
+iterations of Algorithm 1 (Eqs. update, DaiYuan, linesearch; the joint
+reading of the survey), both line-search modes, against the oracle's traces
+in tests/golden/ (written by tests/golden/make_c5_trace.py from the oracle
+alone: FP64, and with every transform rounded to FP32).
+
+* Phi at the start to the objective bar (1e-5); a monotone objective.
+* Decisions: identical step and accepted trial up to a first disagreement,
+  which must be legitimate (_cases.agreed_iterations: a tie, or a Dai-Yuan
+  coefficient the FP32-transform oracle already moves by 1% or more).
+* The first step's 2-norm (object and probe blocks together) within the
+  start's gradient bound, when the first decision agrees.
+* Object windows (ten 16 x 16) and probe windows (four 16 x 16) after every
+  stored iteration within max(1e-3, c x) the FP32-transform oracle's own
+  distance from the FP64 one, c the larger block's trajectory factor at the
+  start (_cases.grad_bound, _cases.trajectory_factor), as for the
+  single-projection traces."""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from _cases import agreed_iterations, c5_workload, grad_bound, rel, trajectory_factor
+from _gpu import dev, lib
+
+pytestmark = pytest.mark.gpu
+torch = pytest.importorskip("torch")
+
+GOLD = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+@pytest.fixture(scope="module")
+def P():
+    return lib()
+
+
+@pytest.fixture(scope="module")
+def gold():
+    g64 = json.load(open(os.path.join(GOLD, "c5_trace_fp64.json")))
+    g32 = json.load(open(os.path.join(GOLD, "c5_trace_fp32t.json")))
+    return g64, g32
+
+
+@pytest.fixture(scope="module")
+def start(P):
+    cfg, inp, probe, obj, data, phi0 = c5_workload()
+    psi = np.ones(obj.shape, np.complex64)
+    p0 = np.abs(probe).astype(np.complex64)
+    far = P.forward(dev(psi), dev(p0), dev(inp.pos)).cpu().numpy()
+    _, bo, bp, fo, fp = grad_bound(far, psi, p0, inp.pos, data, want_probe=True)
+    del far
+    c = max(trajectory_factor(bo, fo), trajectory_factor(bp, fp))
+    print(f"c5 start: gradient bounds object {bo:.2e} probe {bp:.2e}, fp32 floors {fo:.2e} {fp:.2e}, factor {c:.2f}")
+    return psi, p0, max(bo, bp), c
+
+
+def windows(x, corners, w):
+    return np.stack([x[r:r + w, c:c + w] for r, c in corners])
+
+
+def gold_windows(g, m, key):
+    return np.array([np.array(re) + 1j * np.array(im) for re, im in g["snapshots"][str(m)][key]])
+
+
+@pytest.mark.parametrize("ls", ["sequential", "batched"])
+def test_c5_joint_cg_against_oracle(P, gold, start, ls):
+    g64, g32 = gold
+    psi, p0, b, c = start
+    cfg, inp, probe, obj, data, phi0 = c5_workload()
+    iters = g64["iters"]
+    args = (dev(psi), dev(p0), dev(inp.pos), dev(data))
+    res = P.cg_solve(*args, iters, update_probe=True, line_search=ls)
+    tr = res.trace
+    assert res.iters_done == iters
+    print(f"c5 {ls}: gpu {[(r['gamma'], r['halvings'], r['phi']) for r in tr]}")
+    print(f"   oracle {[(r['gamma'], r['halvings'], r['phi']) for r in g64['trace']]}")
+    same, why = agreed_iterations(tr, g64["trace"], g32["trace"])
+    print(f"   decisions agree for {same} of {iters} iterations" + (f"; {why}" if why else ""))
+    phis = [r["phi"] for r in tr]
+    assert abs(phis[0] - g64["trace"][0]["phi"]) <= 1e-5 * g64["trace"][0]["phi"]
+    assert all(y <= x for x, y in zip(phis, phis[1:]))
+    if same >= 1:
+        sn, sn_o = tr[0]["step_norm"], g64["trace"][0]["step_norm"]
+        print(f"   first step norm gpu {sn:.8e} oracle {sn_o:.8e} (bound {b:.2e})")
+        assert abs(sn - sn_o) <= max(b, 1e-5) * sn_o
+    w = g64["window"]
+    for m in range(1, iters + 1):
+        r = res if m == iters else P.cg_solve(*args, m, update_probe=True, line_search=ls)
+        eo = rel(windows(r.obj.cpu().numpy(), g64["window_corners"], w), gold_windows(g64, m, "object_windows"))
+        ep = rel(windows(r.probe.cpu().numpy(), g64["probe_window_corners"], w), gold_windows(g64, m, "probe_windows"))
+        fo = rel(gold_windows(g32, m, "object_windows"), gold_windows(g64, m, "object_windows"))
+        fp = rel(gold_windows(g32, m, "probe_windows"), gold_windows(g64, m, "probe_windows"))
+        print(f"   after {m}: object windows rel {eo:.2e} (fp32 floor {fo:.2e}), probe windows rel {ep:.2e} "
+              f"(floor {fp:.2e}), bounds {max(1e-3, c * fo):.2e} / {max(1e-3, c * fp):.2e}")
+        assert eo <= max(1e-3, c * fo)
+        assert ep <= max(1e-3, c * fp)
