@@ -136,7 +136,10 @@ const char* ptyg_last_error(void);
  * NULL (then the object-only solver with the sequential line search is
  * assumed).  Includes a transposed copy of the intensities (k*n*n floats)
  * used by ptyg_cg_solve, and the stored far fields of the batched line search
- * when opts->line_search is PTYG_LS_BATCHED. */
+ * when opts->line_search is PTYG_LS_BATCHED.  Returns 0 (error text set) for
+ * invalid dims, and for the batched search when k*n*n >= 2^31 (it indexes the
+ * intensities with 32-bit integers; ptyg_cg_solve rejects that case with
+ * PTYG_E_INVAL). */
 size_t ptyg_workspace_size(const ptyg_dims* dims, const ptyg_cg_opts* opts);
 
 /* Number of pixels with d > 0 (or NaN) in data [k][n][n]: the listed pixels

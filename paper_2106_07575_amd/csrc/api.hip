@@ -185,8 +185,19 @@ Layout layout(const ptyg_dims* d, bool joint, bool batched = false, bool views =
   return L;
 }
 
+// The batched line search indexes the k n^2 intensities (and its listed
+// elements) with 32-bit integers.
+ptyg_status check_batched_size(const ptyg_dims* d) {
+  if ((int64_t)d->k * d->n * d->n >= (int64_t(1) << 31))
+    return fail(PTYG_E_INVAL, "k*n*n=%lld intensities: the batched line search takes fewer than 2^31 "
+                "(use the sequential search)", (long long)d->k * d->n * d->n);
+  return PTYG_OK;
+}
+
 ptyg_status check_ws(const ptyg_dims* d, void* ws, size_t ws_bytes, bool joint, Layout* out,
                      bool batched = false, int64_t listed = -1) {
+  if (batched)
+    if (ptyg_status st = check_batched_size(d)) return st;
   *out = layout(d, joint, batched, false, listed);
   if (!ws) return fail(PTYG_E_INVAL, "workspace is NULL");
   if (((uintptr_t)ws) % kAlign) return fail(PTYG_E_INVAL, "workspace not 256-byte aligned");
@@ -339,9 +350,9 @@ size_t ptyg_workspace_size(const ptyg_dims* dims, const ptyg_cg_opts* opts) {
     fail(PTYG_E_INVAL, "line_search=%d is not a PTYG_LS_* value", opts->line_search);
     return 0;
   }
-  return layout(dims, opts && opts->update_probe, opts && opts->line_search == PTYG_LS_BATCHED, false,
-                opts ? opts->max_listed : -1)
-      .total;
+  const bool batched = opts && opts->line_search == PTYG_LS_BATCHED;
+  if (batched && check_batched_size(dims) != PTYG_OK) return 0;
+  return layout(dims, opts && opts->update_probe, batched, false, opts ? opts->max_listed : -1).total;
 }
 
 int64_t ptyg_listed_count(const ptyg_dims* dims, const float* data, ptyg_stream_t stream) {

@@ -116,3 +116,24 @@ def test_batched_workspace_scales_with_listed_pixels():
     # below 128 the far fields are stored whole: the capacity is ignored
     s = ptyg.Dims(320, 320, 64, 49)
     assert ptyg.workspace_size(s, line_search="batched", max_listed=10) == ptyg.workspace_size(s, line_search="batched")
+
+
+def test_host_limits_without_gpu():
+    """Empty and oversized inputs are refused on the host: k = 0, an object
+    smaller than the probe, an object of 2^31 pixels, and the batched search
+    on k n^2 >= 2^31 intensities (32-bit element indices), while the same
+    problem is sized for the sequential search."""
+    from paper_2106_07575_amd import ptyg
+    if not os.path.exists(ptyg.lib_path()):
+        pytest.skip("libptyg.so not built")
+    lib = ptyg.load()
+    for d in (ptyg.Dims(64, 64, 16, 0), ptyg.Dims(15, 64, 16, 4), ptyg.Dims(65536, 32768, 16, 4)):
+        assert lib.ptyg_workspace_size(ctypes.byref(d), None) == 0
+    assert b"k=0" in lib.ptyg_last_error() or b"too large" in lib.ptyg_last_error()
+    big = ptyg.Dims(8192, 8192, 256, 32768)
+    assert ptyg.workspace_size(big) > 0
+    opts = ptyg.CgOpts(1, 0, 1.0, 0.5, 0.0, 40, 1e-32, 0.0, 1, 0, -1)
+    assert lib.ptyg_workspace_size(ctypes.byref(big), ctypes.byref(opts)) == 0
+    assert b"2^31" in lib.ptyg_last_error()
+    fits = ptyg.Dims(8192, 8192, 256, 32767)
+    assert lib.ptyg_workspace_size(ctypes.byref(fits), ctypes.byref(opts)) > 0
