@@ -135,8 +135,8 @@ const char* ptyg_last_error(void);
 /* Bytes of workspace needed by every call below for these dims; `opts` may be
  * NULL (then the object-only solver with the sequential line search is
  * assumed).  Includes a transposed copy of the intensities (k*n*n floats)
- * used by ptyg_cg_solve, and the stored far fields of the batched line search
- * when opts->line_search is PTYG_LS_BATCHED.  Returns 0 (error text set) for
+ * for n = 256 and for the batched line search, and the stored far fields of
+ * the batched line search when opts->line_search is PTYG_LS_BATCHED.  Returns 0 (error text set) for
  * invalid dims, and for the batched search when k*n*n >= 2^31 (it indexes the
  * intensities with 32-bit integers; ptyg_cg_solve rejects that case with
  * PTYG_E_INVAL). */

@@ -110,8 +110,10 @@ Layout layout(const ptyg_dims* d, bool joint, bool batched = false, bool views =
   o = align_up(o + (joint ? probe_n : 1) * sizeof(float2));
   L.grad_probe = o;
   o = align_up(o + (joint ? probe_n : 1) * sizeof(float2));
+  // per-pattern transposed intensities: read by the 256^2 radix stage and
+  // the batched search's compaction only
   L.data_t = o;
-  o = align_up(o + (size_t)d->k * probe_n * sizeof(float));
+  o = align_up(o + (batched || d->n == 256 ? (size_t)d->k * probe_n : 1) * sizeof(float));
   L.ubuf = o;
   o = align_up(o + (size_t)d->k * probe_n * sizeof(float2));
   const size_t T = (size_t)tiles_x(d->obj_w) * tiles_y(d->obj_h);
