@@ -430,7 +430,7 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
   for (int j = 0; j < kResChunk; ++j) dn[j] = load_data<N, LAY>(a.data, k, L, kOrd<N>.s[j]);
   if constexpr (SG) {
     // G psi for the batched line search, in the element order of the
-    // transposed intensities, with sum |G psi|^2.  All stores go out before
+    // transposed intensities (sum |G psi|^2 below).  All stores go out before
     // the intensity loads below: a load waits on every earlier memory
     // operation, so stores interleaved with the loads would add a wait each.
     // (Lanes of a missing pattern hold 0: zero probe.)
@@ -440,7 +440,6 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
     for (int s = 0; s < G::E; ++s) {
       if (s % 8 == 0) __builtin_amdgcn_sched_barrier(0);
       v[s] = cscale(v[s], invN);  // scaled in place: v now holds G psi
-      acc_aa += (double)v[s].x * v[s].x + (double)v[s].y * v[s].y;
       if constexpr (CP) store_compact(a.gstore, srec, L, fidx<N>(s, L.h), v[s]);
       else if (G::PPW == 1 || valid) (gk + (size_t)kFreq<N>.f[s] * N)[lo] = v[s];
     }
@@ -464,6 +463,9 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
       const int s = kOrd<N>.s[c + j];
       const float2 g = SG ? v[s] : cscale(v[s], invN);
       const float x = fmaf(g.x, g.x, g.y * g.y);
+      // sum |G psi|^2 of the batched search in the form the objective and the
+      // search pass use (the FP32 x, summed in FP64)
+      if constexpr (SG) acc_aa += (double)x;
       float phi, ft, fac;
       pixel_terms<WANT_F, EST>(x, dc[j], a.eps, phi, ft, fac);
       acc_phi += (double)phi;
@@ -1190,7 +1192,7 @@ __global__ __launch_bounds__(256) void k_ls_batch(LsArgs a) {
     if constexpr (QUAD) cv = a.C[e];
     const float dv = a.d[e];
     // this element's share of the whole-array sums (the rest is d <= 0)
-    acc[kLsBatch + 0] += (double)av.x * av.x + (double)av.y * av.y;
+    acc[kLsBatch + 0] += (double)fmaf(av.x, av.x, av.y * av.y);  // as GRAD sums |G psi|^2
     acc[kLsBatch + 1] += (double)av.x * bv.x + (double)av.y * bv.y;
     acc[kLsBatch + 2] += (double)bv.x * bv.x + (double)bv.y * bv.y;
     if constexpr (QUAD) {
@@ -1487,7 +1489,7 @@ __global__ __launch_bounds__(256) void k_ls_batch_views(LsArgs a, const int* off
     float2 cv = make_float2(0.f, 0.f);
     if constexpr (QUAD) cv = a.C[e];
     const float dv = a.d[e];
-    acc[kLsBatch + 0] += (double)av.x * av.x + (double)av.y * av.y;
+    acc[kLsBatch + 0] += (double)fmaf(av.x, av.x, av.y * av.y);  // as GRAD sums |G psi|^2
     acc[kLsBatch + 1] += (double)av.x * bv.x + (double)av.y * bv.y;
     acc[kLsBatch + 2] += (double)bv.x * bv.x + (double)bv.y * bv.y;
 #pragma unroll

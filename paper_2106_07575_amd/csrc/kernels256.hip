@@ -300,10 +300,13 @@ __device__ __forceinline__ void comb_item(const PatArgs& a, int ai, int bi, int6
           const size_t e = far_index<LAY>(k, ai + 128 * (j >> 1), bi + 128 * (j & 1));
           if (cp) store_listed(a.gstore, rec[j], e, g[j]);
           else a.gstore[e] = g[j];
-          z[0] += (double)g[j].x * g[j].x + (double)g[j].y * g[j].y;
         }
       }
       const float x = fmaf(g[j].x, g[j].x, g[j].y * g[j].y);
+      // sum |G psi|^2 of the batched search: the FP32 x summed in FP64, the
+      // form of the objective's zero-count terms and of the search pass
+      if constexpr (MODE == 1 && LAY == DataLayout::Transposed)
+        if (a.gstore) z[0] += (double)x;
       float phi, ft, fac;
       // F only where the caller reports it (the solver forms it from Phi)
       pixel_terms<WF, EST>(x, ld[j], a.eps, phi, ft, fac);
