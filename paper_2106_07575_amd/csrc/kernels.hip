@@ -717,9 +717,9 @@ __global__ __launch_bounds__(256) void k_tile_fill_k(const int2* __restrict__ po
   if (t >= 0) list[offsets[t] + atomicAdd(&cursor[t], 1)] = (int)(idx / tpp);
 }
 
-// One workgroup per tile: bitonic sort of its list in LDS (lists of up to
-// kSortMax patterns); a longer list is rebuilt in order by scanning every
-// pattern, as the per-tile fill does.
+// One workgroup per tile: bitonic sort of its list (up to 64 patterns in
+// one wave's lanes, up to kSortMax in LDS); a longer list is rebuilt in
+// order by scanning every pattern, as the per-tile fill does.
 constexpr int kSortMax = 2048;
 __global__ __launch_bounds__(256) void k_tile_sort(const int2* __restrict__ pos, int K, int W, int N,
                                                     const int* __restrict__ offsets, int* __restrict__ list) {
@@ -728,6 +728,23 @@ __global__ __launch_bounds__(256) void k_tile_sort(const int2* __restrict__ pos,
   const int t = blockIdx.x;
   const int beg = offsets[t], len = offsets[t + 1] - beg;
   if (len <= 1) return;
+  if (len <= 64) {
+    // one wave, one key per lane: bitonic network over lane shuffles (the
+    // keys are distinct pattern indices; padding sorts last)
+    if (threadIdx.x >= 64) return;
+    const int l = threadIdx.x;
+    int key = l < len ? list[beg + l] : 0x7fffffff;
+#pragma unroll
+    for (int k = 2; k <= 64; k <<= 1) {
+#pragma unroll
+      for (int j = k >> 1; j > 0; j >>= 1) {
+        const int other = __shfl_xor(key, j);
+        key = (((l & k) == 0) == ((l & j) == 0)) ? min(key, other) : max(key, other);
+      }
+    }
+    if (l < len) list[beg + l] = key;
+    return;
+  }
   if (len <= kSortMax) {
     int P = 1;
     while (P < len) P <<= 1;
@@ -773,8 +790,10 @@ __global__ __launch_bounds__(256) void k_tile_sort(const int2* __restrict__ pos,
   }
 }
 
-// Exclusive scan of counts[0..T) into offsets[0..T] (one workgroup).
-__global__ __launch_bounds__(1024) void k_scan(const int* __restrict__ counts, int T, int* __restrict__ offsets) {
+// Exclusive scan of counts[0..T) into offsets[0..T] (one workgroup); with
+// clear, counts[] is zeroed behind the scan (the fill's cursor).
+__global__ __launch_bounds__(1024) void k_scan(int* __restrict__ counts, int T, int* __restrict__ offsets,
+                                               int clear) {
   __shared__ int part[1024];
   const int per = (T + 1023) / 1024;
   const int lo = threadIdx.x * per, hi = min(T, lo + per);
@@ -792,6 +811,7 @@ __global__ __launch_bounds__(1024) void k_scan(const int* __restrict__ counts, i
   for (int i = lo; i < hi; ++i) {
     offsets[i] = run;
     run += counts[i];
+    if (clear) counts[i] = 0;  // each entry is read and cleared by this thread only
   }
   if (threadIdx.x == 1023) offsets[T] = part[1023];
 }
@@ -1730,7 +1750,7 @@ hipError_t launch_nz_count(const float* d, int64_t n, int* counts, int* offsets,
   const int64_t blocks = (n + kNzChunk - 1) / kNzChunk;
   if (blocks > (1 << 30)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_nz_count, dim3((unsigned)blocks), dim3(256), 0, s, d, n, counts);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, (int)blocks, offsets);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, (int)blocks, offsets, 0);
   return hipGetLastError();
 }
 
@@ -1776,7 +1796,7 @@ hipError_t launch_nz_compact(const float* d, int64_t n, int* counts, int* offset
   const int64_t blocks = (n + kNzChunk - 1) / kNzChunk;
   if (blocks > (1 << 30)) return hipErrorInvalidValue;
   hipLaunchKernelGGL(k_nz_count, dim3((unsigned)blocks), dim3(256), 0, s, d, n, counts);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, (int)blocks, offsets);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, (int)blocks, offsets, 0);
   hipLaunchKernelGGL(k_nz_fill, dim3((unsigned)blocks), dim3(256), 0, s, d, n, offsets, idx, seg, dc);
   return hipGetLastError();
 }
@@ -1908,8 +1928,7 @@ hipError_t launch_tile_lists(const int2* pos, int K, int H, int W, int N, int* o
   const unsigned pb = (unsigned)((pairs + 255) / 256);
   if (hipError_t e = launch_fill_i32(counts, T, 0, s)) return e;
   hipLaunchKernelGGL(k_tile_count_k, dim3(pb), dim3(256), 0, s, pos, pairs, tpp, span_x, H, W, N, counts);
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, T, offsets);
-  if (hipError_t e = launch_fill_i32(counts, T, 0, s)) return e;
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, s, counts, T, offsets, 1);  // also zeroes the cursor
   hipLaunchKernelGGL(k_tile_fill_k, dim3(pb), dim3(256), 0, s, pos, pairs, tpp, span_x, H, W, N, offsets, counts,
                      list);
   hipLaunchKernelGGL(k_tile_sort, dim3(T), dim3(256), 0, s, pos, K, W, N, offsets, list);
