@@ -410,9 +410,10 @@ __device__ __forceinline__ void comb_finish2(const PatArgs& a, int64_t i, const 
 #pragma unroll
     for (int j = 0; j < 4; ++j) {
       ly[j] = half_of(L.y[j], h);
-      ld[j] = h ? L.d[j].y : L.d[j].x;
-      P[j] = half_of(L.P[j], h);
-      Q[j] = half_of(L.Q[j], h);
+      // operands a mode does not load are not read
+      ld[j] = (MODE == 1 || MODE == 2) ? (h ? L.d[j].y : L.d[j].x) : 0.0f;
+      P[j] = (MODE == 0 && a.zs_part) ? half_of(L.P[j], h) : make_float2(0.f, 0.f);
+      Q[j] = (MODE == 0 && a.zs_part && a.zs_q) ? half_of(L.Q[j], h) : make_float2(0.f, 0.f);
     }
     comb_item<MODE, DataLayout::Transposed, EST, WF>(a, ai + h, bi, k, ly, ld, L.rec, P, Q, acc_phi, acc_f, z,
                                                      yn[h]);
