@@ -132,6 +132,29 @@ def grad_bound(gpu_far, psi, probe, pos, data, want_probe=False, estimator="ml",
     return ref, bo, bp, fo, fp
 
 
+def grad_bound_from(gpu_far, psi, probe, pos, data, start, tol=1e-5, eps=O.EPS, estimator="ml"):
+    """grad_bound's object and probe bounds from stored oracle figures at
+    the same start (gradient norms, FP32 floors and the two Lipschitz
+    constants, written by an oracle-only script): only the residual
+    difference ||r(g_hat) - r(g)|| over all patterns is computed here.
+    Returns (bound_obj, bound_probe, floor_obj, floor_probe)."""
+    psi64 = psi.astype(np.complex128)
+    p64 = probe.astype(np.complex128)
+    dr2 = 0.0
+    for lo in range(0, len(pos), 256):
+        sl = slice(lo, lo + 256)
+        g = O.forward(psi64, p64, pos[sl])
+        gh = np.asarray(gpu_far[sl]).astype(np.complex128)
+        d64 = np.asarray(data[sl], dtype=np.float64)
+        diff = _residual(gh, d64, eps, estimator) - _residual(g, d64, eps, estimator)
+        dr2 += float(np.sum(diff.real ** 2 + diff.imag ** 2))
+    dr = np.sqrt(dr2)
+    no, npg = start["grad_obj_norm"], start["grad_probe_norm"]
+    bo = (tol * no + start["lip_obj"] * dr) / no
+    bp = (tol * npg + start["lip_probe"] * dr) / npg
+    return bo, bp, start["floor_obj"], start["floor_probe"]
+
+
 def trajectory_factor(bound, floor):
     """Factor between the iterate bound of an FP32 solver and the divergence
     of the oracle's own FP32-transform trajectory: to first order a solver's

@@ -15,7 +15,9 @@ alone: FP64, and with every transform rounded to FP32).
 * Object windows (ten 16 x 16) and probe windows (four 16 x 16) after every
   stored iteration within max(1e-3, c x) the FP32-transform oracle's own
   distance from the FP64 one, c the larger block's trajectory factor at the
-  start (_cases.grad_bound, _cases.trajectory_factor), as for the
+  start (_cases.grad_bound_from with the oracle's gradient norms, FP32
+  floors and Lipschitz constants at that start from
+  tests/golden/make_c5_start.py; _cases.trajectory_factor), as for the
   single-projection traces."""
 import json
 import os
@@ -23,7 +25,7 @@ import os
 import numpy as np
 import pytest
 
-from _cases import agreed_iterations, c5_workload, grad_bound, rel, trajectory_factor
+from _cases import agreed_iterations, c5_workload, grad_bound_from, rel, trajectory_factor
 from _gpu import dev, lib
 
 pytestmark = pytest.mark.gpu
@@ -50,7 +52,8 @@ def start(P):
     psi = np.ones(obj.shape, np.complex64)
     p0 = np.abs(probe).astype(np.complex64)
     far = P.forward(dev(psi), dev(p0), dev(inp.pos)).cpu().numpy()
-    _, bo, bp, fo, fp = grad_bound(far, psi, p0, inp.pos, data, want_probe=True)
+    figs = json.load(open(os.path.join(GOLD, "c5_start.json")))
+    bo, bp, fo, fp = grad_bound_from(far, psi, p0, inp.pos, data, figs)
     del far
     c = max(trajectory_factor(bo, fo), trajectory_factor(bp, fp))
     print(f"c5 start: gradient bounds object {bo:.2e} probe {bp:.2e}, fp32 floors {fo:.2e} {fp:.2e}, factor {c:.2f}")
