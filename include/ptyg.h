@@ -214,8 +214,11 @@ ptyg_status ptyg_minfunc_noalloc(const ptyg_dims* dims, const ptyg_c64* obj, con
  * iters_done: HOST (nullable).  Synchronous: it waits on `stream` once per
  * iteration and once per line-search trial (sequential search) or per pass of
  * up to 16 trials (batched search), a few bytes read back each time.
- * Returns PTYG_E_BOUNDS for a bad scan position and PTYG_E_NONFINITE if the
- * objective at an iterate is not finite. */
+ * Returns PTYG_E_BOUNDS for a bad scan position, PTYG_E_NONFINITE if the
+ * objective at an iterate is not finite (obj and probe then hold that
+ * iterate: no update follows it), PTYG_E_WORKSPACE if the data list more pixels with
+ * d > 0 than opts->max_listed reserved, and PTYG_E_INVAL for the batched
+ * search on k*n*n >= 2^31 intensities. */
 ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj, ptyg_c64* probe, const int32_t* pos,
                           const float* data, const ptyg_cg_opts* opts, void* ws, size_t ws_bytes,
                           ptyg_cg_iter_stats* trace, int32_t* iters_done, ptyg_stream_t stream);
