@@ -268,15 +268,23 @@ Timing g_timing;
 // Host side of the solver's scalar readbacks: pinned, so that a copy is
 // asynchronous and one stream synchronisation covers it (a copy into pageable
 // memory is staged and waits by itself).  One buffer per host thread,
-// allocated on its first solve and kept until the process ends.
+// allocated on its first solve and freed when the thread ends (every solve
+// has synchronised its stream before it returns, so no copy is pending).
+struct PinnedScalars {
+  double* p = nullptr;
+  ~PinnedScalars() {
+    if (p) (void)hipHostFree(p);
+  }
+};
+
 double* readback_buffer() {
-  thread_local double* buf = nullptr;
-  if (!buf) {
+  thread_local PinnedScalars buf;
+  if (!buf.p) {
     void* p = nullptr;
     if (hipHostMalloc(&p, kScalars * sizeof(double), hipHostMallocDefault) != hipSuccess) return nullptr;
-    buf = static_cast<double*>(p);
+    buf.p = static_cast<double*>(p);
   }
-  return buf;
+  return buf.p;
 }
 
 struct TimedLaunch {
@@ -715,6 +723,11 @@ ptyg_status ptyg_cg_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
   } rb;
   if (batched) PTYG_HIP(hipEventCreateWithFlags(&rb.e, hipEventDisableTiming));
   hipEvent_t rb_ev = rb.e;
+  // every return, the error returns included, leaves no copy into h in flight
+  struct StreamDrain {
+    hipStream_t s;
+    ~StreamDrain() { (void)hipStreamSynchronize(s); }
+  } drain{s};
   bool restart = true;
   const int nvb_o = vec_blocks(on), nvb_p = vec_blocks(pn);
   // the direction update reads its coefficient from the device: start from a

@@ -112,9 +112,13 @@ __global__ PTYG_SUB_KERNEL void k_sub_fwd(PatArgs a) {
   static_assert(!PS || LIN, "patch sums with the first-order term");
   __shared__ float2 lds[G::LDS_ELEMS];
   __shared__ double psred[PS ? 5 * (G::WG / 64) : 1];
-  const int blk = blockIdx.x;
-  const int k = blk >> 2, pq = blk & 3, p = pq >> 1, q = pq & 1;
-  if (k >= a.K) return;  // the grid is exactly 4 K blocks
+  // workgroup b runs on XCD b % 8: the four sub-grids of a pattern (which
+  // read the same cache lines of its patch, every other column each) go to
+  // one XCD, consecutive patterns to consecutive XCDs
+  const int g = blockIdx.x >> 5, r32 = blockIdx.x & 31;
+  const int k = 8 * g + (r32 & 7), pq = r32 >> 3, p = pq >> 1, q = pq & 1;
+  if (k >= a.K) return;  // the grid is 32 ceil(K / 8) blocks
+  const int blk = 4 * k + pq;
   const Lane L = lane_info<NS>();
   const int2 rc = a.pos[k];
   float2 v[G::E];
@@ -139,7 +143,7 @@ __global__ PTYG_SUB_KERNEL void k_sub_fwd(PatArgs a) {
 #pragma unroll
         for (int w = 0; w < G::WG / 64; ++w) t += psred[5 * w + si];
       }
-      a.ps_part[4 * ((r ? (size_t)gridDim.x : 0) + blk) + e] = t;
+      a.ps_part[4 * ((r ? 4 * (size_t)a.K : 0) + blk) + e] = t;
     }
   }
   fwd_line<NS>(v, L.h);
@@ -525,8 +529,11 @@ hipError_t combine(const PatArgs& a, DataLayout lay, int* blocks_out, hipStream_
   });
 }
 
+// k_sub_fwd's grid: four workgroups per pattern, in groups of eight patterns
+dim3 sub_fwd_grid(int K) { return dim3(32 * ((K + 7) / 8)); }
+
 hipError_t sub_fwd(const PatArgs& a, hipStream_t s) {
-  const dim3 g(4 * a.K), b(G::WG);
+  const dim3 g = sub_fwd_grid(a.K), b(G::WG);
   const bool lo = a.dobj != nullptr, lp = a.dprobe != nullptr;
   if (lo && lp) hipLaunchKernelGGL((k_sub_fwd<true, true>), g, b, 0, s, a);
   else if (lo) hipLaunchKernelGGL((k_sub_fwd<true, false>), g, b, 0, s, a);
@@ -582,7 +589,7 @@ int fwd_t256_blocks(int K) { return combine_blocks(K); }
 hipError_t launch_fwd_t256(const PatArgs& a, bool lin, hipStream_t s) {
   if (!staged_ok(a) || !a.far || !a.obj || !a.probe) return hipErrorInvalidValue;
   if (lin && (!a.dobj || !a.dprobe)) return hipErrorInvalidValue;
-  const dim3 g(4 * a.K), b(G::WG);
+  const dim3 g = sub_fwd_grid(a.K), b(G::WG);
   if (lin && a.ps_part) hipLaunchKernelGGL((k_sub_fwd<false, false, true, true>), g, b, 0, s, a);
   else if (lin) hipLaunchKernelGGL((k_sub_fwd<false, false, true>), g, b, 0, s, a);
   else hipLaunchKernelGGL((k_sub_fwd<false, false>), g, b, 0, s, a);

@@ -6,7 +6,9 @@ oracle (Eqs. fwd_model, ML, gradient; Algorithm 1):
   last valid position on both axes), for every probe size: forward and
   adjoint (object and probe) at 1e-5, Phi at 1e-5, the object and probe
   gradients within the bound of _cases.grad_bound;
-* zero CG iterations in both line-search modes: nothing changes, no trace."""
+* zero CG iterations in both line-search modes: nothing changes, no trace;
+* solves on host threads that end (each frees its pinned readback buffer)
+  give the same iterates as on the test's own thread."""
 import numpy as np
 import pytest
 
@@ -76,3 +78,22 @@ def test_zero_iterations_change_nothing(P, ls):
     res = P.cg_solve(dev(psi), dev(probe), dev(pos), dev(data), 0, update_probe=True, line_search=ls)
     assert res.iters_done == 0 and res.trace == []
     assert np.array_equal(res.obj.cpu().numpy(), psi) and np.array_equal(res.probe.cpu().numpy(), probe)
+
+
+@pytest.mark.parametrize("ls", ["sequential", "batched"])
+def test_solves_on_threads_that_end(P, ls):
+    # each host thread owns a pinned readback buffer, freed when the thread
+    # ends: solves on short-lived threads match the same solve on this one
+    import threading
+
+    probe, obj, pos, data = case(32, 80, 70, [[0, 0], [20, 10], [48, 38]], 510)
+    args = lambda: (dev(np.ones(obj.shape, np.complex64)), dev(probe), dev(pos), dev(data), 3)
+    ref = P.cg_solve(*args(), line_search=ls)
+    for _ in range(3):
+        out = {}
+        th = threading.Thread(target=lambda: out.update(r=P.cg_solve(*args(), line_search=ls)))
+        th.start()
+        th.join()
+        r = out["r"]
+        assert [t["phi"] for t in r.trace] == [t["phi"] for t in ref.trace]
+        assert np.array_equal(r.obj.cpu().numpy(), ref.obj.cpu().numpy())
