@@ -88,9 +88,9 @@ Layout layout(const ptyg_dims* d, bool joint, bool batched = false, bool views =
   Layout L{};
   const size_t obj_n = (size_t)d->obj_h * d->obj_w;
   const size_t probe_n = (size_t)d->n * d->n;
-  // partial (phi, f) pairs: pattern kernels use <= k + 8 blocks, the 256^2
-  // radix stage <= 8192, vector kernels <= 2048
-  L.n_partials = std::max<size_t>((size_t)d->k + 16, 8192) + 16;
+  // partial (phi, f) pairs: pattern kernels use <= k + 8 blocks, a 256^2
+  // GRAD pass grad256_blocks(k), vector kernels <= 2048
+  L.n_partials = std::max<size_t>({(size_t)d->k + 16, 8192, d->n == 256 ? (size_t)grad256_blocks(d->k) : 0}) + 16;
   size_t o = 0;
   L.partials = o;
   o = align_up(o + L.n_partials * 2 * sizeof(double));

@@ -46,8 +46,9 @@ struct PatArgs {
   // 256^2 joint direction forward (first-order term): when set, per-block
   // patch sums of a = p psi, b = p eta + eta_p psi, c = eta_p eta, two rows
   // of 4 per block: (Re a b*, 0, |b|^2, 0) at ps_part[4 blk], (Re a c*,
-  // Re b c*, |c|^2, 0) at ps_part[4 (blocks + blk)]
+  // Re b c*, |c|^2, 0) at ps_part[4 (4 ps_k + blk)], blk = 4 k + sub-grid
   double* ps_part;
+  int ps_k;  // patterns of the whole sequence of staged chunks (set by the 256^2 launchers)
 };
 
 // Batched line search over stored far fields: trial j evaluates the
@@ -176,7 +177,11 @@ hipError_t launch_minfunc(const PatArgs& a, DataLayout lay, int* blocks_out, hip
 // (the first-order term of (p + g dp)(psi + g eta)).
 hipError_t launch_fwd_t(const PatArgs& a, bool lin, hipStream_t s);
 hipError_t launch_fwd_t256(const PatArgs& a, bool lin, hipStream_t s);
+// Rows of per-workgroup partials that a 256^2 direction forward / GRAD pass
+// over K patterns writes (radix-stage workgroups; GRAD sums them over its
+// staged chunks).
 int fwd_t256_blocks(int K);
+int grad256_blocks(int K);
 // Objective partials of a.J trials; `blocks_out` rows of kLsRow doubles.
 hipError_t launch_ls_batch(const LsArgs& a, int* blocks_out, hipStream_t s);
 // Joint-mode search coefficients over the patches (a' = p psi_k,

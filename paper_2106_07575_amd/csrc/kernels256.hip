@@ -13,7 +13,8 @@
 //   k_sub_inv    inverse sub-transforms -> u_pq, in place (polyphase layout)
 // after which k_tile_sum / k_probe_partial form G^H with the polyphase
 // index map.  A line-search trial is k_sub_fwd (psi + gamma eta) followed by
-// the objective-only combine.
+// the objective-only combine.  A GRAD pass runs its kernels chunk by chunk
+// over the patterns (for_chunks below).
 #include <hip/hip_runtime.h>
 
 #include "kernels.hpp"
@@ -143,7 +144,7 @@ __global__ PTYG_SUB_KERNEL void k_sub_fwd(PatArgs a) {
 #pragma unroll
         for (int w = 0; w < G::WG / 64; ++w) t += psred[5 * w + si];
       }
-      a.ps_part[4 * ((r ? 4 * (size_t)a.K : 0) + blk) + e] = t;
+      a.ps_part[4 * ((r ? 4 * (size_t)a.ps_k : 0) + blk) + e] = t;
     }
   }
   fwd_line<NS>(v, L.h);
@@ -495,19 +496,70 @@ __global__ __launch_bounds__(256) void k_combine(PatArgs a, int64_t items) {
   }
 }
 
-constexpr int kCombineBlocks = 8192;
+// Staged chunks: a GRAD pass (three kernels, two of which read back what
+// the previous one left in U) runs chunk by chunk over the patterns
+// (sub-transforms, radix stage and inverse sub-transforms of kChunk256
+// patterns, then the next chunk), so the 512 KiB per pattern staged in U is
+// read back while the memory-side cache still holds it instead of after a
+// whole 8 GiB pass.  A forward-only pass reads U back once; there the tail
+// of every chunk's launches costs more than the cache saves, so it runs as
+// one chunk.
+constexpr int kChunk256 = 512;
+constexpr int kChunkCombineBlocks = 2048;  // radix-stage workgroups per GRAD chunk
+constexpr int kCombineBlocks = 8192;       // radix-stage workgroups of a one-chunk pass
 
-int combine_blocks(int K) {
+int combine_blocks(int K, int cap) {
   const int64_t items = (int64_t)K * SUB;
   const int64_t nb = (items + 255) / 256;
-  return (int)(nb < kCombineBlocks ? nb : kCombineBlocks);
+  return (int)(nb < cap ? nb : cap);
+}
+
+int pass_blocks(int K, int chunk, int cap) {
+  int t = 0;
+  for (int k0 = 0; k0 < K; k0 += chunk) t += combine_blocks(K - k0 < chunk ? K - k0 : chunk, cap);
+  return t;
+}
+
+// The arguments of one chunk [k0, k0 + kn): per-pattern arrays offset to
+// pattern k0 (compacted stores keep their whole-array indices: their
+// records are offset instead), per-workgroup rows after the `before` rows
+// of the earlier chunks (zs_width doubles per row).
+PatArgs chunk_of(const PatArgs& a, int k0, int kn, int before, int zs_width) {
+  PatArgs c = a;
+  const size_t off = (size_t)k0 * NB * NB;
+  c.K = kn;
+  c.ps_k = a.K;
+  c.pos = a.pos + k0;
+  c.ubuf = a.ubuf + off;
+  if (a.data) c.data = a.data + off;
+  if (a.far && !a.cseg) c.far = a.far + off;
+  if (a.gstore && !a.cseg) c.gstore = a.gstore + off;
+  if (a.cseg) c.cseg = a.cseg + off / 32;
+  if (a.zs_p) c.zs_p = a.zs_p + off;
+  if (a.zs_q) c.zs_q = a.zs_q + off;
+  if (a.partials) c.partials = a.partials + 2 * (size_t)before;
+  if (a.zs_part) c.zs_part = a.zs_part + (size_t)zs_width * before;
+  if (a.ps_part) c.ps_part = a.ps_part + 16 * (size_t)k0;
+  return c;
+}
+
+// Runs f(chunk arguments) over chunks of `chunk` patterns in ascending
+// order; each chunk's radix stage takes combine_blocks(kn, cap) workgroups.
+template <typename F>
+hipError_t for_chunks(const PatArgs& a, int chunk, int cap, int zs_width, F&& f) {
+  int before = 0;
+  for (int k0 = 0; k0 < a.K; k0 += chunk) {
+    const int kn = a.K - k0 < chunk ? a.K - k0 : chunk;
+    if (hipError_t e = f(chunk_of(a, k0, kn, before, zs_width))) return e;
+    before += combine_blocks(kn, cap);
+  }
+  return hipSuccess;
 }
 
 template <int MODE>
-hipError_t combine(const PatArgs& a, DataLayout lay, int* blocks_out, hipStream_t s) {
-  const int nb = combine_blocks(a.K);
+hipError_t combine(const PatArgs& a, DataLayout lay, int cap, hipStream_t s) {
+  const int nb = combine_blocks(a.K, cap);
   const int64_t items = (int64_t)a.K * SUB;
-  if (blocks_out) *blocks_out = nb;
   // the estimator only enters the modes with objective terms
   constexpr bool OBJ = MODE == 1 || MODE == 2 || MODE == 4;
   const int est = OBJ ? a.est : 0;
@@ -558,49 +610,61 @@ hipError_t launch_forward256(const PatArgs& a, hipStream_t s) {
   PatArgs b = a;
   b.dobj = nullptr;
   b.dprobe = nullptr;
+  b.ps_k = a.K;
   if (hipError_t e = sub_fwd(b, s)) return e;
-  return combine<0>(b, DataLayout::Rows, nullptr, s);
+  return combine<0>(b, DataLayout::Rows, kCombineBlocks, s);
 }
 
 hipError_t launch_adjoint256(const PatArgs& a, hipStream_t s) {
   if (!staged_ok(a) || !a.far) return hipErrorInvalidValue;
-  if (hipError_t e = combine<3>(a, DataLayout::Rows, nullptr, s)) return e;
+  if (hipError_t e = combine<3>(a, DataLayout::Rows, kCombineBlocks, s)) return e;
   return sub_inv(a, s);
 }
+
+int grad256_blocks(int K) { return pass_blocks(K, kChunk256, kChunkCombineBlocks); }
 
 hipError_t launch_grad256(const PatArgs& a, DataLayout lay, int* blocks_out, hipStream_t s) {
   if (!staged_ok(a) || !a.data || !a.partials || !a.obj || !a.probe) return hipErrorInvalidValue;
   PatArgs b = a;
   b.dobj = nullptr;
   b.dprobe = nullptr;
-  if (hipError_t e = sub_fwd(b, s)) return e;
-  if (hipError_t e = combine<1>(b, lay, blocks_out, s)) return e;
-  return sub_inv(b, s);
+  if (blocks_out) *blocks_out = grad256_blocks(a.K);
+  return for_chunks(b, kChunk256, kChunkCombineBlocks, 1, [&](const PatArgs& c) {
+    if (hipError_t e = sub_fwd(c, s)) return e;
+    if (hipError_t e = combine<1>(c, lay, kChunkCombineBlocks, s)) return e;
+    return sub_inv(c, s);
+  });
 }
 
 hipError_t launch_grad_far256(const PatArgs& a, int* blocks_out, hipStream_t s) {
   if (!staged_ok(a) || !a.far || !a.data || !a.partials) return hipErrorInvalidValue;
-  if (hipError_t e = combine<4>(a, DataLayout::Rows, blocks_out, s)) return e;
-  return sub_inv(a, s);
+  if (blocks_out) *blocks_out = grad256_blocks(a.K);
+  return for_chunks(a, kChunk256, kChunkCombineBlocks, 0, [&](const PatArgs& c) {
+    if (hipError_t e = combine<4>(c, DataLayout::Rows, kChunkCombineBlocks, s)) return e;
+    return sub_inv(c, s);
+  });
 }
 
-int fwd_t256_blocks(int K) { return combine_blocks(K); }
+int fwd_t256_blocks(int K) { return combine_blocks(K, kCombineBlocks); }
 
 hipError_t launch_fwd_t256(const PatArgs& a, bool lin, hipStream_t s) {
   if (!staged_ok(a) || !a.far || !a.obj || !a.probe) return hipErrorInvalidValue;
   if (lin && (!a.dobj || !a.dprobe)) return hipErrorInvalidValue;
-  const dim3 g = sub_fwd_grid(a.K), b(G::WG);
-  if (lin && a.ps_part) hipLaunchKernelGGL((k_sub_fwd<false, false, true, true>), g, b, 0, s, a);
-  else if (lin) hipLaunchKernelGGL((k_sub_fwd<false, false, true>), g, b, 0, s, a);
-  else hipLaunchKernelGGL((k_sub_fwd<false, false>), g, b, 0, s, a);
+  PatArgs b = a;
+  b.ps_k = a.K;
+  const dim3 g = sub_fwd_grid(b.K), bl(G::WG);
+  if (lin && b.ps_part) hipLaunchKernelGGL((k_sub_fwd<false, false, true, true>), g, bl, 0, s, b);
+  else if (lin) hipLaunchKernelGGL((k_sub_fwd<false, false, true>), g, bl, 0, s, b);
+  else hipLaunchKernelGGL((k_sub_fwd<false, false>), g, bl, 0, s, b);
   if (hipError_t e = hipGetLastError()) return e;
-  return combine<0>(a, DataLayout::Transposed, nullptr, s);
+  return combine<0>(b, DataLayout::Transposed, kCombineBlocks, s);
 }
 
 hipError_t launch_minfunc256(const PatArgs& a, DataLayout lay, int* blocks_out, hipStream_t s) {
   if (!staged_ok(a) || !a.data || !a.partials || !a.obj || !a.probe) return hipErrorInvalidValue;
+  if (blocks_out) *blocks_out = combine_blocks(a.K, kCombineBlocks);
   if (hipError_t e = sub_fwd(a, s)) return e;
-  return combine<2>(a, lay, blocks_out, s);
+  return combine<2>(a, lay, kCombineBlocks, s);
 }
 
 }  // namespace ptyg
