@@ -82,7 +82,7 @@ HBM_PEAK_GBS = 8000.0
 TRAFFIC_BYTES = {
     # solver GRAD kernel 1078.9 MB + ordered overlap sum 710.7 MB (+ finalize < 1 MB),
     # profiles/cg_c2_batched_ls_hbm_bytes.md
-    ("grad_unit", "c2", "batched"): 1789.6e6,
+    ("grad_unit", "c2", "batched"): 1744.6e6,
 }
 FP32_PEAK_TFLOPS = 157.3
 

@@ -422,18 +422,25 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
   }
   const float invN = 1.0f / N;
   double acc_phi = 0.0, acc_f = 0.0, acc_aa = 0.0;
-  // intensities one chunk ahead: chunk c + 1's loads are issued before
-  // chunk c's arithmetic, so their latency overlaps it; the first chunk goes
-  // out before the G psi stores (a load waits for every earlier store)
-  float dn[kResChunk];
+  // intensities PF chunks ahead: chunk c + PF's loads are issued before
+  // chunk c's arithmetic, so their latency overlaps it.  With the G psi
+  // stores, the first PF chunks go out before the stores, and a load issued
+  // after them waits for every store (one in-order counter for loads and
+  // stores): four chunks ahead, that wait comes four chunks of arithmetic
+  // after the stores (the solver's GRAD 398 -> 387 us at 2048^2 / 4096
+  // patterns, 246 VGPRs; six chunks spill)
+  constexpr int PF = SG ? 4 : 1;
+  float dn[PF][kResChunk];
 #pragma unroll
-  for (int j = 0; j < kResChunk; ++j) dn[j] = load_data<N, LAY>(a.data, k, L, kOrd<N>.s[j]);
+  for (int q = 0; q < PF; ++q)
+#pragma unroll
+    for (int j = 0; j < kResChunk; ++j) dn[q][j] = load_data<N, LAY>(a.data, k, L, kOrd<N>.s[q * kResChunk + j]);
   if constexpr (SG) {
     // G psi for the batched line search, in the element order of the
-    // transposed intensities (sum |G psi|^2 below).  All stores go out before
-    // the intensity loads below: a load waits on every earlier memory
-    // operation, so stores interleaved with the loads would add a wait each.
-    // (Lanes of a missing pattern hold 0: zero probe.)
+    // transposed intensities (sum |G psi|^2 below).  All stores go out
+    // together: stores between the residual loop's loads would each add a
+    // wait, and doing them inside that loop spills.  (Lanes of a missing
+    // pattern hold 0: zero probe.)
     const uint32_t lo = lane_off<N>(L, (G::E / 2) * N);
     float2* gk = a.gstore + (size_t)k * N * N;
 #pragma unroll
@@ -451,12 +458,13 @@ __global__ PTYG_PATTERN_KERNEL(N) void k_grad(PatArgs a) {
 #pragma unroll
   for (int c = 0; c < G::E; c += kResChunk) {
     __builtin_amdgcn_sched_barrier(0);
+    const int q = (c / kResChunk) % PF;  // a constant once the loop is unrolled
     float dc[kResChunk];
 #pragma unroll
-    for (int j = 0; j < kResChunk; ++j) dc[j] = dn[j];
-    if (c + kResChunk < G::E) {
+    for (int j = 0; j < kResChunk; ++j) dc[j] = dn[q][j];
+    if (c + PF * kResChunk < G::E) {
 #pragma unroll
-      for (int j = 0; j < kResChunk; ++j) dn[j] = load_data<N, LAY>(a.data, k, L, kOrd<N>.s[c + kResChunk + j]);
+      for (int j = 0; j < kResChunk; ++j) dn[q][j] = load_data<N, LAY>(a.data, k, L, kOrd<N>.s[c + PF * kResChunk + j]);
     }
 #pragma unroll
     for (int j = 0; j < kResChunk; ++j) {
