@@ -6,8 +6,9 @@ sum is exact in FP32, whatever the order).  Covered: the natural layout of
 n <= 128 (with and without the conj(probe) multiply, probe = 1 so the
 product is exact), the polyphase layout of 256^2 patterns, objects whose
 width is not a multiple of the 64-pixel tile and whose height is not a
-multiple of 16, the single-projection shape (2048^2, 128^2, 4096 positions)
-and the large one-GPU share (8192^2, 256^2, 16384 positions)."""
+multiple of 16, the single-projection shape (2048^2, 128^2, 4096 positions),
+the large one-GPU share (8192^2, 256^2, 16384 positions), and tiles crowded
+by up to thousands of patterns (each way the tile-list sort orders a list)."""
 import numpy as np
 import pytest
 
@@ -87,4 +88,19 @@ def test_tile_sum_bit_exact_large_share_shape(P):
     cfg = synth.CONFIGS["c5"]
     inp = synth.make_inputs(cfg)
     out, ref = run(P, inp.pos, (cfg.obj_h, cfg.obj_w), cfg.n, chunk=512)
+    assert np.array_equal(out, ref)
+
+
+@pytest.mark.parametrize("k,hot", [(700, 60), (700, 300), (3000, 2500), (9000, 2100)])
+def test_tile_sum_bit_exact_crowded_tiles(P, k, hot):
+    # `hot` patterns stacked on the origin (one tile list that long) among
+    # random ones on a 2048^2 object with 16^2 patterns: the tile-list sort
+    # takes a list of up to 64 in one wave's lanes (hot = 60), up to 2048 in
+    # LDS (hot = 300), and rebuilds a longer one by an ordered scan over all
+    # patterns (hot = 2100, 2500)
+    n, h, w = 16, 2048, 2048
+    rng = np.random.default_rng(k + hot)
+    pos = np.stack([rng.integers(0, h - n + 1, k), rng.integers(0, w - n + 1, k)], 1).astype(np.int32)
+    pos[rng.choice(k, hot, replace=False)] = 0
+    out, ref = run(P, pos, (h, w), n)
     assert np.array_equal(out, ref)
