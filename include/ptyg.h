@@ -245,9 +245,13 @@ ptyg_status ptyg_gd_solve(const ptyg_dims* dims, ptyg_c64* obj, ptyg_c64* probe,
  * patterns, and every reduction, direction, step and line-search decision
  * is per view.  Each view's iterates are those ptyg_cg_solve gives for it
  * alone, up to the order of floating-point sums.
- * dims: ONE view (obj_h, obj_w, n, k); n <= 128; k a multiple of the
- * patterns per workgroup (16 for n = 16, 8 for n = 32, 2 for n = 64);
- * k*n*n a multiple of 4096.
+ * dims: ONE view (obj_h, obj_w, n, k); n <= 128.  Each view's k patterns
+ * are padded in the workspace to a multiple of the patterns per workgroup
+ * (16 for n = 16, 8 for n = 32, 2 for n = 64) with k*n*n a multiple of 4096;
+ * the padding patterns lie on n zero rows added below the stacked views,
+ * with zero intensities, and contribute nothing.  With padding, the object
+ * and the intensities are staged in the workspace and the iterates copied
+ * back to obj before the call returns (also on an error return).
  * obj: [views][obj_h][obj_w] (in: psi_0, out: iterates); probe: [n][n],
  * shared and fixed (object-only); pos: [views][k][2], each inside its own
  * view's object; data: [views][k][n][n].  opts as for ptyg_cg_solve, with

@@ -9,6 +9,7 @@
 #include <algorithm>
 #include <mutex>
 #include <string>
+#include <numeric>
 #include <vector>
 
 #include "../../include/ptyg.h"
@@ -1075,33 +1076,49 @@ ptyg_status ptyg_gd_solve(const ptyg_dims* dims, ptyg_c64* obj_c, ptyg_c64* prob
 
 namespace {
 // Multi-view batch: the views are stacked along the rows into one object of
-// views * obj_h rows; their patterns follow each other.
+// views * obj_h rows; their patterns follow each other.  Each view's patterns
+// are padded to kp, a multiple of the patterns per workgroup and of the
+// compaction chunk (kp = k when k already is one).  With padding, the stacked
+// object gets n zero rows below the last view and the padding patterns sit
+// there with zero intensities: their exit waves, objective terms and
+// gradients are exactly 0, and no view's vector operations reach those rows,
+// so they stay 0.  The object and the intensities are then copied into the
+// workspace in the padded layout (the object back at the end).
 struct ViewsLayout {
   ptyg_dims stacked;
   Layout L;  // of the stacked problem
-  size_t pos2, vparts, vout, vbeta, valpha, total;
+  int kp;    // patterns per view after padding
+  size_t pos2, vparts, vout, vbeta, valpha, objp, datap, total;
 };
 
 ptyg_status views_layout(const ptyg_dims* d, int32_t views, const ptyg_cg_opts* opts, ViewsLayout* out) {
   if (ptyg_status st = check_dims(d)) return st;
   if (views < 1) return fail(PTYG_E_INVAL, "views=%d must be >= 1", views);
   if (d->n > 128) return fail(PTYG_E_INVAL, "the multi-view batch supports n <= 128 (n=%d)", d->n);
-  const int ppw = patterns_per_block(d->n);
-  if (d->k % ppw) return fail(PTYG_E_INVAL, "k=%d per view must be a multiple of %d for n=%d", d->k, ppw, d->n);
-  const int64_t elems = (int64_t)d->k * d->n * d->n;
-  if (elems % kNzChunk)
-    return fail(PTYG_E_INVAL, "k*n*n=%lld per view must be a multiple of %d", (long long)elems, kNzChunk);
-  if ((int64_t)views * d->obj_h * d->obj_w >= (int64_t(1) << 31) || (int64_t)views * elems >= (int64_t(1) << 31))
+  const int nn = d->n * d->n;
+  const int unit = std::lcm(patterns_per_block(d->n), nn >= kNzChunk ? 1 : kNzChunk / nn);
+  const int64_t kp = ((int64_t)d->k + unit - 1) / unit * unit;
+  const bool pad = kp != d->k;
+  const int64_t rows = (int64_t)d->obj_h * views + (pad ? d->n : 0);
+  if (rows * d->obj_w >= (int64_t(1) << 31) || (int64_t)views * kp * nn >= (int64_t(1) << 31))
     return fail(PTYG_E_INVAL, "%d views of this size are too large", views);
   if (opts && opts->update_probe) return fail(PTYG_E_INVAL, "the multi-view batch is object-only");
   ViewsLayout V{};
+  V.kp = (int)kp;
   V.stacked = *d;
-  V.stacked.obj_h = d->obj_h * views;
-  V.stacked.k = d->k * views;
+  V.stacked.obj_h = (int)rows;
+  V.stacked.k = (int)kp * views;
   V.L = layout(&V.stacked, false, opts && opts->line_search == PTYG_LS_BATCHED, true);
   size_t o = V.L.total;
   V.pos2 = o;
   o = align_up(o + (size_t)V.stacked.k * sizeof(int2));
+  V.objp = V.datap = 0;
+  if (pad) {
+    V.objp = o;
+    o = align_up(o + (size_t)rows * d->obj_w * sizeof(float2));
+    V.datap = o;
+    o = align_up(o + (size_t)V.stacked.k * nn * sizeof(float));
+  }
   V.vparts = o;
   o = align_up(o + (size_t)views * kSegBlocks * kLsRow * sizeof(double));
   V.vout = o;
@@ -1154,12 +1171,39 @@ ptyg_status ptyg_cg_solve_views(const ptyg_dims* dims, int32_t views, ptyg_c64* 
     d1.k = dims->k * V;
     if (ptyg_status st = ptyg_check_positions(&d1, pos_i, ws, ws_bytes, stream)) return st;
   }
-  float2* obj = reinterpret_cast<float2*>(obj_c);
+  const int kp = VL.kp;  // patterns per view in the stacked problem
+  const bool pad = VL.objp != 0;
+  const int64_t on = (int64_t)dims->obj_h * dims->obj_w;  // per view
+  const int64_t pe = (int64_t)kp * dims->n * dims->n;    // pattern elements per view
+  // padded: the stacked object (views, then n zero rows) and the intensities
+  // (each view's k patterns, then zeros up to kp) in the workspace
+  float2* obj = pad ? at<float2>(ws, VL.objp) : reinterpret_cast<float2*>(obj_c);
+  const float* dat = pad ? at<float>(ws, VL.datap) : data;
+  // every return from here on leaves the iterates in obj_c with no copy in flight
+  struct ViewsOut {
+    hipStream_t s;
+    ptyg_c64* dst;
+    const float2* src;
+    size_t bytes;
+    ~ViewsOut() {
+      if (src) (void)hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, s);
+      (void)hipStreamSynchronize(s);
+    }
+  } out{s, obj_c, nullptr, 0};
+  if (pad) {
+    const size_t pb = (size_t)dims->k * dims->n * dims->n * sizeof(float);
+    PTYG_HIP(hipMemcpyAsync(obj, obj_c, (size_t)V * on * sizeof(float2), hipMemcpyDeviceToDevice, s));
+    out.src = obj;
+    out.bytes = (size_t)V * on * sizeof(float2);
+    PTYG_HIP(launch_zero(obj + V * on, (int64_t)dims->n * dims->obj_w, s));
+    PTYG_HIP(launch_fill_i32(reinterpret_cast<int*>(at<float>(ws, VL.datap)), (int64_t)V * pe, 0, s));
+    PTYG_HIP(hipMemcpy2DAsync(at<float>(ws, VL.datap), (size_t)pe * sizeof(float), data, pb, pb, V,
+                              hipMemcpyDeviceToDevice, s));
+  }
   const float2* probe = reinterpret_cast<const float2*>(probe_c);
   int2* pos = at<int2>(ws, VL.pos2);
-  PTYG_HIP(launch_shift_views(reinterpret_cast<const int2*>(pos_i), dims->k, V, dims->obj_h, pos, s));
-  const int64_t on = (int64_t)dims->obj_h * dims->obj_w;  // per view
-  const int64_t pe = (int64_t)dims->k * dims->n * dims->n;  // pattern elements per view
+  PTYG_HIP(launch_shift_views(reinterpret_cast<const int2*>(pos_i), dims->k, kp, V, dims->obj_h, V * dims->obj_h,
+                              pos, s));
   float2* eta_o = at<float2>(ws, L.eta_obj);
   float2* grad_o = at<float2>(ws, L.grad_obj);
   float* dt = at<float>(ws, L.data_t);
@@ -1172,8 +1216,8 @@ ptyg_status ptyg_cg_solve_views(const ptyg_dims* dims, int32_t views, ptyg_c64* 
   float2* far_b = batched ? at<float2>(ws, L.far_b) : nullptr;
   // the transform kernels read the intensities as given; the compaction of
   // the batched search reads a per-pattern transposed copy
-  if (batched) PTYG_HIP(launch_transpose_data(data, dt, D->k, D->n, s));
-  PTYG_HIP(launch_zero(eta_o, on * V, s));
+  if (batched) PTYG_HIP(launch_transpose_data(dat, dt, D->k, D->n, s));
+  PTYG_HIP(launch_zero(eta_o, (int64_t)D->obj_h * D->obj_w, s));
   if (ptyg_status st = build_tiles(D, pos, ws, L, s)) return st;
   const int cpv = (int)(pe / kNzChunk);  // compaction chunks per view
   if (batched)
@@ -1182,7 +1226,7 @@ ptyg_status ptyg_cg_solve_views(const ptyg_dims* dims, int32_t views, ptyg_c64* 
 
   // per-view data constants: Eq. ML's F = Phi + sum over d > 0 of d - d log d
   std::vector<double> dconst(V, 0.0);
-  PTYG_HIP(launch_data_const(data, pe, V, at<double>(ws, VL.vparts), at<double>(ws, VL.vout), s));
+  PTYG_HIP(launch_data_const(dat, pe, V, at<double>(ws, VL.vparts), at<double>(ws, VL.vout), s));
   PTYG_HIP(hipMemcpyAsync(dconst.data(), at<double>(ws, VL.vout), V * sizeof(double), hipMemcpyDeviceToHost, s));
   PTYG_HIP(hipStreamSynchronize(s));
   // per-view state
@@ -1193,15 +1237,15 @@ ptyg_status ptyg_cg_solve_views(const ptyg_dims* dims, int32_t views, ptyg_c64* 
   // vout slots: 0 phi, 1 f, 2 n1, 3 n2, 4 n3, 5 eta2, 6 |a|^2, 8..11 direction sums
   for (int m = 0; m < opts->iters; ++m) {
     // GRAD over every view in one launch; objectives and sums per view
-    if (ptyg_status st = run_grad(D, obj, probe, pos, data, DataLayout::Rows, eps, est, grad_o, nullptr,
+    if (ptyg_status st = run_grad(D, obj, probe, pos, dat, DataLayout::Rows, eps, est, grad_o, nullptr,
                                   nullptr, ws, L, s, far_a, nullptr, nullptr, nullptr, nullptr, nullptr, nullptr,
                                   false))
       return st;
-    PTYG_HIP(launch_finalize_views(partials, D->n, D->k, dims->k, V, 2, vparts, s));
+    PTYG_HIP(launch_finalize_views(partials, D->n, D->k, kp, V, 2, vparts, s));
     PTYG_HIP(launch_dot2_views(grad_o, eta_o, on, V, vparts + 2 * V, s));
     PTYG_HIP(launch_finalize_seg(vparts + 2 * V, kSegBlocks, 2, V, vparts + (size_t)V * kSegBlocks * 2 + 2 * V,
                                  s));
-    if (batched) PTYG_HIP(launch_finalize_views(at<double>(ws, L.zparts), D->n, D->k, dims->k, V, 1, dalpha, s));
+    if (batched) PTYG_HIP(launch_finalize_views(at<double>(ws, L.zparts), D->n, D->k, kp, V, 1, dalpha, s));
     // gather [V][2] (phi, f), [V][2] (n1, n2), [V] |a|^2 to the host
     std::vector<double> pf(2 * V), nn(2 * V), aa(V, 0.0);
     PTYG_HIP(hipMemcpyAsync(pf.data(), vparts, 2 * V * sizeof(double), hipMemcpyDeviceToHost, s));
@@ -1251,7 +1295,7 @@ ptyg_status ptyg_cg_solve_views(const ptyg_dims* dims, int32_t views, ptyg_c64* 
         TimedLaunch tl_fwd(2, s);
         PTYG_HIP(launch_fwd_t(fa, false, s));
       }
-      PTYG_HIP(launch_finalize_views(fa.zs_part, D->n, D->k, dims->k, V, 4, vout + 2 * V, s));
+      PTYG_HIP(launch_finalize_views(fa.zs_part, D->n, D->k, kp, V, 4, vout + 2 * V, s));
       std::vector<double> zs4(4 * V);
       PTYG_HIP(hipMemcpyAsync(zs4.data(), vout + 2 * V, 4 * V * sizeof(double), hipMemcpyDeviceToHost, s));
       LsArgs la{};
@@ -1329,7 +1373,7 @@ ptyg_status ptyg_cg_solve_views(const ptyg_dims* dims, int32_t views, ptyg_c64* 
         a.probe = probe;
         a.gamma = (float)gamma;
         a.pos = pos;
-        a.data = data;
+        a.data = dat;
         a.eps = eps;
         a.est = est;
         a.partials = partials;
@@ -1338,7 +1382,7 @@ ptyg_status ptyg_cg_solve_views(const ptyg_dims* dims, int32_t views, ptyg_c64* 
           TimedLaunch tl(1, s);
           PTYG_HIP(launch_minfunc(a, DataLayout::Rows, nullptr, s));
         }
-        PTYG_HIP(launch_finalize_views(partials, D->n, D->k, dims->k, V, 2, vout + 8 * V, s));
+        PTYG_HIP(launch_finalize_views(partials, D->n, D->k, kp, V, 2, vout + 8 * V, s));
         std::vector<double> pt(2 * V);
         PTYG_HIP(hipMemcpyAsync(pt.data(), vout + 8 * V, 2 * V * sizeof(double), hipMemcpyDeviceToHost, s));
         PTYG_HIP(hipStreamSynchronize(s));
@@ -1374,6 +1418,10 @@ ptyg_status ptyg_cg_solve_views(const ptyg_dims* dims, int32_t views, ptyg_c64* 
     // the host vectors copied to the device above must outlive the copies
     PTYG_HIP(hipStreamSynchronize(s));
     if (iters_done) *iters_done = m + 1;
+  }
+  if (pad) {
+    PTYG_HIP(hipMemcpyAsync(obj_c, obj, out.bytes, hipMemcpyDeviceToDevice, s));
+    out.src = nullptr;
   }
   PTYG_HIP(hipStreamSynchronize(s));
   return PTYG_OK;

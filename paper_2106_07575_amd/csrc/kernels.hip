@@ -1566,11 +1566,15 @@ __global__ __launch_bounds__(256) void k_ls_finalize_views(const double* partial
   if (threadIdx.x == 0) out[(size_t)v * kLsRow + j] = red[0];
 }
 
-__global__ void k_shift_views(const int2* pos, int k, int views, int rows_per_view, int2* out) {
+// Stacked positions: view v's pattern j < k at its position shifted down by
+// v * rows_per_view; the slots j in [k, kp) that pad each view to kp
+// patterns at (pad_row, 0), on the zero rows below the last view.
+__global__ void k_shift_views(const int2* pos, int k, int kp, int views, int rows_per_view, int pad_row,
+                              int2* out) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= k * views) return;
-  const int2 p = pos[i];
-  out[i] = make_int2(p.x + (i / k) * rows_per_view, p.y);
+  if (i >= kp * views) return;
+  const int v = i / kp, j = i % kp;
+  out[i] = j < k ? make_int2(pos[v * k + j].x + v * rows_per_view, pos[v * k + j].y) : make_int2(pad_row, 0);
 }
 
 // In-order reduction of `count` rows of `width` (<= 4) doubles, one workgroup.
@@ -2075,10 +2079,11 @@ hipError_t launch_ls_finalize_views(const double* partials, int views, double* o
   return hipGetLastError();
 }
 
-hipError_t launch_shift_views(const int2* pos, int k, int views, int rows_per_view, int2* out, hipStream_t s) {
-  if (!pos || !out || k < 1 || views < 1) return hipErrorInvalidValue;
-  hipLaunchKernelGGL(k_shift_views, dim3((k * views + 255) / 256), dim3(256), 0, s, pos, k, views, rows_per_view,
-                     out);
+hipError_t launch_shift_views(const int2* pos, int k, int kp, int views, int rows_per_view, int pad_row, int2* out,
+                              hipStream_t s) {
+  if (!pos || !out || k < 1 || kp < k || views < 1) return hipErrorInvalidValue;
+  hipLaunchKernelGGL(k_shift_views, dim3((kp * views + 255) / 256), dim3(256), 0, s, pos, k, kp, views, rows_per_view,
+                     pad_row, out);
   return hipGetLastError();
 }
 

@@ -239,7 +239,8 @@ hipError_t launch_finalize_seg(const double* partials, int rows, int width, int 
 // partial rows [v][kSegBlocks][kLsRow].
 hipError_t launch_ls_batch_views(const LsArgs& a, const int* offsets, int chunks_per_view, int views,
                                  hipStream_t s);
-hipError_t launch_shift_views(const int2* pos, int k, int views, int rows_per_view, int2* out, hipStream_t s);
+hipError_t launch_shift_views(const int2* pos, int k, int kp, int views, int rows_per_view, int pad_row, int2* out,
+                              hipStream_t s);
 // out[v][j] = ordered sum of rows [v][0..kSegBlocks) column j, j < kLsRow.
 hipError_t launch_ls_finalize_views(const double* partials, int views, double* out, hipStream_t s);
 // out[j] = in-order sum over `count` rows of partials[row][j], j < kLsRow.
