@@ -137,3 +137,27 @@ def test_host_limits_without_gpu():
     assert b"2^31" in lib.ptyg_last_error()
     fits = ptyg.Dims(8192, 8192, 256, 32767)
     assert lib.ptyg_workspace_size(ctypes.byref(fits), ctypes.byref(opts)) > 0
+
+
+def test_views_workspace_pads_ragged_pattern_counts():
+    """The multi-view batch sizes any pattern count (host-only size queries):
+    a count that does not fill the 8 patterns per workgroup at n = 32 gets
+    the padded stacked problem plus the staged object and intensities, so it
+    needs more workspace than the next full multiple, which needs none of
+    that; n = 256 and a joint solve are still refused."""
+    from paper_2106_07575_amd import ptyg
+    if not os.path.exists(ptyg.lib_path()):
+        pytest.skip("libptyg.so not built")
+    lib = ptyg.load()
+    opts = ptyg.CgOpts(1, 0, 1.0, 0.5, 0.0, 40, 1e-32, -1.0, 1, 0, -1)
+    size = lambda k, n=32, views=3: lib.ptyg_views_workspace_size(ctypes.byref(ptyg.Dims(120, 120, n, k)), views,
+                                                                  ctypes.byref(opts))
+    full, ragged = size(64), size(63)
+    assert full > 0 and ragged > full
+    # the staged copies: 3 views + 32 zero rows of 120 complex64, 3 x 64 patterns of 32^2 float32
+    assert ragged - full >= (3 * 120 + 32) * 120 * 8 + 3 * 64 * 32 * 32 * 4
+    assert size(57) == ragged  # padded to the same 64 patterns per view
+    assert lib.ptyg_views_workspace_size(ctypes.byref(ptyg.Dims(300, 300, 256, 4)), 3, ctypes.byref(opts)) == 0
+    assert b"n <= 128" in lib.ptyg_last_error()
+    joint = ptyg.CgOpts(1, 1, 1.0, 0.5, 0.0, 40, 1e-32, -1.0, 1, 0, -1)
+    assert lib.ptyg_views_workspace_size(ctypes.byref(ptyg.Dims(120, 120, 32, 64)), 3, ctypes.byref(joint)) == 0
